@@ -1,0 +1,161 @@
+"""Seeded synthetic workloads for the finite-difference wave step.
+
+This module only *generates inputs*: velocity models, anisotropy fields,
+source signatures and acquisition geometry.  It contains none of the
+scheme's arithmetic, and both the GPU path and the CPU oracle take their
+inputs from here.
+
+The paper evaluates on the Devito example models, which are not available
+offline; the generators below stand in for them with the paper's shapes and
+setup where it gives them (space order 8, a 40-point absorbing layer, a
+Ricker source, hundreds of steps; problem-setup section).  Randomness uses
+``numpy.random.default_rng(seed)`` in float64, rounded to float32 at the end.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Stability numbers S = -w_0 + 2 sum_k |w_k| of the centred second-derivative
+# stencil of each space order (the largest magnitude of its Fourier symbol).
+# Leapfrog is stable for v dt / h <= 2 / sqrt(ndim * S).  Used only to choose
+# a time step for the synthetic workloads ("dt at 0.5 CFL").
+_STAB = {2: 4.0, 4: 16.0 / 3.0, 8: 6.501587301587301, 12: 7.072943722943723,
+         16: 7.426938775510204}
+
+
+def courant_limit(so: int, ndim: int) -> float:
+    return 2.0 / math.sqrt(ndim * _STAB[so])
+
+
+def stable_dt(so: int, ndim: int, h: float, vmax: float, frac: float = 0.5) -> float:
+    return frac * courant_limit(so, ndim) * h / vmax
+
+
+def ricker(nt: int, dt: float, f0: float, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet sampled at t_n = n dt, peak amplitude 1, delay t0 = 1/f0."""
+    t0 = 1.0 / f0 if t0 is None else t0
+    t = np.arange(nt) * dt - t0
+    a = (math.pi * f0 * t) ** 2
+    return ((1.0 - 2.0 * a) * np.exp(-a)).astype(np.float32)
+
+
+def smooth_noise(shape, sigma: float, rng) -> np.ndarray:
+    """N(0,1) noise smoothed by a periodic Gaussian filter of std `sigma` cells
+    (applied in Fourier space), float64."""
+    x = rng.standard_normal(shape)
+    X = np.fft.rfftn(x)
+    k2 = 0.0
+    for ax, n in enumerate(shape):
+        if ax == len(shape) - 1:
+            k = np.fft.rfftfreq(n)
+        else:
+            k = np.fft.fftfreq(n)
+        sh = [1] * len(shape)
+        sh[ax] = -1
+        k2 = k2 + (k.reshape(sh) * 2 * math.pi) ** 2
+    X *= np.exp(-0.5 * sigma * sigma * k2)
+    return np.fft.irfftn(X, s=shape, axes=list(range(len(shape))))
+
+
+def minmax(a: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    a = (a - a.min()) / (a.max() - a.min())
+    return lo + (hi - lo) * a
+
+
+def layered_profile(nz: int, seed: int, vmin=1500.0, vmax=4500.0, min_thick=4) -> np.ndarray:
+    """1-D velocity profile v(z) of 8-12 flat layers, velocities increasing
+    with depth.  Returns float32 [nz]."""
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(8, 13))
+    vel = np.sort(rng.uniform(vmin, vmax, L))
+    while True:
+        cuts = np.sort(rng.choice(np.arange(min_thick, nz - min_thick), L - 1, replace=False))
+        th = np.diff(np.concatenate([[0], cuts, [nz]]))
+        if th.min() >= min_thick:
+            break
+    prof = np.empty(nz)
+    edges = np.concatenate([[0], cuts, [nz]])
+    for i in range(L):
+        prof[edges[i]:edges[i + 1]] = vel[i]
+    return prof.astype(np.float32)
+
+
+def smooth_state(shape, seed: int, sigma: float = 4.0) -> np.ndarray:
+    """A smooth random wavefield (unit std) for one-step parity checks."""
+    rng = np.random.default_rng(seed)
+    a = smooth_noise(tuple(shape), sigma, rng)
+    return (a / a.std()).astype(np.float32)
+
+
+@dataclass
+class Acoustic:
+    """One acoustic workload: DOMAIN shape (z,[y,]x), spacing, space order,
+    sponge width, time step, steps, velocity, sources, receivers."""
+    name: str
+    shape: tuple
+    spacing: tuple
+    so: int
+    nbl: int
+    dt: float
+    nt: int
+    vmax: float
+    boundary: int                       # 0 zero halo, 1 loopback (periodic)
+    src: np.ndarray                     # [ns][ndim] metres from DOMAIN index 0
+    rec: np.ndarray                     # [nr][ndim]
+    q: np.ndarray                       # [nt][ns] float32
+    vel_profile: np.ndarray | None = None   # [nz] when the model is flat in x, y
+    vel: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    def velocity(self) -> np.ndarray:
+        """DOMAIN-shaped float32 velocity (materialised on demand)."""
+        if self.vel is not None:
+            return self.vel
+        p = self.vel_profile.reshape((-1,) + (1,) * (self.ndim - 1))
+        return np.ascontiguousarray(np.broadcast_to(p, self.shape)).astype(np.float32)
+
+    @property
+    def points(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def cfg_2d(nt: int = 200) -> Acoustic:
+    """2-D homogeneous acoustic: 128 x 128 physical grid + 20-point sponge per
+    side (DOMAIN 168 x 168), h = 10 m, v = 1500 m/s, so 4, dt at 0.5 CFL,
+    10 Hz Ricker at the centre, 128 receivers 20 m below the top of the
+    physical region."""
+    n, nbl, h, v, so = 168, 20, 10.0, 1500.0, 4
+    dt = stable_dt(so, 2, h, v)
+    c = (n - 1) / 2.0 * h
+    src = np.array([[c, c]])
+    rec = np.array([[(nbl + 2) * h, (nbl + i) * h] for i in range(128)])
+    q = ricker(nt, dt, 10.0)[:, None]
+    return Acoustic("acoustic2d_168sq_so4", (n, n), (h, h), so, nbl, dt, nt, v, 0,
+                    src, rec, q, vel=np.full((n, n), v, dtype=np.float32))
+
+
+def cfg_3d_layered(n: int = 512, nt: int = 500, seed: int = 2, so: int = 8, nbl: int = 40,
+                   nrec: int | None = None) -> Acoustic:
+    """3-D layered acoustic on an n^3 DOMAIN (headline: n = 512, so 8, 500 steps):
+    seeded 8-12 flat layers, 1.5-4.5 km/s increasing with depth, 40-point
+    sponge, 15 Hz Ricker, h = 10 m, dt at 0.5 CFL, a line of receivers, and
+    loopback halo exchange of all six faces every step."""
+    h = 10.0
+    prof = layered_profile(n, seed)
+    vmax = 4500.0
+    dt = stable_dt(so, 3, h, vmax)
+    s = n / 512.0
+    src = np.array([[(50.5 * s) * h, (n / 2 - 0.5) * h, (n / 2 - 0.5) * h]])
+    nr = n if nrec is None else nrec
+    rz = round(45 * s)
+    rec = np.array([[rz * h, (n / 2 - 0.5) * h, (i * (n - 1) / max(nr - 1, 1)) * h]
+                    for i in range(nr)])
+    q = ricker(nt, dt, 15.0)[:, None]
+    return Acoustic("acoustic3d_%dcube_so%d_layered" % (n, so), (n, n, n), (h, h, h), so, nbl,
+                    dt, nt, vmax, 1, src, rec, q, vel_profile=prof)

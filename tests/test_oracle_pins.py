@@ -1,0 +1,471 @@
+"""Pins of the FP64 oracle against facts fixed independently of its code.
+
+Each test checks the oracle against something other than itself: exact
+rational weights from an independent Taylor-matching solve, the worked
+example printed in the paper, exact discrete solutions, invariants of the
+scheme, and brute force on tiny inputs.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_13094_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# independent exact weights: solve the symmetric moment conditions in Q
+# --------------------------------------------------------------------------
+
+def _solve_exact(A, b):
+    n = len(A)
+    M = [row[:] + [b[i]] for i, row in enumerate(A)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c] / M[c][c]
+                M[r] = [a - f * bb for a, bb in zip(M[r], M[c])]
+    return [M[i][n] / M[i][i] for i in range(n)]
+
+
+def exact_d2(so):
+    """w_0..w_r with w_0 [k=0]^p + 2 sum_k w_k k^p = 2 [p == 2] for even p <= so."""
+    r = so // 2
+    A, b = [], []
+    for p in range(0, 2 * r + 1, 2):
+        A.append([Fraction(1 if p == 0 else 0)] + [Fraction(2 * k ** p) for k in range(1, r + 1)])
+        b.append(Fraction(2 if p == 2 else 0))
+    return _solve_exact(A, b)
+
+
+def exact_d1(so):
+    """a_1..a_r with 2 sum_k a_k k^p = [p == 1] for odd p < so."""
+    r = so // 2
+    A, b = [], []
+    for p in range(1, 2 * r, 2):
+        A.append([Fraction(2 * k ** p) for k in range(1, r + 1)])
+        b.append(Fraction(1 if p == 1 else 0))
+    return _solve_exact(A, b)
+
+
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_d2_weights_match_exact_taylor_solve(so):
+    w = O.d2_weights(so)
+    ex = exact_d2(so)
+    for a, e in zip(w, ex):
+        assert abs(a - float(e)) <= 1e-15 * max(1.0, abs(float(e)))
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 12])
+def test_d2_weights_order(so):
+    """Exact for polynomials up to degree so+1, not beyond (order is exactly so)."""
+    w = O.d2_weights(so)
+    r = so // 2
+    for p in range(0, so + 4):
+        m = (w[0] if p == 0 else 0.0) + sum(w[k] * (k ** p + (-k) ** p) for k in range(1, r + 1))
+        target = 2.0 if p == 2 else 0.0
+        if p <= so + 1:
+            assert abs(m - target) <= 1e-9 * max(1, r ** p)
+    p = so + 2
+    m = sum(w[k] * 2 * k ** p for k in range(1, r + 1))
+    assert abs(m) > 1e-3
+
+
+def test_d2_weights_so2_is_generated_code():
+    """The generated-code appendix updates with r3 = -2 u[x] and +u[x-1], +u[x+1]
+    scaled by 1/h^2: the so-2 weights are (-2, 1)."""
+    assert list(O.d2_weights(2)) == [-2.0, 1.0]
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
+def test_d1_weights_match_exact_taylor_solve(so):
+    a = O.d1_weights(so)
+    ex = exact_d1(so)
+    for x, e in zip(a, ex):
+        assert abs(x - float(e)) <= 1e-15 * max(1.0, abs(float(e)))
+
+
+# --------------------------------------------------------------------------
+# the worked example printed in the paper (diffusion, 4 x 4, 2 x 2 ranks)
+# --------------------------------------------------------------------------
+
+def _load_worked_example():
+    blocks, cur = {}, None
+    with open(os.path.join(GOLDEN, "heat_4x4_worked_example.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line[0].isalpha():
+                cur = tuple(line.split())
+                blocks[cur] = []
+            else:
+                blocks[cur].append([float(t) for t in line.split()])
+    return {k: np.array(v) for k, v in blocks.items()}
+
+
+def _assemble(blocks, stage):
+    top = np.hstack([blocks[(stage, "rank0")], blocks[(stage, "rank1")]])
+    bot = np.hstack([blocks[(stage, "rank2")], blocks[(stage, "rank3")]])
+    return np.vstack([top, bot])
+
+
+def _heat_grid(shape, bc):
+    dx = 2.0 / 3.0
+    dt = 0.25 * dx * dx / 0.5
+    return O.Grid(shape, (dx, dx), so=2, dt=dt, bc=bc)
+
+
+def test_worked_example_single_domain():
+    """time_M = 1 runs the inclusive range [0, 1]: two forward-Euler steps with a
+    zero halo reproduce the printed field exactly."""
+    ex = _load_worked_example()
+    g = _heat_grid((4, 4), bc=0)
+    u = g.zeros()
+    g.interior(u)[1:-1, 1:-1] = 1.0
+    assert np.array_equal(g.interior(u), _assemble(ex, "before"))
+    O.heat(g, u, 2)
+    np.testing.assert_array_equal(g.interior(u), _assemble(ex, "after"))
+
+
+def test_worked_example_four_subdomains():
+    """The same run on a 2 x 2 decomposition, halos exchanged face by face with
+    the oracle's pack/unpack, reproduces every printed rank-local array."""
+    ex = _load_worked_example()
+    gs = _heat_grid((2, 2), bc=2)
+    ranks = {}
+    for rk in range(4):
+        u = gs.zeros()
+        gs.interior(u)[...] = ex[("before", "rank%d" % rk)]
+        ranks[rk] = u
+    coords = {0: (0, 0), 1: (0, 1), 2: (1, 0), 3: (1, 1)}
+    where = {v: k for k, v in coords.items()}
+    for _ in range(2):
+        for rk, (i, j) in coords.items():
+            u = ranks[rk]
+            # zero everything outside DOMAIN, then receive from neighbours
+            inner = gs.interior(u).copy()
+            u[...] = 0.0
+            gs.interior(u)[...] = inner
+        bufs = {rk: [O.pack_face(gs, ranks[rk], f) for f in range(6)] for rk in ranks}
+        for rk, (i, j) in coords.items():
+            # faces: 0/1 = -/+ axis 0, 4/5 = -/+ axis 1 (a 2-D grid has no y faces)
+            for f, (di, dj) in {0: (-1, 0), 1: (1, 0), 4: (0, -1), 5: (0, 1)}.items():
+                nb = where.get((i + di, j + dj))
+                if nb is not None:
+                    O.unpack_face(gs, ranks[rk], f, bufs[nb][f ^ 1])
+        for rk in ranks:
+            O.heat(gs, ranks[rk], 1)
+    for rk in range(4):
+        np.testing.assert_array_equal(gs.interior(ranks[rk]), ex[("after", "rank%d" % rk)])
+
+
+# --------------------------------------------------------------------------
+# halo faces: periodic fill equals numpy wrap-around (brute force)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,so", [((7, 6, 9), 4), ((9, 11), 8), ((5, 8, 6), 2)])
+def test_periodic_halo_is_wraparound(shape, so):
+    g = O.Grid(shape, (1.0,) * len(shape), so=so, dt=1e-3, bc=1)
+    rng = np.random.default_rng(0)
+    dom = rng.standard_normal(shape)
+    u = g.pad(dom)
+    O.fill_halo(g, u)
+    r = g.r
+    idx = [np.arange(-r, n + r) % n for n in shape]
+    wrapped = dom[np.ix_(*idx)]
+    # faces only: points outside DOMAIN along exactly one axis
+    grids = np.meshgrid(*[np.arange(-r, n + r) for n in shape], indexing="ij")
+    outside = sum(((gg < 0) | (gg >= n)).astype(int) for gg, n in zip(grids, shape))
+    face = outside == 1
+    np.testing.assert_array_equal(u[face], wrapped[face])
+    np.testing.assert_array_equal(u[outside == 0], wrapped[outside == 0])
+
+
+def test_face_buffer_layout():
+    """Face buffers are the OWNED slab in field axis order, row-major."""
+    g = O.Grid((4, 5, 6), (1.0, 1.0, 1.0), so=4, dt=1e-3)
+    dom = np.arange(4 * 5 * 6, dtype=np.float64).reshape(4, 5, 6)
+    u = g.pad(dom)
+    r = 2
+    want = {0: dom[:r], 1: dom[-r:], 2: dom[:, :r], 3: dom[:, -r:], 4: dom[:, :, :r],
+            5: dom[:, :, -r:]}
+    for f in range(6):
+        np.testing.assert_array_equal(O.pack_face(g, u, f), want[f].ravel())
+
+
+# --------------------------------------------------------------------------
+# exact discrete plane wave (periodic, no damping, no source)
+# --------------------------------------------------------------------------
+
+def _symbol(ex, theta):
+    """Fourier symbol of the exact second-derivative weights: w_0 + 2 sum w_k cos k theta."""
+    return float(ex[0]) + 2 * sum(float(ex[k]) * math.cos(k * theta) for k in range(1, len(ex)))
+
+
+@pytest.mark.parametrize("shape,spacing,so,modes,nt", [
+    ((24, 20, 16), (10.0, 12.0, 8.0), 8, (2, 3, 1), 300),
+    ((32, 28), (5.0, 7.0), 4, (3, 5), 400),
+    ((18, 16, 20), (10.0, 10.0, 10.0), 12, (1, 2, 3), 200),
+])
+def test_plane_wave_is_exact(shape, spacing, so, modes, nt):
+    v = 1800.0
+    ndim = len(shape)
+    dt = synth.stable_dt(so, ndim, min(spacing), v, frac=0.8)
+    g = O.Grid(shape, spacing, so=so, dt=dt, bc=1)
+    ex = exact_d2(so)
+    ks = [2 * math.pi * m / (n * h) for m, n, h in zip(modes, shape, spacing)]
+    s2 = -(v * dt) ** 2 / 4 * sum(_symbol(ex, k * h) / h ** 2 for k, h in zip(ks, spacing))
+    omega = 2 * math.asin(math.sqrt(s2)) / dt
+    xs = np.meshgrid(*[np.arange(n) * h for n, h in zip(shape, spacing)], indexing="ij")
+    phase = sum(k * x for k, x in zip(ks, xs))
+    u0 = g.pad(np.cos(phase))
+    um = g.pad(np.cos(phase + omega * dt))
+    u, uo, _, _ = O.forward(g, np.full(shape, v), nt=nt, u0=u0, um=um)
+    want = np.cos(phase - omega * nt * dt)
+    err = np.abs(g.interior(u) - want).max()
+    assert err < 1e-11, err
+    err1 = np.abs(g.interior(uo) - np.cos(phase - omega * (nt - 1) * dt)).max()
+    assert err1 < 1e-11
+
+
+# --------------------------------------------------------------------------
+# energy: conserved without damping, non-increasing with it
+# --------------------------------------------------------------------------
+
+def _energy(g, v, u_new, u, dt):
+    m = 1.0 / v ** 2
+    kin = 0.5 * np.sum(m * ((g.interior(u_new) - g.interior(u)) / dt) ** 2)
+    ul = u.copy()
+    O.fill_halo(g, ul)
+    pot = -0.5 * np.sum(g.interior(u_new) * O.laplacian(g, ul))
+    return kin + pot
+
+
+@pytest.mark.parametrize("shape,so", [((40, 36), 8), ((20, 18, 22), 4)])
+def test_energy_conserved_without_damping(shape, so):
+    rng = np.random.default_rng(1)
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, 4000.0)
+    dt = synth.stable_dt(so, len(shape), 10.0, 4000.0)
+    g = O.Grid(shape, (10.0,) * len(shape), so=so, dt=dt, bc=0)
+    u0 = g.pad(synth.smooth_state(shape, 2, 2.0).astype(np.float64) *
+               np.pad(np.ones(tuple(s - 8 for s in shape)), 4))
+    u, um = u0, u0.copy()
+    es = []
+    for _ in range(60):
+        un, uo, _, _ = O.forward(g, v, nt=1, u0=u, um=um)
+        es.append(_energy(g, v, un, uo, dt))
+        u, um = un, uo
+    es = np.array(es)
+    assert np.abs(es - es[0]).max() <= 1e-12 * abs(es[0])
+
+
+def test_energy_decays_with_damping():
+    shape, so = (60, 60), 4
+    v = np.full(shape, 2000.0)
+    dt = synth.stable_dt(so, 2, 10.0, 2000.0)
+    g = O.Grid(shape, (10.0, 10.0), so=so, dt=dt, nbl=15, vmax=2000.0, bc=0)
+    u0 = g.pad(synth.smooth_state(shape, 3, 2.0).astype(np.float64))
+    u, um = u0, u0.copy()
+    es = []
+    for _ in range(200):
+        un, uo, _, _ = O.forward(g, v, nt=1, u0=u, um=um)
+        es.append(_energy(g, v, un, uo, dt))
+        u, um = un, uo
+    es = np.array(es)
+    assert np.all(np.diff(es) <= 1e-12 * es[0])
+    assert es[-1] < 0.05 * es[0]
+
+
+def test_sponge_profile_shape():
+    """Zero inside, quadratic ramp, symmetric, summed over axes."""
+    g = O.Grid((30, 26), (10.0, 5.0), so=4, dt=1e-3, nbl=6, vmax=3000.0)
+    gam = O.sponge_gamma(g)
+    assert np.all(gam[6:-6, 6:-6] == 0.0)
+    np.testing.assert_allclose(gam, gam[::-1, ::-1], rtol=0, atol=1e-12)
+    row = gam[15, :]
+    ramp = row[:7][::-1]            # depth 0..6 into the layer
+    xi = np.arange(7) / 6.0
+    np.testing.assert_allclose(ramp, ramp[-1] * xi ** 2, rtol=1e-13)
+    # finer spacing along x -> proportionally stronger ramp (per-length damping)
+    assert abs(gam[0, 15] * 10.0 - gam[15, 0] * 5.0) < 1e-9 * gam[0, 15]
+    np.testing.assert_allclose(gam[0, 0], gam[0, 15] + gam[15, 0], rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# sparse interpolation: exact on affine fields, adjoint pair
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_interpolation_exact_on_affine_fields(ndim):
+    shape = (9, 7, 8)[:ndim] if ndim == 3 else (9, 8)
+    h = (10.0, 7.0, 5.0)[:ndim] if ndim == 3 else (10.0, 5.0)
+    g = O.Grid(shape, h, so=4, dt=1e-3)
+    rng = np.random.default_rng(5)
+    coef = rng.standard_normal(ndim + 1)
+    xs = np.meshgrid(*[np.arange(n) * hh for n, hh in zip(shape, h)], indexing="ij")
+    field = coef[0] + sum(c * x for c, x in zip(coef[1:], xs))
+    u = g.pad(field).ravel()
+    pts = np.stack([rng.uniform(0, (n - 1) * hh, 50) for n, hh in zip(shape, h)], 1)
+    pts[0] = [(n - 1) * hh for n, hh in zip(shape, h)]   # upper corner, clamped base
+    pts[1] = 0.0
+    node, wt = O.sparse_weights(g, pts)
+    got = (wt * u[node]).sum(1)
+    want = coef[0] + pts @ coef[1:]
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(wt.sum(1), 1.0, rtol=1e-14)
+
+
+def test_sparse_point_outside_rejected():
+    g = O.Grid((9, 8), (10.0, 5.0), so=4, dt=1e-3)
+    with pytest.raises(ValueError):
+        O.sparse_weights(g, np.array([[80.1, 10.0]]))
+    with pytest.raises(ValueError):
+        O.sparse_weights(g, np.array([[10.0, -0.01]]))
+
+
+# --------------------------------------------------------------------------
+# adjoint: dot-product test
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,so,nbl,bc", [((40, 44), 4, 8, 0), ((18, 20, 16), 8, 4, 0),
+                                           ((24, 22), 12, 5, 1)])
+def test_dot_product(shape, so, nbl, bc):
+    rng = np.random.default_rng(7)
+    ndim = len(shape)
+    h = 10.0
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, 3500.0)
+    dt = synth.stable_dt(so, ndim, h, 3500.0)
+    g = O.Grid(shape, (h,) * ndim, so=so, dt=dt, nbl=nbl, vmax=3500.0, bc=bc)
+    nt = 40
+    src = np.stack([rng.uniform(0, (n - 1) * h, 3) for n in shape], 1)
+    rec = np.stack([rng.uniform(0, (n - 1) * h, 30) for n in shape], 1)
+    q = rng.standard_normal((nt, 3))
+    r = rng.standard_normal((nt, 30))
+    _, _, d, _ = O.forward(g, v, src, q, rec, nt)
+    _, _, qa, _ = O.adjoint(g, v, rec, r, src, nt)
+    a, b = np.sum(d * r), np.sum(q * qa)
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+# --------------------------------------------------------------------------
+# gradient: central finite differences of J(m)
+# --------------------------------------------------------------------------
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(11)
+    shape, so, h = (30, 32), 4, 10.0
+    v0 = synth.minmax(synth.smooth_noise(shape, 4.0, rng), 1800.0, 2600.0)
+    vt = v0 * (1 + 0.05 * np.exp(-((np.arange(30)[:, None] - 16) ** 2 +
+                                   (np.arange(32)[None, :] - 15) ** 2) / 20.0))
+    dt = synth.stable_dt(so, 2, h, 2800.0)
+    g = O.Grid(shape, (h, h), so=so, dt=dt, nbl=6, vmax=2800.0, bc=0)
+    nt = 120
+    src = np.array([[60.0, 155.0]])
+    rec = np.array([[70.0, x * h] for x in range(2, 30)])
+    q = synth.ricker(nt, dt, 25.0).astype(np.float64)[:, None]
+    _, _, dobs, _ = O.forward(g, vt, src, q, rec, nt)
+
+    def J(v):
+        _, _, d, _ = O.forward(g, v, src, q, rec, nt)
+        return 0.5 * np.sum((d - dobs) ** 2)
+
+    _, _, d, hist = O.forward(g, v0, src, q, rec, nt, history=True)
+    _, _, _, gm = O.adjoint(g, v0, rec, d - dobs, src, nt, hist=hist)
+    gv = gm * (-2.0 / v0 ** 3)
+    dv = rng.standard_normal(shape) * 10.0
+    eps = 1e-3
+    fd = (J(v0 + eps * dv) - J(v0 - eps * dv)) / (2 * eps)
+    an = np.sum(gv * dv)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+# --------------------------------------------------------------------------
+# physics: analytic Green's function of the homogeneous 3-D wave equation
+# --------------------------------------------------------------------------
+
+def _greens_error(n, h, so, f0, dist_m, tmax):
+    v = 2000.0
+    dt = synth.stable_dt(so, 3, h, v, frac=0.5)
+    nt = int(tmax / dt)
+    g = O.Grid((n, n, n), (h, h, h), so=so, dt=dt, bc=0)
+    c = (n // 2) * h
+    src = np.array([[c, c, c]])
+    rec = np.array([[c, c, c + dist_m]])
+    q = synth.ricker(nt, dt, f0).astype(np.float64)
+    _, _, d, _ = O.forward(g, np.full((n, n, n), v), src, q[:, None], rec, nt)
+    # d[k] is u at t_{k+1}; analytic u(r, t) = q(t - r/v) / (4 pi r)
+    t = (np.arange(nt) + 1) * dt
+    t0 = 1.0 / f0
+    arg = np.pi * f0 * (t - dist_m / v - t0)
+    exact = (1 - 2 * arg ** 2) * np.exp(-arg ** 2) / (4 * np.pi * dist_m)
+    return np.linalg.norm(d[:, 0] - exact) / np.linalg.norm(exact)
+
+
+def test_greens_function_3d_and_convergence():
+    """Source scaling (h^-3 delta, v^2 dt^2) and dispersion: the trace 200 m
+    from a point source matches q(t - r/v)/(4 pi r) before any boundary
+    arrival (1040 m cube, zero halo), and the error drops about 4x (second
+    order in time) when h and dt are halved."""
+    e1 = _greens_error(52, 20.0, 8, 6.0, 200.0, 0.42)
+    e2 = _greens_error(104, 10.0, 8, 6.0, 200.0, 0.42)
+    assert e2 < 0.002, (e1, e2)
+    assert e1 / e2 > 3.0, (e1, e2)
+
+
+# --------------------------------------------------------------------------
+# multi-subdomain emulation: P subdomains exchanging faces == one domain
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,split,so", [((24, 20, 18), (2, 2, 1), 8), ((30, 27), (3, 2), 4)])
+def test_multidomain_emulation_bitwise(shape, split, so):
+    rng = np.random.default_rng(3)
+    ndim = len(shape)
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, 3000.0)
+    dt = synth.stable_dt(so, ndim, 10.0, 3000.0)
+    gfull = O.Grid(shape, (10.0,) * ndim, so=so, dt=dt, bc=0)
+    init = synth.smooth_state(shape, 4, 2.0).astype(np.float64)
+    nt = 12
+    u_ref, _, _, _ = O.forward(gfull, v, nt=nt, u0=gfull.pad(init), um=gfull.pad(0.5 * init))
+
+    cuts = [np.array_split(np.arange(n), p) for n, p in zip(shape, split)]
+    blocks = list(np.ndindex(*split))
+    sub = {}
+    for b in blocks:
+        sl = tuple(slice(c[i][0], c[i][-1] + 1) for c, i in zip(cuts, b))
+        gs = O.Grid(tuple(s.stop - s.start for s in sl), (10.0,) * ndim, so=so, dt=dt, bc=2)
+        sub[b] = dict(g=gs, sl=sl, v=np.ascontiguousarray(v[sl]),
+                      u=gs.pad(init[sl]), um=gs.pad(0.5 * init[sl]))
+    faces = [(a, s) for a in range(ndim) for s in (-1, 1)]
+
+    def face_id(a, s):
+        ax = a if ndim == 3 else (0 if a == 0 else 2)
+        return 2 * ax + (1 if s > 0 else 0)
+
+    for _ in range(nt):
+        bufs = {b: {face_id(a, s): O.pack_face(sub[b]["g"], sub[b]["u"], face_id(a, s))
+                    for a, s in faces} for b in blocks}
+        for b in blocks:
+            st = sub[b]
+            inner = st["g"].interior(st["u"]).copy()
+            st["u"][...] = 0.0
+            st["g"].interior(st["u"])[...] = inner
+            for a, s in faces:
+                nb = list(b)
+                nb[a] += s
+                if 0 <= nb[a] < split[a]:
+                    O.unpack_face(st["g"], st["u"], face_id(a, s), bufs[tuple(nb)][face_id(a, -s)])
+        for b in blocks:
+            st = sub[b]
+            st["u"], st["um"], _, _ = O.forward(st["g"], st["v"], nt=1, u0=st["u"], um=st["um"])
+    out = np.zeros(shape)
+    for b in blocks:
+        out[sub[b]["sl"]] = sub[b]["g"].interior(sub[b]["u"])
+    np.testing.assert_array_equal(out, gfull.interior(u_ref))
