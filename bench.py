@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Headline benchmark: 3-D space-order-8 acoustic forward modelling on one GPU.
+
+Workload: a 512^3 DOMAIN (plus a halo of 4), seeded layered velocity
+(8-12 flat layers, 1.5-4.5 km/s), 40-point damping layer, 15 Hz Ricker
+source, 512 receivers on a line, 500 time steps, and the six halo faces
+packed into device buffers and unpacked (loopback) every step.
+
+One bench "step" is one full fd_forward call: 500 time steps of the whole
+hot path (halo pack + unpack, stencil/leapfrog/damping, source injection,
+receiver interpolation).  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line with Gpts/s, the roofline of the dominant kernel (the
+stencil step, timed live with HIP events on its own stream) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpts/s & % HBM roofline, 3D so-8 acoustic; learned vs plain time at same err"
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
+STEP_BYTES_PER_POINT = 16             # read u, u-, v^2dt^2; write u+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "acoustic_step_512cube_so8_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_13094_amd", "csrc", "k_acoustic.hip")
+
+
+def _kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 PMC
+    summary, or None if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != _kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(c, budget_s):
+    """The FP64 oracle on the same 512^3 workload for as many of its steps
+    as fit in about `budget_s` seconds (at least one)."""
+    import numpy as np
+
+    import oracle as O
+    og = O.Grid(c.shape, c.spacing, so=c.so, dt=c.dt, nbl=c.nbl, vmax=c.vmax, bc=c.boundary)
+    v = c.velocity().astype(np.float64)
+    q = c.q.astype(np.float64)
+    t0 = time.perf_counter()
+    O.forward(og, v, c.src, q[:1], c.rec, 1)
+    t1 = time.perf_counter() - t0
+    nt = int(max(1, min(c.nt, round(budget_s / max(t1, 1e-3)))))
+    t0 = time.perf_counter()
+    O.forward(og, v, c.src, q[:nt], c.rec, nt)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(c.points * nt / dt / 1e9, 4), "unit": "Gpts/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "same %s workload, first %d of %d time steps, FP64 C oracle with OpenMP "
+                      "(%.1f s)" % ("x".join(map(str, c.shape)), nt, c.nt, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="cube side (headline 512)")
+    ap.add_argument("--nt", type=int, default=500, help="time steps per bench step (headline 500)")
+    ap.add_argument("--tile", type=str, default="", help="by,ry,nzb,xcd override")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2312_13094_amd import fd, synth
+
+    dev = torch.device("cuda", 0)
+    c = synth.cfg_3d_layered(n=args.n, nt=args.nt)
+    g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, boundary=c.boundary)
+    if args.tile:
+        g.set_tile(*[int(t) for t in args.tile.split(",")])
+    n = args.n
+    vel = torch.from_numpy(c.vel_profile).to(dev)[:, None, None].expand(n, n, n).contiguous()
+    g.set_model(vel)
+    del vel
+    states = [g.field(), g.field()]
+    S, R = g.sparse(c.src), g.sparse(c.rec)
+    q = torch.from_numpy(c.q).to(dev)
+    d = torch.zeros((c.nt, R.n), dtype=torch.float32, device=dev)
+
+    for _ in range(args.warmup):
+        g.forward(states, S, q, R, d, c.nt)
+    torch.cuda.synchronize()
+
+    g.profile_begin(args.steps * c.nt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.forward(states, S, q, R, d, c.nt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = g.profile_end()
+
+    if not torch.isfinite(d).all():
+        print("non-finite traces", file=sys.stderr)
+        sys.exit(1)
+
+    pts = c.points * c.nt * args.steps
+    gpts = pts / wall / 1e9
+    avg_ms = kern_ms / max(launches, 1)
+    bytes_launch = STEP_BYTES_PER_POINT * c.points
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic()
+    out = {
+        "metric": METRIC,
+        "value": round(gpts, 3),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": c.name + "_%dsteps_loopback_halo" % c.nt,
+                   "shape": list(c.shape), "space_order": c.so, "time_steps": c.nt,
+                   "sponge": c.nbl, "receivers": int(R.n), "sources": int(S.n),
+                   "halo_faces_per_step": 6, "tile": args.tile or "default"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_acoustic_zmarch (stencil + leapfrog + damping)",
+                     "avg_launch_ms": round(avg_ms, 5), "launches_timed": launches,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "cpu_baseline": None,
+    }
+    g.close()
+    del states, d
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

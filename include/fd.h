@@ -1,0 +1,207 @@
+/*
+ * fd.h -- C ABI of libfd, an MI355X (gfx950) explicit finite-difference
+ * wave-propagation library.
+ *
+ * One handle describes one rank's subdomain: a DOMAIN of (z, y, x) points
+ * with a read-only HALO of width r = space_order/2 around it (paper,
+ * "Access alignment" and "Data regions" paragraphs).  The library advances
+ * the second-order-in-time wave equation of the appendix "Isotropic
+ * acoustic" (equation (acou)), or the pseudo-acoustic TTI system of
+ * appendix "Anisotropic acoustic (TTI)", with a damping layer, sparse source
+ * injection and receiver interpolation, and the six-face halo pack/unpack of
+ * the "basic" exchange pattern (table "Summary of communication/computation
+ * patterns").
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an int status: FD_OK (0) or a negative FD_E*
+ *     code; none aborts or throws.  fd_last_error() gives a message for the
+ *     calling thread's last failure.
+ *   - Pointers suffixed _dev are device (HBM) pointers owned by the caller.
+ *     The library never frees caller memory, and fd_forward / fd_adjoint /
+ *     fd_pack_halo / fd_unpack_halo allocate nothing.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued asynchronously; execution errors surface at the caller's
+ *     stream synchronisation.  Argument errors are reported synchronously.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Axis order is (z, y, x) with x unit-stride.  A 2-D grid (ndim = 2)
+ *     lists its extents as (z, x) in shape[0], shape[1]; it has no y halo.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FD_OK = 0,
+    FD_EINVAL = -1,     /* bad argument (shape, order, pointer, sparse point outside) */
+    FD_ENOMEM = -2,     /* device allocation failed (handle creation / set_model only) */
+    FD_EDEVICE = -3,    /* HIP runtime / launch error */
+    FD_EUNSTABLE = -4,  /* time step violates the leapfrog stability limit */
+    FD_ENOTSUP = -5     /* valid request this build does not implement */
+};
+
+enum { FD_ACOUSTIC = 0, FD_TTI = 1 };
+
+/* How the halo of the propagated field is refreshed before every step:
+ *   FD_BC_ZERO      never written: stays as the caller allocated it (zero);
+ *   FD_BC_LOOPBACK  the rank is its own neighbour on a periodic topology:
+ *                   all faces are packed into device buffers and unpacked
+ *                   into the opposite face's halo every step;
+ *   FD_BC_EXTERNAL  left as the caller filled it (one step per call, with
+ *                   fd_pack_halo / fd_unpack_halo around it). */
+enum { FD_BC_ZERO = 0, FD_BC_LOOPBACK = 1, FD_BC_EXTERNAL = 2 };
+
+typedef struct fd_grid fd_grid;   /* opaque, library-owned */
+
+typedef struct {
+    int ndim;               /* 2 or 3 */
+    int64_t shape[3];       /* DOMAIN points, (z, y, x) or (z, x) */
+    double spacing[3];      /* metres, same order as shape */
+    int space_order;        /* even, 2..16 (TTI: 4..12) */
+    int nbl;                /* damping-layer width in points, inside DOMAIN; 0 = none */
+    int physics;            /* FD_ACOUSTIC or FD_TTI */
+    int boundary;           /* FD_BC_* */
+    double dt;              /* seconds */
+    double vmax;            /* upper bound of the velocity model (m/s); sets the
+                               damping strength and the stability check */
+    double eps_max;         /* TTI: upper bound of epsilon (stability check); else 0 */
+    int device;             /* HIP device ordinal */
+} fd_grid_desc;
+
+/* Field layout in HBM, identical for every padded field of a handle.
+ * Element (z, y, x) of DOMAIN lives at offset + z*pitch_z + y*pitch_y + x;
+ * halo points use z, y, x in [-halo, 0) and [n, n + halo).  DOMAIN rows start
+ * 128-byte aligned (x is padded on the left and right). */
+typedef struct {
+    int64_t padded[3];      /* allocated extent (z, y, x) in elements */
+    int64_t pitch_y;        /* elements between rows */
+    int64_t pitch_z;        /* elements between planes */
+    int64_t offset;         /* element offset of DOMAIN point (0, 0, 0) */
+    int halo;               /* r = space_order / 2 */
+    int64_t field_elems;    /* floats per padded field */
+    size_t field_bytes;
+} fd_layout;
+
+/* A set of sparse (off-grid) points prepared by fd_sparse_prepare and copied
+ * to the device by the caller: base[n][ndim] int32 lower node index and
+ * frac[n][ndim] fractional offset in [0, 1], axis order as `shape`. */
+typedef struct {
+    int n;
+    const int32_t *base_dev;
+    const float *frac_dev;
+} fd_sparse;
+
+/* Validate `desc`, compute the layout and FP32 stencil weights, and allocate
+ * the handle's own device memory (model coefficients and, for
+ * FD_BC_LOOPBACK, six face buffers).  Returns FD_EUNSTABLE if
+ * vmax*dt/h exceeds the leapfrog stability limit of the space order. */
+int fd_create_grid(const fd_grid_desc *desc, fd_grid **out);
+
+void fd_destroy_grid(fd_grid *g);
+
+int fd_field_layout(const fd_grid *g, fd_layout *out);
+
+/* Select the 3-D step kernel's tile: blocks of 64 x by threads, each thread
+ * computing ry consecutive rows (tile 64 x by*ry points), nzb planes per
+ * block, xcd != 0 remaps blocks so each XCD sweeps a contiguous tile range.
+ * by = 0 selects the one-thread-per-point kernel.  Supported (by, ry):
+ * (4,1) (4,2) (4,4) (4,8) (8,2) (8,4) (2,8).  Results do not depend on the
+ * tile (same arithmetic per point). */
+int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd);
+
+/* Multilinear weights of sparse points (paper, "Sparse data" paragraph:
+ * injection and interpolation at points off the grid).  coords_m is host
+ * [n][ndim] in metres from DOMAIN index 0.  base = floor(c/h) computed in
+ * FP64, clamped to shape-2; frac = c/h - base rounded to FP32.  Writes host
+ * arrays base_host[n][ndim], frac_host[n][ndim].  FD_EINVAL if any point lies
+ * outside [0, (shape-1) h]. */
+int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n,
+                      int32_t *base_host, float *frac_host);
+
+/* Load the model.  vel_dev is DOMAIN-shaped dense (nz, ny, nx) float32 in
+ * m/s.  For FD_TTI, tti_dev = {epsilon, delta, theta, phi} DOMAIN-shaped
+ * (theta: tilt from vertical, phi: azimuth, radians); NULL for acoustic.
+ * Builds the handle's v^2 dt^2 coefficient field on the device, then
+ * synchronises `stream` to check max(vel) <= vmax (FD_EUNSTABLE otherwise). */
+int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream);
+
+/* Forward modelling: nt leapfrog updates of equation (acou) (or the TTI
+ * system), each followed by source injection and receiver sampling.
+ *   state_dev  acoustic {u^n, u^(n-1)}, TTI {p^n, p^(n-1), r^n, r^(n-1)}:
+ *              padded fields, in/out; on return they hold the states nt
+ *              updates later in the same order.
+ *   src, q_dev ns sources and their signatures q[nt][ns]; update k uses q[k]
+ *              to produce the state at k+1.  src may be NULL (no source).
+ *   rec, d_dev nr receivers, traces d[nt][nr]: d[k] sampled after update k.
+ *              rec may be NULL.
+ *   ckpt_dev   NULL, or nstate * ceil(nt / ckpt_every) padded fields: before
+ *              update k with k % ckpt_every == 0 the state is copied into
+ *              ckpt_dev[(k / ckpt_every) * nstate + i] (nstate = 2 or 4).
+ * Allocates nothing; enqueues on `stream`. */
+int fd_forward(fd_grid *g, float *const *state_dev,
+               const fd_sparse *src, const float *q_dev,
+               const fd_sparse *rec, float *d_dev, int nt,
+               float *const *ckpt_dev, int ckpt_every, void *stream);
+
+/* Adjoint (exact transpose of fd_forward, acoustic): the same recurrence
+ * run backwards in time, receivers injecting the residual resid[nt][nr]
+ * (scaled by v^2 dt^2 / (1 + gamma dt/2), no cell-volume factor) and
+ * sources sampling qadj[nt][ns] = h^-d sum w lambda_n.
+ *   state_dev  {lambda_(n+1), lambda_(n+2)} padded work fields, zero on entry
+ *              for the terminal condition; on return lambda_0, lambda_1.
+ *   grad_m_dev NULL, or DOMAIN-shaped dense float32 accumulating (+=) the
+ *              zero-lag imaging condition
+ *                dJ/dm = - sum_n lambda_n [(1/dt^2 + gamma/2dt) u^(n+1)
+ *                          - (2/dt^2) u^n + (1/dt^2 - gamma/2dt) u^(n-1)];
+ *              then ckpt_dev / ckpt_every must be those of the forward run
+ *              (with src, q_dev of that run) and slot_dev must hold
+ *              ckpt_every + 2 padded work fields for the recomputation.
+ * Allocates nothing; enqueues on `stream`. */
+int fd_adjoint(fd_grid *g, float *const *state_dev,
+               const fd_sparse *rec, const float *resid_dev,
+               const fd_sparse *src, const float *q_dev, float *qadj_dev, int nt,
+               float *const *ckpt_dev, int ckpt_every, float *const *slot_dev,
+               float *grad_m_dev, void *stream);
+
+/* grad_v = grad_m * (-2 / v^3) for the loaded model (both DOMAIN-shaped). */
+int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *grad_v_dev,
+                            void *stream);
+
+/* Halo faces.  face 0..5 = -z, +z, -y, +y, -x, +x.  The buffer of face f is
+ * the r-deep slab of DOMAIN adjacent to that face over the full DOMAIN extent
+ * of the other axes, in field axis order, row-major; fd_halo_face_elems gives
+ * its length (0 for the y faces of a 2-D grid).  Returns < 0 on a bad face. */
+int64_t fd_halo_face_elems(const fd_grid *g, int face);
+
+/* Pack the OWNED slab of every face in face_mask (bit f = face f) of
+ * field_dev into buf_dev[f].  One kernel launch for all selected faces. */
+int fd_pack_halo(const fd_grid *g, const float *field_dev, unsigned face_mask,
+                 float *const *buf_dev, void *stream);
+
+/* Unpack buf_dev[f] (what the neighbour across face f sent: its packed face
+ * f^1) into the HALO slab beyond face f, for every face in face_mask. */
+int fd_unpack_halo(const fd_grid *g, float *field_dev, unsigned face_mask,
+                   const float *const *buf_dev, void *stream);
+
+/* Measurement hooks.  fd_profile_begin(g, n) arms HIP events around the
+ * next n launches of the step kernel made by fd_forward / fd_adjoint (on the
+ * stream they run on); fd_profile_end synchronises those events and returns
+ * the summed kernel time in milliseconds and the number of launches timed,
+ * then disarms.  Creates events (host-side objects), allocates no device
+ * memory. */
+int fd_profile_begin(fd_grid *g, int max_launches);
+int fd_profile_end(fd_grid *g, double *total_ms, int *launches);
+
+/* Thread-local description of the calling thread's last error ("" if none). */
+const char *fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H */

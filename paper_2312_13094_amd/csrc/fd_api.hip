@@ -1,0 +1,533 @@
+// Host side of libfd: validation, layout, the time loops of fd_forward and
+// fd_adjoint, halo entry points and error reporting.  Every kernel is in
+// k_*.hip; this file only launches them.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(FD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return FD_OK;
+}
+
+// Makes the handle's device current for the duration of a call.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev_ >= 0) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = -1;
+    bool ok_ = true;
+};
+
+// FP64 centred second-derivative weights of order 2r (unit spacing):
+// w_k = 2 (-1)^(k+1) (r!)^2 / (k^2 (r-k)! (r+k)!), w_0 = -2 sum 1/k^2.
+static void d2_weights(int r, double *w)
+{
+    auto lf = [](int k) { return std::lgamma((double)k + 1.0); };
+    w[0] = 0.0;
+    for (int k = 1; k <= r; ++k) {
+        const double mag = 2.0 * std::exp(2.0 * lf(r) - lf(r - k) - lf(r + k)) / ((double)k * k);
+        w[k] = (k % 2) ? mag : -mag;
+        w[0] -= 2.0 / ((double)k * k);
+    }
+}
+
+static void prof_release(fd_grid *g);
+
+static int64_t roundup(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+static void free_grid(fd_grid *g)
+{
+    if (!g) return;
+    prof_release(g);
+    (void)hipFree(g->vdt2);
+    for (float *&p : g->tti) (void)hipFree(p);
+    for (float *&p : g->facebuf) (void)hipFree(p);
+    (void)hipFree(g->scratch_u32);
+    delete g;
+}
+
+static double cell_volume(const fd_grid *g)
+{
+    double v = g->h[0] * g->h[2];
+    if (g->ndim == 3) v *= g->h[1];
+    return v;
+}
+
+static int validate_sparse(const fd_grid *g, const fd_sparse *sp, const void *vals,
+                           const char *what)
+{
+    if (!sp || sp->n == 0) return FD_OK;
+    if (sp->n < 0 || !sp->base_dev || !sp->frac_dev || !vals)
+        return set_error(FD_EINVAL, std::string(what) + ": null pointer or negative count");
+    (void)g;
+    return FD_OK;
+}
+
+// step kernel launch, bracketed by timing events while profiling is armed
+static int timed_step(fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+{
+    const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
+    if (t && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
+        return set_error(FD_EDEVICE, "hipEventRecord failed");
+    int rc = launch_step(g, u, um, up, s);
+    if (rc) return rc;
+    if (t) {
+        if (hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
+            return set_error(FD_EDEVICE, "hipEventRecord failed");
+        ++g->prof_used;
+    }
+    return FD_OK;
+}
+
+static void prof_release(fd_grid *g)
+{
+    for (hipEvent_t e : g->prof_ev) (void)hipEventDestroy(e);
+    g->prof_ev.clear();
+    g->prof_used = 0;
+}
+
+static int halo_exchange_loopback(fd_grid *g, float *field, hipStream_t s)
+{
+    int rc = launch_pack(g, field, 0x3fu, g->facebuf, s);
+    if (rc) return rc;
+    const float *recv[6];
+    for (int f = 0; f < 6; ++f) recv[f] = g->facebuf[f ^ 1];
+    return launch_unpack(g, field, 0x3fu, recv, s);
+}
+
+}  // namespace fd
+
+using namespace fd;
+
+extern "C" {
+
+const char *fd_last_error(void) { return g_err.c_str(); }
+
+int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
+{
+    if (!desc || !out) return set_error(FD_EINVAL, "fd_create_grid: null argument");
+    *out = nullptr;
+    const fd_grid_desc &d = *desc;
+    if (d.ndim != 2 && d.ndim != 3) return set_error(FD_EINVAL, "ndim must be 2 or 3");
+    if (d.space_order < 2 || d.space_order > 16 || d.space_order % 2)
+        return set_error(FD_EINVAL, "space_order must be even, 2..16");
+    if (d.physics != FD_ACOUSTIC)
+        return set_error(FD_ENOTSUP, "only FD_ACOUSTIC is implemented");
+    if (d.boundary < FD_BC_ZERO || d.boundary > FD_BC_EXTERNAL)
+        return set_error(FD_EINVAL, "unknown boundary mode");
+    if (!(d.dt > 0.0) || !(d.vmax > 0.0)) return set_error(FD_EINVAL, "dt and vmax must be > 0");
+    const int r = d.space_order / 2;
+
+    fd_grid *g = new fd_grid();
+    g->d = d;
+    g->ndim = d.ndim;
+    g->r = r;
+    if (d.ndim == 3) {
+        for (int a = 0; a < 3; ++a) {
+            g->n[a] = (int)d.shape[a];
+            g->h[a] = d.spacing[a];
+        }
+    } else {
+        g->n[0] = (int)d.shape[0];
+        g->n[1] = 1;
+        g->n[2] = (int)d.shape[1];
+        g->h[0] = d.spacing[0];
+        g->h[1] = 1.0;
+        g->h[2] = d.spacing[1];
+    }
+    for (int a = 0; a < d.ndim; ++a) {
+        if (d.shape[a] < 2 || d.shape[a] < r || d.shape[a] > (1 << 20) || !(d.spacing[a] > 0.0)) {
+            delete g;
+            return set_error(FD_EINVAL, "each extent must be >= max(2, space_order/2) and spacing > 0");
+        }
+        if (d.nbl < 0 || 2 * d.nbl > d.shape[a]) {
+            delete g;
+            return set_error(FD_EINVAL, "nbl must be in [0, extent/2]");
+        }
+    }
+
+    // stability: v dt sqrt(S sum 1/h^2) <= 2 with S the symbol bound of the stencil
+    double w[kMaxR + 1];
+    d2_weights(r, w);
+    double S = -w[0];
+    for (int k = 1; k <= r; ++k) S += 2.0 * std::fabs(w[k]);
+    double ih2 = 1.0 / (g->h[0] * g->h[0]) + 1.0 / (g->h[2] * g->h[2]);
+    if (d.ndim == 3) ih2 += 1.0 / (g->h[1] * g->h[1]);
+    if (d.vmax * d.dt * std::sqrt(S * ih2) > 2.0 * (1.0 + 1e-12)) {
+        delete g;
+        return set_error(FD_EUNSTABLE, "time step exceeds the leapfrog stability limit");
+    }
+
+    // layout
+    fd_layout &L = g->L;
+    L.halo = r;
+    L.pitch_y = roundup(kXOff + g->n[2] + r, 32);
+    const int64_t Y = d.ndim == 3 ? g->n[1] + 2 * r : 1;
+    const int64_t Z = g->n[0] + 2 * r;
+    L.pitch_z = Y * L.pitch_y;
+    L.padded[0] = Z;
+    L.padded[1] = Y;
+    L.padded[2] = L.pitch_y;
+    L.offset = r * L.pitch_z + (d.ndim == 3 ? r : 0) * L.pitch_y + kXOff;
+    L.field_elems = Z * L.pitch_z;
+    L.field_bytes = (size_t)L.field_elems * sizeof(float);
+
+    // step constants
+    StepParams &p = g->sp;
+    p.nz = g->n[0];
+    p.ny = g->n[1];
+    p.nx = g->n[2];
+    p.nbl = d.nbl;
+    p.pitch_y = L.pitch_y;
+    p.pitch_z = L.pitch_z;
+    p.offset = L.offset;
+    for (int k = 0; k <= kMaxR; ++k) {
+        const double wk = k <= r ? w[k] : 0.0;
+        p.cz[k] = (float)(wk / (g->h[0] * g->h[0]));
+        p.cx[k] = (float)(wk / (g->h[2] * g->h[2]));
+        p.cy[k] = d.ndim == 3 ? (float)(wk / (g->h[1] * g->h[1])) : 0.0f;
+    }
+    p.c0 = (float)(w[0] / (g->h[0] * g->h[0]) + w[0] / (g->h[2] * g->h[2]) +
+                   (d.ndim == 3 ? w[0] / (g->h[1] * g->h[1]) : 0.0));
+    const double lnR = std::log(1.0e3);
+    auto gmax = [&](double h) { return d.nbl > 0 ? 3.0 * d.vmax * lnR / (2.0 * d.nbl * h) : 0.0; };
+    p.gz = (float)gmax(g->h[0]);
+    p.gy = d.ndim == 3 ? (float)gmax(g->h[1]) : 0.0f;
+    p.gx = (float)gmax(g->h[2]);
+    p.inv_nbl = d.nbl > 0 ? 1.0f / (float)d.nbl : 0.0f;
+    p.half_dt = (float)(0.5 * d.dt);
+
+    g->tune = d.ndim == 3 ? Tuning{4, 4, 64, 1} : Tuning{0, 0, 0, 0};
+
+    DeviceGuard dg(d.device);
+    if (!dg.ok()) {
+        delete g;
+        return set_error(FD_EDEVICE, "cannot select device");
+    }
+    if (hipMalloc(&g->vdt2, L.field_bytes) != hipSuccess ||
+        hipMalloc(&g->scratch_u32, 256) != hipSuccess) {
+        free_grid(g);
+        return set_error(FD_ENOMEM, "device allocation failed");
+    }
+    if (hipMemset(g->vdt2, 0, L.field_bytes) != hipSuccess) {
+        free_grid(g);
+        return set_error(FD_EDEVICE, "hipMemset failed");
+    }
+    if (d.boundary == FD_BC_LOOPBACK) {
+        for (int f = 0; f < 6; ++f) {
+            const int64_t e = fd_halo_face_elems(g, f);
+            if (e > 0 && hipMalloc(&g->facebuf[f], e * sizeof(float)) != hipSuccess) {
+                free_grid(g);
+                return set_error(FD_ENOMEM, "face buffer allocation failed");
+            }
+        }
+    }
+    *out = g;
+    return FD_OK;
+}
+
+void fd_destroy_grid(fd_grid *g)
+{
+    if (!g) return;
+    DeviceGuard dg(g->d.device);
+    free_grid(g);
+}
+
+int fd_field_layout(const fd_grid *g, fd_layout *out)
+{
+    if (!g || !out) return set_error(FD_EINVAL, "fd_field_layout: null argument");
+    *out = g->L;
+    return FD_OK;
+}
+
+int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
+{
+    if (!g) return set_error(FD_EINVAL, "fd_set_tile: null handle");
+    if (by == 0) {   // simple kernel
+        g->tune = Tuning{0, 0, 0, 0};
+        return FD_OK;
+    }
+    if (g->ndim != 3) return set_error(FD_EINVAL, "tiles apply to 3-D grids");
+    const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
+                       (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
+    if (!known || nzb < 1) return set_error(FD_EINVAL, "unsupported tile shape");
+    g->tune = Tuning{by, ry, nzb, xcd ? 1 : 0};
+    return FD_OK;
+}
+
+int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n, int32_t *base_host,
+                      float *frac_host)
+{
+    if (!g || n < 0 || (n > 0 && (!coords_m || !base_host || !frac_host)))
+        return set_error(FD_EINVAL, "fd_sparse_prepare: bad argument");
+    const int nd = g->ndim;
+    for (int p = 0; p < n; ++p) {
+        for (int j = 0; j < nd; ++j) {
+            const int axis = nd == 3 ? j : (j == 0 ? 0 : 2);
+            const double s = coords_m[p * nd + j] / g->h[axis];
+            const int ext = g->n[axis];
+            if (!(s >= 0.0) || s > (double)(ext - 1))
+                return set_error(FD_EINVAL, "sparse point " + std::to_string(p) + " outside the grid");
+            int64_t b = (int64_t)std::floor(s);
+            if (b > ext - 2) b = ext - 2;
+            base_host[p * nd + j] = (int32_t)b;
+            frac_host[p * nd + j] = (float)(s - (double)b);
+        }
+    }
+    return FD_OK;
+}
+
+int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream)
+{
+    if (!g || !vel_dev) return set_error(FD_EINVAL, "fd_set_model: null argument");
+    (void)tti_dev;
+    DeviceGuard dg(g->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemsetAsync(g->scratch_u32, 0, sizeof(unsigned), s) != hipSuccess)
+        return set_error(FD_EDEVICE, "hipMemsetAsync failed");
+    int rc = launch_build_vdt2(g, vel_dev, g->vdt2, g->scratch_u32, s);
+    if (rc) return rc;
+    unsigned bits = 0;
+    if (hipMemcpyAsync(&bits, g->scratch_u32, sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(FD_EDEVICE, "model check copy failed");
+    float vmax;
+    std::memcpy(&vmax, &bits, sizeof(float));
+    if (!(vmax <= (float)g->d.vmax * (1.0f + 1e-6f))) {
+        g->model_loaded = false;
+        return set_error(FD_EUNSTABLE, "velocity model exceeds vmax or is not positive");
+    }
+    g->model_loaded = true;
+    return FD_OK;
+}
+
+int64_t fd_halo_face_elems(const fd_grid *g, int face)
+{
+    if (!g || face < 0 || face > 5) return FD_EINVAL;
+    const int axis = face / 2;
+    if (axis == 1 && g->ndim == 2) return 0;
+    int64_t e = 1;
+    for (int a = 0; a < 3; ++a) e *= (a == axis) ? g->r : g->n[a];
+    return e;
+}
+
+int fd_pack_halo(const fd_grid *g, const float *field_dev, unsigned face_mask,
+                 float *const *buf_dev, void *stream)
+{
+    if (!g || !field_dev || !buf_dev || face_mask > 0x3fu)
+        return set_error(FD_EINVAL, "fd_pack_halo: bad argument");
+    for (int f = 0; f < 6; ++f)
+        if ((face_mask >> f) & 1u && fd_halo_face_elems(g, f) > 0 && !buf_dev[f])
+            return set_error(FD_EINVAL, "fd_pack_halo: null buffer for a selected face");
+    DeviceGuard dg(g->d.device);
+    return launch_pack(g, field_dev, face_mask, buf_dev, (hipStream_t)stream);
+}
+
+int fd_unpack_halo(const fd_grid *g, float *field_dev, unsigned face_mask,
+                   const float *const *buf_dev, void *stream)
+{
+    if (!g || !field_dev || !buf_dev || face_mask > 0x3fu)
+        return set_error(FD_EINVAL, "fd_unpack_halo: bad argument");
+    for (int f = 0; f < 6; ++f)
+        if ((face_mask >> f) & 1u && fd_halo_face_elems(g, f) > 0 && !buf_dev[f])
+            return set_error(FD_EINVAL, "fd_unpack_halo: null buffer for a selected face");
+    DeviceGuard dg(g->d.device);
+    return launch_unpack(g, field_dev, face_mask, buf_dev, (hipStream_t)stream);
+}
+
+int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const float *q_dev,
+               const fd_sparse *rec, float *d_dev, int nt, float *const *ckpt_dev,
+               int ckpt_every, void *stream)
+{
+    if (!g || !state_dev || !state_dev[0] || !state_dev[1] || nt < 0)
+        return set_error(FD_EINVAL, "fd_forward: bad argument");
+    if (state_dev[0] == state_dev[1]) return set_error(FD_EINVAL, "fd_forward: states alias");
+    if (!g->model_loaded) return set_error(FD_EINVAL, "fd_forward: no model loaded");
+    if (ckpt_dev && ckpt_every < 1) return set_error(FD_EINVAL, "fd_forward: ckpt_every < 1");
+    int rc = validate_sparse(g, src, q_dev, "sources");
+    if (rc) return rc;
+    if ((rc = validate_sparse(g, rec, d_dev, "receivers"))) return rc;
+    if (g->d.boundary == FD_BC_EXTERNAL && nt > 1)
+        return set_error(FD_EINVAL, "FD_BC_EXTERNAL advances one step per call");
+    DeviceGuard dg(g->d.device);
+    hipStream_t s = (hipStream_t)stream;
+
+    SparseArgs inj{src ? src->n : 0, src ? src->base_dev : nullptr, src ? src->frac_dev : nullptr,
+                   nullptr, nullptr, (float)(1.0 / cell_volume(g))};
+    SparseArgs smp{rec ? rec->n : 0, rec ? rec->base_dev : nullptr, rec ? rec->frac_dev : nullptr,
+                   nullptr, nullptr, 1.0f};
+    float *cur = state_dev[0], *prev = state_dev[1];
+    for (int n = 0; n < nt; ++n) {
+        if (ckpt_dev && n % ckpt_every == 0) {
+            float *c0 = ckpt_dev[2 * (n / ckpt_every)], *c1 = ckpt_dev[2 * (n / ckpt_every) + 1];
+            if (!c0 || !c1) return set_error(FD_EINVAL, "fd_forward: null checkpoint buffer");
+            if (hipMemcpyAsync(c0, cur, g->L.field_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(c1, prev, g->L.field_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return set_error(FD_EDEVICE, "checkpoint copy failed");
+        }
+        if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, cur, s))) return rc;
+        if ((rc = timed_step(g, cur, prev, prev, s))) return rc;
+        inj.vals = inj.n ? q_dev + (int64_t)n * inj.n : nullptr;
+        smp.out = smp.n ? d_dev + (int64_t)n * smp.n : nullptr;
+        if ((rc = launch_sparse(g, prev, inj, smp, s))) return rc;
+        float *t = cur;
+        cur = prev;
+        prev = t;
+    }
+    if (nt % 2) return launch_swap(state_dev[0], state_dev[1], g->L.field_elems, s);
+    return FD_OK;
+}
+
+int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const float *resid_dev,
+               const fd_sparse *src, const float *q_dev, float *qadj_dev, int nt,
+               float *const *ckpt_dev, int ckpt_every, float *const *slot_dev, float *grad_m_dev,
+               void *stream)
+{
+    if (!g || !state_dev || !state_dev[0] || !state_dev[1] || nt < 0)
+        return set_error(FD_EINVAL, "fd_adjoint: bad argument");
+    if (state_dev[0] == state_dev[1]) return set_error(FD_EINVAL, "fd_adjoint: states alias");
+    if (!g->model_loaded) return set_error(FD_EINVAL, "fd_adjoint: no model loaded");
+    if (g->d.boundary == FD_BC_EXTERNAL)
+        return set_error(FD_ENOTSUP, "fd_adjoint: FD_BC_EXTERNAL is not supported");
+    int rc = validate_sparse(g, rec, resid_dev, "receivers");
+    if (rc) return rc;
+    const bool grad = grad_m_dev != nullptr;
+    if (grad) {
+        if (!ckpt_dev || ckpt_every < 1 || !slot_dev)
+            return set_error(FD_EINVAL, "fd_adjoint: the gradient needs checkpoints and slots");
+        if ((rc = validate_sparse(g, src, q_dev, "sources"))) return rc;
+        for (int i = 0; i < ckpt_every + 2; ++i)
+            if (!slot_dev[i]) return set_error(FD_EINVAL, "fd_adjoint: null slot");
+    }
+    if (src && src->n > 0 && qadj_dev == nullptr && !grad)
+        return set_error(FD_EINVAL, "fd_adjoint: sources given without qadj output");
+    DeviceGuard dg(g->d.device);
+    hipStream_t s = (hipStream_t)stream;
+
+    const float hinv = (float)(1.0 / cell_volume(g));
+    SparseArgs inj{rec ? rec->n : 0, rec ? rec->base_dev : nullptr, rec ? rec->frac_dev : nullptr,
+                   nullptr, nullptr, 1.0f};
+    SparseArgs smp{(src && qadj_dev) ? src->n : 0, src ? src->base_dev : nullptr,
+                   src ? src->frac_dev : nullptr, nullptr, nullptr, hinv};
+    SparseArgs fsrc{src ? src->n : 0, src ? src->base_dev : nullptr, src ? src->frac_dev : nullptr,
+                    nullptr, nullptr, hinv};
+    const SparseArgs none{0, nullptr, nullptr, nullptr, nullptr, 0.0f};
+
+    float *lam = state_dev[0], *lamo = state_dev[1];
+    const int k = grad ? ckpt_every : (nt > 0 ? nt : 1);
+    const int nseg = (nt + k - 1) / k;
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int lo = j * k, hi = std::min(nt, (j + 1) * k);
+        if (grad) {
+            // recompute u^(lo-1) .. u^hi into slots 0 .. hi-lo+1
+            float *c0 = ckpt_dev[2 * j], *c1 = ckpt_dev[2 * j + 1];
+            if (!c0 || !c1) return set_error(FD_EINVAL, "fd_adjoint: null checkpoint buffer");
+            if (hipMemcpyAsync(slot_dev[1], c0, g->L.field_bytes, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess ||
+                hipMemcpyAsync(slot_dev[0], c1, g->L.field_bytes, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                return set_error(FD_EDEVICE, "checkpoint restore failed");
+            for (int i = 0; i < hi - lo; ++i) {
+                float *cur = slot_dev[i + 1], *prv = slot_dev[i], *out = slot_dev[i + 2];
+                if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, cur, s)))
+                    return rc;
+                if ((rc = timed_step(g, cur, prv, out, s))) return rc;
+                fsrc.vals = fsrc.n ? q_dev + (int64_t)(lo + i) * fsrc.n : nullptr;
+                if ((rc = launch_sparse(g, out, fsrc, none, s))) return rc;
+            }
+        }
+        for (int n = hi - 1; n >= lo; --n) {
+            if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, lam, s))) return rc;
+            if ((rc = timed_step(g, lam, lamo, lamo, s))) return rc;
+            inj.vals = inj.n ? resid_dev + (int64_t)n * inj.n : nullptr;
+            smp.out = smp.n ? qadj_dev + (int64_t)n * smp.n : nullptr;
+            if ((rc = launch_sparse(g, lamo, inj, smp, s))) return rc;
+            float *t = lam;
+            lam = lamo;
+            lamo = t;
+            if (grad) {
+                const int i = n - lo;
+                if ((rc = launch_imaging(g, lam, slot_dev[i + 2], slot_dev[i + 1], slot_dev[i],
+                                         grad_m_dev, s)))
+                    return rc;
+            }
+        }
+    }
+    if (nt % 2) return launch_swap(state_dev[0], state_dev[1], g->L.field_elems, s);
+    return FD_OK;
+}
+
+int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *grad_v_dev,
+                            void *stream)
+{
+    if (!g || !grad_m_dev || !grad_v_dev) return set_error(FD_EINVAL, "bad argument");
+    if (!g->model_loaded) return set_error(FD_EINVAL, "no model loaded");
+    DeviceGuard dg(g->d.device);
+    return launch_grad_to_vel(g, grad_m_dev, grad_v_dev, (hipStream_t)stream);
+}
+
+int fd_profile_begin(fd_grid *g, int max_launches)
+{
+    if (!g || max_launches < 1 || max_launches > (1 << 20))
+        return set_error(FD_EINVAL, "fd_profile_begin: bad argument");
+    DeviceGuard dg(g->d.device);
+    prof_release(g);
+    g->prof_ev.resize(2 * (size_t)max_launches);
+    for (size_t i = 0; i < g->prof_ev.size(); ++i)
+        if (hipEventCreate(&g->prof_ev[i]) != hipSuccess) {
+            g->prof_ev.resize(i);
+            prof_release(g);
+            return set_error(FD_EDEVICE, "hipEventCreate failed");
+        }
+    return FD_OK;
+}
+
+int fd_profile_end(fd_grid *g, double *total_ms, int *launches)
+{
+    if (!g || !total_ms || !launches) return set_error(FD_EINVAL, "fd_profile_end: bad argument");
+    DeviceGuard dg(g->d.device);
+    double tot = 0.0;
+    for (int i = 0; i < g->prof_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(g->prof_ev[2 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, g->prof_ev[2 * i], g->prof_ev[2 * i + 1]) != hipSuccess) {
+            prof_release(g);
+            return set_error(FD_EDEVICE, "event timing failed");
+        }
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = g->prof_used;
+    prof_release(g);
+    return FD_OK;
+}
+
+}  // extern "C"

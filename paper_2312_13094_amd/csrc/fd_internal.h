@@ -1,0 +1,115 @@
+// Internal declarations shared by the libfd translation units (host side and
+// kernel launchers).  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fd.h"
+
+namespace fd {
+
+constexpr int kMaxR = 8;          // space order 16
+constexpr int kXOff = 32;         // DOMAIN x offset in a row: 128-byte aligned rows
+
+// Per-launch constants of one leapfrog step; passed by value (kernarg
+// segment, read through the scalar cache).
+struct StepParams {
+    int nz, ny, nx;               // DOMAIN extents (ny == 1 in 2-D)
+    int nbl;                      // damping layer width (0 = none)
+    int64_t pitch_y, pitch_z;     // elements
+    int64_t offset;               // element offset of DOMAIN (0,0,0)
+    float cz[kMaxR + 1];          // w_k / h_z^2, k = 0..r
+    float cy[kMaxR + 1];          // w_k / h_y^2 (zero in 2-D)
+    float cx[kMaxR + 1];          // w_k / h_x^2
+    float c0;                     // cz[0] + cy[0] + cx[0]
+    float gz, gy, gx;             // damping gamma_max per axis (1/s)
+    float inv_nbl;                // 1 / nbl
+    float half_dt;                // dt / 2
+};
+
+// Damping rate along one axis at DOMAIN index i: gamma_max * xi^2 with xi the
+// depth into the layer, 0 at the inner edge, 1 at the outermost point.
+__host__ __device__ inline float sponge1(int i, int n, int nbl, float inv_nbl, float gmax)
+{
+    float xi = 0.0f;
+    if (i < nbl) xi = (float)(nbl - i) * inv_nbl;
+    else if (i > n - 1 - nbl) xi = (float)(i - (n - 1 - nbl)) * inv_nbl;
+    return gmax * xi * xi;
+}
+
+// a = (dt/2) * gamma(z, y, x)
+__device__ inline float damp_a(const StepParams &p, int z, int y, int x)
+{
+    if (p.nbl <= 0) return 0.0f;
+    float g = sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) + sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx);
+    if (p.ny > 1) g += sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy);
+    return p.half_dt * g;
+}
+
+// Tile choice for the z-marching 3-D kernel.
+struct Tuning {
+    int by;        // waves per block (block = 64 x by threads)
+    int ry;        // rows per thread (tile height = by * ry)
+    int nzb;       // planes per block (z chunk)
+    int xcd;       // 1: XCD-aware block remap
+};
+
+// One set of sparse points bound to a step.
+struct SparseArgs {
+    int n;
+    const int32_t *base;   // [n][ndim]
+    const float *frac;     // [n][ndim]
+    const float *vals;     // injection: [n] values of this step; else NULL
+    float *out;            // sampling: [n] outputs of this step; else NULL
+    float scale;
+};
+
+}  // namespace fd
+
+struct fd_grid {
+    fd_grid_desc d;
+    int ndim;
+    int n[3];               // (nz, ny, nx); ny == 1 in 2-D
+    double h[3];            // (hz, hy, hx); hy unused in 2-D
+    int r;
+    fd_layout L;
+    fd::StepParams sp;
+    fd::Tuning tune;
+    float *vdt2 = nullptr;        // padded v^2 dt^2
+    float *tti[4] = {nullptr, nullptr, nullptr, nullptr};  // padded eps, delta, theta, phi
+    float *facebuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    unsigned *scratch_u32 = nullptr;  // small device scratch (model checks)
+    bool model_loaded = false;
+    std::vector<hipEvent_t> prof_ev;  // armed step-kernel timing events (pairs)
+    int prof_used = 0;
+};
+
+namespace fd {
+
+// error helpers (fd_api.hip)
+int set_error(int code, const std::string &msg);
+int check_launch(const char *what);
+
+// kernel launchers; each returns FD_OK or an error code
+int launch_step(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s);
+int launch_step_simple(const fd_grid *g, const float *u, const float *um, float *up,
+                       hipStream_t s);
+int launch_sparse(const fd_grid *g, float *u, const SparseArgs &inj, const SparseArgs &smp,
+                  hipStream_t s);
+int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *const *buf,
+                hipStream_t s);
+int launch_unpack(const fd_grid *g, float *field, unsigned mask, const float *const *buf,
+                  hipStream_t s);
+int launch_swap(float *a, float *b, int64_t n, hipStream_t s);
+int launch_build_vdt2(const fd_grid *g, const float *vel, float *vdt2, unsigned *vmax_bits,
+                      hipStream_t s);
+int launch_imaging(const fd_grid *g, const float *lam, const float *up, const float *u0,
+                   const float *um, float *grad, hipStream_t s);
+int launch_grad_to_vel(const fd_grid *g, const float *gm, float *gv, hipStream_t s);
+
+}  // namespace fd

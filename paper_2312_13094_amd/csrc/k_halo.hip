@@ -1,0 +1,112 @@
+// Halo face pack / unpack and state swap.
+//
+// The "basic" exchange pattern sends one message per face (table "Summary of
+// communication/computation patterns": 6 messages in 3-D).  pack copies the
+// r-deep OWNED slab next to each selected face into a contiguous device
+// buffer; unpack copies a received buffer into the HALO slab beyond a face.
+// All selected faces go in one launch (blockIdx.y = face).  Element k of a
+// face buffer is slab point (k / (c1 c2), (k / c2) % c1, k % c2) in field axis
+// order, so the z and y faces move whole 128-byte-aligned rows.
+#include "fd_internal.h"
+
+namespace fd {
+
+struct FaceJob {
+    float *buf[6];
+    int cnt[6][3];        // slab extent (z, y, x)
+    int start[6][3];      // DOMAIN coordinate of the slab origin
+    int elems[6];
+};
+
+template <bool UNPACK>
+__global__ __launch_bounds__(256) void k_faces(float *field, const FaceJob job,
+                                               const int64_t offset, const int64_t PY,
+                                               const int64_t PZ)
+{
+    const int f = blockIdx.y;
+    const int n = job.elems[f];
+    if (n == 0) return;
+    const int c1 = job.cnt[f][1], c2 = job.cnt[f][2];
+    const int sz = job.start[f][0], sy = job.start[f][1], sx = job.start[f][2];
+    float *buf = job.buf[f];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int i2 = e % c2;
+        const int t = e / c2;
+        const int i1 = t % c1;
+        const int i0 = t / c1;
+        const int64_t idx = offset + (int64_t)(sz + i0) * PZ + (int64_t)(sy + i1) * PY + (sx + i2);
+        if (UNPACK) field[idx] = buf[e];
+        else buf[e] = field[idx];
+    }
+}
+
+static void face_job(const fd_grid *g, unsigned mask, bool halo_side, FaceJob &job, int &maxe)
+{
+    maxe = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int axis = f / 2, plus = f & 1;
+        const bool active = (mask >> f) & 1u && !(axis == 1 && g->ndim == 2);
+        int cnt[3] = {g->n[0], g->n[1], g->n[2]}, st[3] = {0, 0, 0};
+        cnt[axis] = g->r;
+        if (!halo_side) st[axis] = plus ? g->n[axis] - g->r : 0;
+        else st[axis] = plus ? g->n[axis] : -g->r;
+        for (int a = 0; a < 3; ++a) {
+            job.cnt[f][a] = cnt[a];
+            job.start[f][a] = st[a];
+        }
+        job.elems[f] = active ? cnt[0] * cnt[1] * cnt[2] : 0;
+        if (job.elems[f] > maxe) maxe = job.elems[f];
+    }
+}
+
+int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *const *buf,
+                hipStream_t s)
+{
+    FaceJob job;
+    int maxe;
+    face_job(g, mask, false, job, maxe);
+    for (int f = 0; f < 6; ++f) job.buf[f] = job.elems[f] ? buf[f] : nullptr;
+    if (maxe == 0) return FD_OK;
+    const int nbx = std::min((maxe + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_faces<false>, dim3(nbx, 6), dim3(256), 0, s, const_cast<float *>(field),
+                       job, g->L.offset, g->L.pitch_y, g->L.pitch_z);
+    return check_launch("halo pack");
+}
+
+int launch_unpack(const fd_grid *g, float *field, unsigned mask, const float *const *buf,
+                  hipStream_t s)
+{
+    FaceJob job;
+    int maxe;
+    face_job(g, mask, true, job, maxe);
+    for (int f = 0; f < 6; ++f) job.buf[f] = job.elems[f] ? const_cast<float *>(buf[f]) : nullptr;
+    if (maxe == 0) return FD_OK;
+    const int nbx = std::min((maxe + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_faces<true>, dim3(nbx, 6), dim3(256), 0, s, field, job, g->L.offset,
+                       g->L.pitch_y, g->L.pitch_z);
+    return check_launch("halo unpack");
+}
+
+__global__ __launch_bounds__(256) void k_swap(float4 *a, float4 *b, int64_t n4)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 t = a[i];
+        a[i] = b[i];
+        b[i] = t;
+    }
+}
+
+// n must be a multiple of 4 and both pointers 16-byte aligned (padded fields are)
+int launch_swap(float *a, float *b, int64_t n, hipStream_t s)
+{
+    if (n % 4 || reinterpret_cast<uintptr_t>(a) % 16 || reinterpret_cast<uintptr_t>(b) % 16)
+        return set_error(FD_EINVAL, "state fields must be 16-byte aligned");
+    const int64_t n4 = n / 4;
+    const int nb = (int)std::min<int64_t>((n4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_swap, dim3(nb), dim3(256), 0, s, reinterpret_cast<float4 *>(a),
+                       reinterpret_cast<float4 *>(b), n4);
+    return check_launch("state swap");
+}
+
+}  // namespace fd

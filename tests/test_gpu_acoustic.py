@@ -1,0 +1,336 @@
+"""GPU parity of the acoustic hot path (HIP kernels via the C ABI) against
+the FP64 oracle on the same seeded inputs.
+
+Tolerances: relative L2 <= 1e-5 after one step, <= 1e-4 after a full run
+(fields and traces); integer/byte work (halo pack/unpack, subdomain
+emulation, tile independence) is bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_13094_amd import synth
+from gpu_helpers import rel_l2, run_gpu_forward, run_oracle_forward, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _fd():
+    from paper_2312_13094_amd import fd
+    return fd
+
+
+def _sparse_points(shape, h, n, rng, margin=0):
+    return np.stack([rng.uniform(margin * h, (s - 1 - margin) * h, n) for s in shape], 1)
+
+
+# ---------------------------------------------------------------------------
+# halo faces: bit-exact against the oracle's pack/unpack
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,so", [((21, 19, 70), 8), ((9, 33, 65), 4), ((40, 37), 12),
+                                      ((17, 16, 130), 16)])
+def test_pack_unpack_bit_exact(shape, so):
+    import torch
+    FD = _fd()
+    rng = np.random.default_rng(0)
+    g = FD.Grid(shape, (10.0,) * len(shape), so, 1e-4, 1000.0)
+    og = O.Grid(shape, (10.0,) * len(shape), so=so, dt=1e-4)
+    f = g.field()
+    f.copy_(torch.from_numpy(rng.standard_normal(g.field_elems).astype(np.float32)))
+    bufs = [torch.full((max(g.face_elems(k), 1),), float("nan"), device="cuda") for k in range(6)]
+    g.pack_halo(f, bufs)
+    torch.cuda.synchronize()
+    ref = og.zeros()
+    r = so // 2
+    ref[...] = g.with_halo(f).double().cpu().numpy()
+    for k in range(6):
+        n = og_face = O.face_elems(og, k)
+        assert g.face_elems(k) == og_face
+        if n:
+            np.testing.assert_array_equal(bufs[k][:n].double().cpu().numpy(), O.pack_face(og, ref, k))
+    # unpack fresh random buffers into every halo face
+    new = [torch.from_numpy(rng.standard_normal(max(g.face_elems(k), 1)).astype(np.float32)).cuda()
+           for k in range(6)]
+    g.unpack_halo(f, new)
+    torch.cuda.synchronize()
+    for k in range(6):
+        n = O.face_elems(og, k)
+        if n:
+            O.unpack_face(og, ref, k, new[k][:n].double().cpu().numpy())
+    np.testing.assert_array_equal(g.with_halo(f).double().cpu().numpy(), ref)
+    del r
+
+
+def test_pack_rejects_bad_face_mask():
+    import torch
+    FD = _fd()
+    g = FD.Grid((8, 8, 8), (10.0,) * 3, 4, 1e-4, 1000.0)
+    f = g.field()
+    bufs = [torch.zeros(g.face_elems(k), device="cuda") for k in range(6)]
+    with pytest.raises(FD.FdError):
+        g.pack_halo(f, bufs, mask=0x40)
+    bufs[3] = None
+    with pytest.raises(FD.FdError):
+        g.pack_halo(f, bufs)
+
+
+# ---------------------------------------------------------------------------
+# one step from a smooth random state
+# ---------------------------------------------------------------------------
+
+ONE_STEP = [
+    # shape, so, nbl, boundary, tile
+    ((37, 29, 101), 8, 6, 0, (4, 4, 16, 1)),
+    ((37, 29, 101), 8, 6, 1, (4, 2, 64, 1)),
+    ((33, 40, 70), 4, 5, 0, (8, 2, 8, 0)),
+    ((26, 35, 66), 12, 4, 1, (4, 8, 64, 1)),
+    ((34, 31, 65), 16, 8, 0, (2, 8, 16, 1)),
+    ((30, 24, 64), 2, 3, 0, (4, 1, 7, 1)),
+    ((22, 20, 90), 8, 4, 0, (0, 0, 0, 0)),     # one-thread-per-point kernel
+    ((168, 168), 4, 20, 0, None),
+    ((50, 77), 8, 10, 1, None),
+]
+
+
+@pytest.mark.parametrize("shape,so,nbl,bc,tile", ONE_STEP)
+def test_one_step_parity(shape, so, nbl, bc, tile):
+    rng = np.random.default_rng(10 + so)
+    ndim = len(shape)
+    h = 10.0
+    vmax = 4000.0
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, ndim, h, vmax)
+    u0 = synth.smooth_state(shape, 1, 4.0)
+    um = (0.9 * u0 + 0.1 * synth.smooth_state(shape, 2, 4.0)).astype(np.float32)
+    src = _sparse_points(shape, h, 3, rng)
+    rec = _sparse_points(shape, h, 40, rng)
+    q = rng.standard_normal((1, 3)).astype(np.float32) * 1e3
+    args = dict(shape=shape, spacing=(h,) * ndim, so=so, dt=dt, vmax=vmax, v=v, nt=1, nbl=nbl,
+                boundary=bc, src=src, q=q, rec=rec, u0=u0, um=um)
+    gu, gum, gd = run_gpu_forward(tile=tile, **args)
+    ou, oum, od = run_oracle_forward(**args)
+    assert rel_l2(gu, ou) <= 1e-5
+    np.testing.assert_array_equal(gum, u0.astype(np.float64))   # u^0 handed back unchanged
+    assert rel_l2(gd, od) <= 1e-5
+
+
+def test_tiles_are_bit_identical():
+    """The per-point arithmetic does not depend on the tile or z chunk."""
+    rng = np.random.default_rng(3)
+    shape, so, h, vmax = (45, 38, 97), 8, 10.0, 3000.0
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, 3, h, vmax)
+    u0 = synth.smooth_state(shape, 5, 3.0)
+    base = None
+    for tile in [(4, 4, 64, 1), (4, 1, 5, 0), (4, 2, 13, 1), (4, 8, 45, 1), (8, 2, 9, 1),
+                 (8, 4, 64, 0), (2, 8, 3, 1)]:
+        u, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, 5, nbl=7, u0=u0, tile=tile)
+        if base is None:
+            base = u
+        else:
+            np.testing.assert_array_equal(u, base)
+
+
+# ---------------------------------------------------------------------------
+# full runs
+# ---------------------------------------------------------------------------
+
+def test_2d_homogeneous_full_run():
+    """168 x 168 (128^2 + 20-point sponge), so 4, 200 steps, Ricker at the
+    centre, 128 receivers: fields and traces within 1e-4 of the oracle."""
+    c = synth.cfg_2d()
+    args = dict(shape=c.shape, spacing=c.spacing, so=c.so, dt=c.dt, vmax=c.vmax,
+                v=c.velocity(), nt=c.nt, nbl=c.nbl, boundary=c.boundary, src=c.src, q=c.q,
+                rec=c.rec)
+    gu, gum, gd = run_gpu_forward(**args)
+    ou, oum, od = run_oracle_forward(**args)
+    assert rel_l2(gu, ou) <= 1e-4
+    assert rel_l2(gum, oum) <= 1e-4
+    assert rel_l2(gd, od) <= 1e-4
+    assert np.abs(od).max() > 0
+
+
+@pytest.mark.parametrize("tile", [None, (4, 2, 32, 1)])
+def test_3d_layered_loopback_full_run(tile):
+    """The layered so-8 workload at 96^3 (same recipe as the 512^3 headline:
+    sponge, Ricker, receiver line, loopback halo exchange every step)."""
+    c = synth.cfg_3d_layered(n=96, nt=300, nbl=16)
+    args = dict(shape=c.shape, spacing=c.spacing, so=c.so, dt=c.dt, vmax=c.vmax,
+                v=c.velocity(), nt=c.nt, nbl=c.nbl, boundary=c.boundary, src=c.src, q=c.q,
+                rec=c.rec)
+    gu, _, gd = run_gpu_forward(tile=tile, **args)
+    ou, _, od = run_oracle_forward(**args)
+    assert rel_l2(gu, ou) <= 1e-4
+    assert rel_l2(gd, od) <= 1e-4
+
+
+def test_nan_in_padding_never_reaches_domain():
+    """Poison everything outside DOMAIN + halo (x padding) and the halo edges
+    and corners: a star stencil must read none of it."""
+    import torch
+    FD = _fd()
+    rng = np.random.default_rng(4)
+    shape, so, h, vmax = (30, 27, 75), 8, 10.0, 3000.0
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, 3, h, vmax)
+    u0 = synth.smooth_state(shape, 6, 3.0)
+    ref, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, 10, nbl=5, u0=u0)
+    g = FD.Grid(shape, (h,) * 3, so, dt, vmax, nbl=5)
+    g.set_model(to_dev(v))
+    a, b = g.field(), g.field()
+    for f in (a, b):
+        f.fill_(float("nan"))
+        hv = g.with_halo(f)
+        r = so // 2
+        hv[r:-r, r:-r, :] = 0.0     # halo faces along x zero
+        hv[r:-r, :, r:-r] = 0.0     # halo faces along y zero
+        hv[:, r:-r, r:-r] = 0.0     # halo faces along z zero
+    g.domain(a).copy_(to_dev(u0))
+    g.forward([a, b], nt=10)
+    torch.cuda.synchronize()
+    got = g.domain(a).double().cpu().numpy()
+    assert np.isfinite(got).all()
+    np.testing.assert_array_equal(got, ref)
+
+
+# ---------------------------------------------------------------------------
+# headline size (512^3, so 8): one step vs the oracle; 500 steps vs an exact
+# discrete solution
+# ---------------------------------------------------------------------------
+
+def _plane_waves(shape, h, modes, phases):
+    xs = [np.arange(n, dtype=np.float64) * h for n in shape]
+    out = np.zeros(shape, dtype=np.float64)
+    for m, ph in zip(modes, phases):
+        k = [2 * math.pi * mi / (n * h) for mi, n in zip(m, shape)]
+        out += np.cos(k[0] * xs[0][:, None, None] + k[1] * xs[1][None, :, None] +
+                      k[2] * xs[2][None, None, :] + ph)
+    return out
+
+
+@pytest.mark.slow
+def test_headline_512_one_step_vs_oracle():
+    c = synth.cfg_3d_layered()
+    u0 = _plane_waves(c.shape, 10.0, [(3, 5, 7), (11, 2, 6), (1, 13, 4)], [0.3, 1.1, 2.0])
+    u0 = u0.astype(np.float32)
+    um = (0.97 * u0).astype(np.float32)
+    args = dict(shape=c.shape, spacing=c.spacing, so=c.so, dt=c.dt, vmax=c.vmax,
+                v=c.velocity(), nt=1, nbl=c.nbl, boundary=c.boundary, src=c.src,
+                q=(c.q[40:41] * 1e6).astype(np.float32), rec=c.rec, u0=u0, um=um)
+    gu, _, gd = run_gpu_forward(**args)
+    ou, _, od = run_oracle_forward(**args)
+    assert rel_l2(gu, ou) <= 1e-5
+    assert rel_l2(gd, od) <= 1e-5
+
+
+def _symbol(w, theta):
+    return w[0] + 2 * sum(w[k] * math.cos(k * theta) for k in range(1, len(w)))
+
+
+@pytest.mark.slow
+def test_headline_512_plane_wave_500_steps():
+    """512^3, so 8, loopback (periodic) halos every step, 500 steps: the
+    discrete plane wave cos(k.x - w t) with sin^2(w dt/2) = -(v dt)^2/4 sum
+    sigma(k_a h)/h^2 is exact; FP32 stays within 1e-4 relative L2."""
+    import torch
+    FD = _fd()
+    n, so, h, v, nt = 512, 8, 10.0, 3000.0, 500
+    dt = synth.stable_dt(so, 3, h, 4500.0)
+    g = FD.Grid((n, n, n), (h,) * 3, so, dt, 4500.0, nbl=0, boundary=FD.FD_BC_LOOPBACK)
+    g.set_model(torch.full((n, n, n), v, dtype=torch.float32, device="cuda"))
+    w = O.d2_weights(so)  # FP64 weights, pinned by the oracle tests
+    m = (5, 3, 7)
+    k = [2 * math.pi * mi / (n * h) for mi in m]
+    s2 = -(v * dt) ** 2 / 4 * sum(_symbol(w, kk * h) / h ** 2 for kk in k)
+    om = 2 * math.asin(math.sqrt(s2)) / dt
+    ph = (torch.arange(n, device="cuda", dtype=torch.float64) * h)
+    phase = (k[0] * ph[:, None, None] + k[1] * ph[None, :, None] + k[2] * ph[None, None, :])
+    a, b = g.field(), g.field()
+    g.domain(a).copy_(torch.cos(phase).float())
+    g.domain(b).copy_(torch.cos(phase + om * dt).float())
+    g.forward([a, b], nt=nt)
+    want = torch.cos(phase - om * nt * dt)
+    got = g.domain(a).double()
+    err = (torch.linalg.vector_norm(got - want) / torch.linalg.vector_norm(want)).item()
+    assert err <= 1e-4, err
+
+
+# ---------------------------------------------------------------------------
+# multi-subdomain emulation on the device (external halos, pack/unpack)
+# ---------------------------------------------------------------------------
+
+def test_multidomain_emulation_bitwise():
+    import torch
+    FD = _fd()
+    rng = np.random.default_rng(8)
+    shape, so, h, vmax = (40, 36, 130), 8, 10.0, 3000.0
+    split = (2, 2, 2)
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, 3, h, vmax)
+    u0 = synth.smooth_state(shape, 9, 3.0)
+    nt = 8
+    ref, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, nt, u0=u0)
+    cuts = [np.array_split(np.arange(s), p) for s, p in zip(shape, split)]
+    blocks = list(np.ndindex(*split))
+    sub = {}
+    for bk in blocks:
+        sl = tuple(slice(c[i][0], c[i][-1] + 1) for c, i in zip(cuts, bk))
+        g = FD.Grid(tuple(s.stop - s.start for s in sl), (h,) * 3, so, dt, vmax,
+                    boundary=FD.FD_BC_EXTERNAL)
+        g.set_model(to_dev(np.ascontiguousarray(v[sl])))
+        a, b = g.field(), g.field()
+        g.domain(a).copy_(to_dev(np.ascontiguousarray(u0[sl])))
+        bufs = [torch.zeros(max(g.face_elems(k), 1), device="cuda") for k in range(6)]
+        sub[bk] = dict(g=g, sl=sl, st=[a, b], bufs=bufs)
+    for _ in range(nt):
+        for bk in blocks:
+            s = sub[bk]
+            s["g"].pack_halo(s["st"][0], s["bufs"])
+        for bk in blocks:
+            s = sub[bk]
+            recv = [None] * 6
+            mask = 0
+            for f in range(6):
+                nb = list(bk)
+                nb[f // 2] += 1 if f & 1 else -1
+                if 0 <= nb[f // 2] < split[f // 2]:
+                    recv[f] = sub[tuple(nb)]["bufs"][f ^ 1]
+                    mask |= 1 << f
+            s["g"].unpack_halo(s["st"][0], recv, mask=mask)
+        for bk in blocks:
+            s = sub[bk]
+            s["g"].forward(s["st"], nt=1)
+    torch.cuda.synchronize()
+    out = np.zeros(shape)
+    for bk in blocks:
+        s = sub[bk]
+        out[s["sl"]] = s["g"].domain(s["st"][0]).double().cpu().numpy()
+    np.testing.assert_array_equal(out, ref)
+
+
+# ---------------------------------------------------------------------------
+# error paths that need a device
+# ---------------------------------------------------------------------------
+
+def test_model_above_vmax_is_rejected():
+    FD = _fd()
+    g = FD.Grid((16, 16, 16), (10.0,) * 3, 8, 1e-4, 2000.0)
+    v = np.full((16, 16, 16), 1500.0, dtype=np.float32)
+    v[3, 4, 5] = 2500.0
+    with pytest.raises(FD.FdError) as e:
+        g.set_model(to_dev(v))
+    assert e.value.code == FD.FD_EUNSTABLE
+    v[3, 4, 5] = -1.0
+    with pytest.raises(FD.FdError):
+        g.set_model(to_dev(v))
+
+
+def test_receiver_outside_grid_is_rejected():
+    FD = _fd()
+    g = FD.Grid((16, 16, 16), (10.0,) * 3, 8, 1e-4, 2000.0)
+    with pytest.raises(FD.FdError) as e:
+        g.sparse(np.array([[10.0, 10.0, 150.5]]))
+    assert e.value.code == FD.FD_EINVAL
