@@ -66,18 +66,19 @@ def minmax(a: np.ndarray, lo: float, hi: float) -> np.ndarray:
 
 
 def layered_profile(nz: int, seed: int, vmin=1500.0, vmax=4500.0, min_thick=4) -> np.ndarray:
-    """1-D velocity profile v(z) of 8-12 flat layers, velocities increasing
-    with depth.  Returns float32 [nz]."""
+    """1-D velocity profile v(z) of 8-12 flat layers (fewer if nz is too
+    short for them at min_thick cells each), velocities increasing with
+    depth.  Thicknesses are min_thick plus a random composition of the
+    remaining cells.  Returns float32 [nz]."""
     rng = np.random.default_rng(seed)
     L = int(rng.integers(8, 13))
+    L = max(1, min(L, nz // min_thick))
     vel = np.sort(rng.uniform(vmin, vmax, L))
-    while True:
-        cuts = np.sort(rng.choice(np.arange(min_thick, nz - min_thick), L - 1, replace=False))
-        th = np.diff(np.concatenate([[0], cuts, [nz]]))
-        if th.min() >= min_thick:
-            break
+    spare = nz - L * min_thick
+    bars = np.sort(rng.integers(0, spare + 1, L - 1))
+    extra = np.diff(np.concatenate([[0], bars, [spare]]))
+    edges = np.concatenate([[0], np.cumsum(min_thick + extra)])
     prof = np.empty(nz)
-    edges = np.concatenate([[0], cuts, [nz]])
     for i in range(L):
         prof[edges[i]:edges[i + 1]] = vel[i]
     return prof.astype(np.float32)
