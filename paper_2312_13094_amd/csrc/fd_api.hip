@@ -58,6 +58,33 @@ static void d2_weights(int r, double *w)
     }
 }
 
+// FP64 centred first-derivative weights of order 2r (unit spacing):
+// a_k = (-1)^(k+1) (r!)^2 / (k (r-k)! (r+k)!), k = 1..r.
+static void d1_weights(int r, double *a)
+{
+    auto lf = [](int k) { return std::lgamma((double)k + 1.0); };
+    for (int k = 1; k <= r; ++k) {
+        const double mag = std::exp(2.0 * lf(r) - lf(r - k) - lf(r + k)) / (double)k;
+        a[k - 1] = (k % 2) ? mag : -mag;
+    }
+}
+
+// peak of the squared first-derivative symbol (2 sum_k a_k sin k xi)^2
+static double d1_symbol_peak(int r)
+{
+    double a[kMaxR];
+    d1_weights(r, a);
+    double best = 0.0;
+    const int ns = 20000;
+    for (int i = 0; i <= ns; ++i) {
+        const double xi = M_PI * i / ns;
+        double s = 0.0;
+        for (int k = 1; k <= r; ++k) s += 2.0 * a[k - 1] * std::sin(k * xi);
+        best = std::max(best, s * s);
+    }
+    return best;
+}
+
 static void prof_release(fd_grid *g);
 
 static int64_t roundup(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
@@ -69,6 +96,7 @@ static void free_grid(fd_grid *g)
     (void)hipFree(g->vdt2);
     for (float *&p : g->tti) (void)hipFree(p);
     for (float *&p : g->facebuf) (void)hipFree(p);
+    for (float *&p : g->inter) (void)hipFree(p);
     (void)hipFree(g->scratch_u32);
     delete g;
 }
@@ -138,8 +166,15 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     if (d.ndim != 2 && d.ndim != 3) return set_error(FD_EINVAL, "ndim must be 2 or 3");
     if (d.space_order < 2 || d.space_order > 16 || d.space_order % 2)
         return set_error(FD_EINVAL, "space_order must be even, 2..16");
-    if (d.physics != FD_ACOUSTIC)
-        return set_error(FD_ENOTSUP, "only FD_ACOUSTIC is implemented");
+    if (d.physics != FD_ACOUSTIC && d.physics != FD_TTI)
+        return set_error(FD_EINVAL, "unknown physics");
+    if (d.physics == FD_TTI) {
+        if (d.ndim != 3 || d.space_order < 4 || d.space_order > 12)
+            return set_error(FD_EINVAL, "TTI needs a 3-D grid and space order 4..12");
+        if (d.boundary != FD_BC_ZERO)
+            return set_error(FD_ENOTSUP, "TTI supports the zero halo only");
+        if (!(d.eps_max >= 0.0)) return set_error(FD_EINVAL, "eps_max must be >= 0");
+    }
     if (d.boundary < FD_BC_ZERO || d.boundary > FD_BC_EXTERNAL)
         return set_error(FD_EINVAL, "unknown boundary mode");
     if (!(d.dt > 0.0) || !(d.vmax > 0.0)) return set_error(FD_EINVAL, "dt and vmax must be > 0");
@@ -180,6 +215,7 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     for (int k = 1; k <= r; ++k) S += 2.0 * std::fabs(w[k]);
     double ih2 = 1.0 / (g->h[0] * g->h[0]) + 1.0 / (g->h[2] * g->h[2]);
     if (d.ndim == 3) ih2 += 1.0 / (g->h[1] * g->h[1]);
+    if (d.physics == FD_TTI) S = d1_symbol_peak(r) * (1.0 + 2.0 * d.eps_max);
     if (d.vmax * d.dt * std::sqrt(S * ih2) > 2.0 * (1.0 + 1e-12)) {
         delete g;
         return set_error(FD_EUNSTABLE, "time step exceeds the leapfrog stability limit");
@@ -214,6 +250,14 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
         p.cx[k] = (float)(wk / (g->h[2] * g->h[2]));
         p.cy[k] = d.ndim == 3 ? (float)(wk / (g->h[1] * g->h[1])) : 0.0f;
     }
+    double a1[kMaxR];
+    d1_weights(r, a1);
+    for (int k = 0; k < kMaxR; ++k) {
+        const double ak = k < r ? a1[k] : 0.0;
+        p.dz[k] = (float)(ak / g->h[0]);
+        p.dy[k] = (float)(ak / g->h[1]);
+        p.dx[k] = (float)(ak / g->h[2]);
+    }
     p.c0 = (float)(w[0] / (g->h[0] * g->h[0]) + w[0] / (g->h[2] * g->h[2]) +
                    (d.ndim == 3 ? w[0] / (g->h[1] * g->h[1]) : 0.0));
     const double lnR = std::log(1.0e3);
@@ -239,6 +283,20 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     if (hipMemset(g->vdt2, 0, L.field_bytes) != hipSuccess) {
         free_grid(g);
         return set_error(FD_EDEVICE, "hipMemset failed");
+    }
+    if (d.physics == FD_TTI) {
+        for (int i = 0; i < 4; ++i)
+            if (hipMalloc(&g->tti[i], L.field_bytes) != hipSuccess ||
+                hipMemset(g->tti[i], 0, L.field_bytes) != hipSuccess) {
+                free_grid(g);
+                return set_error(FD_ENOMEM, "TTI model allocation failed");
+            }
+        for (int i = 0; i < 6; ++i)
+            if (hipMalloc(&g->inter[i], L.field_bytes) != hipSuccess ||
+                hipMemset(g->inter[i], 0, L.field_bytes) != hipSuccess) {
+                free_grid(g);
+                return set_error(FD_ENOMEM, "TTI work-field allocation failed");
+            }
     }
     if (d.boundary == FD_BC_LOOPBACK) {
         for (int f = 0; f < 6; ++f) {
@@ -307,23 +365,31 @@ int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n, int32_t *
 int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream)
 {
     if (!g || !vel_dev) return set_error(FD_EINVAL, "fd_set_model: null argument");
-    (void)tti_dev;
+    const bool tti = g->d.physics == FD_TTI;
+    if (tti && (!tti_dev || !tti_dev[0] || !tti_dev[1] || !tti_dev[2] || !tti_dev[3]))
+        return set_error(FD_EINVAL, "fd_set_model: TTI needs epsilon, delta, theta, phi");
     DeviceGuard dg(g->d.device);
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemsetAsync(g->scratch_u32, 0, sizeof(unsigned), s) != hipSuccess)
+    if (hipMemsetAsync(g->scratch_u32, 0, 2 * sizeof(unsigned), s) != hipSuccess)
         return set_error(FD_EDEVICE, "hipMemsetAsync failed");
-    int rc = launch_build_vdt2(g, vel_dev, g->vdt2, g->scratch_u32, s);
+    int rc = tti ? launch_tti_model(g, vel_dev, tti_dev, g->scratch_u32, s)
+                 : launch_build_vdt2(g, vel_dev, g->vdt2, g->scratch_u32, s);
     if (rc) return rc;
-    unsigned bits = 0;
-    if (hipMemcpyAsync(&bits, g->scratch_u32, sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
+    unsigned bits[2] = {0u, 0u};
+    if (hipMemcpyAsync(bits, g->scratch_u32, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_error(FD_EDEVICE, "model check copy failed");
-    float vmax;
-    std::memcpy(&vmax, &bits, sizeof(float));
+    float vmax, emax;
+    std::memcpy(&vmax, &bits[0], sizeof(float));
+    std::memcpy(&emax, &bits[1], sizeof(float));
     if (!(vmax <= (float)g->d.vmax * (1.0f + 1e-6f))) {
         g->model_loaded = false;
         return set_error(FD_EUNSTABLE, "velocity model exceeds vmax or is not positive");
+    }
+    if (tti && !(emax <= (float)g->d.eps_max * (1.0f + 1e-6f) + 1e-12f)) {
+        g->model_loaded = false;
+        return set_error(FD_EUNSTABLE, "epsilon exceeds eps_max, or epsilon/delta <= -1/2");
     }
     g->model_loaded = true;
     return FD_OK;
@@ -363,6 +429,48 @@ int fd_unpack_halo(const fd_grid *g, float *field_dev, unsigned face_mask,
     return launch_unpack(g, field_dev, face_mask, buf_dev, (hipStream_t)stream);
 }
 
+// TTI forward: states {p, p-, r, r-}; both fields updated in place each step
+static int forward_tti(fd_grid *g, float *const *st, SparseArgs inj, SparseArgs smp,
+                       const float *q_dev, float *d_dev, int nt, float *const *ckpt_dev,
+                       int ckpt_every, hipStream_t s)
+{
+    int rc;
+    float *p = st[0], *pm = st[1], *r = st[2], *rm = st[3];
+    const SparseArgs none{0, nullptr, nullptr, nullptr, nullptr, 0.0f};
+    for (int n = 0; n < nt; ++n) {
+        if (ckpt_dev && n % ckpt_every == 0) {
+            float *const *c = ckpt_dev + 4 * (n / ckpt_every);
+            const float *src4[4] = {p, pm, r, rm};
+            for (int i = 0; i < 4; ++i) {
+                if (!c[i]) return set_error(FD_EINVAL, "fd_forward: null checkpoint buffer");
+                if (hipMemcpyAsync(c[i], src4[i], g->L.field_bytes, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                    return set_error(FD_EDEVICE, "checkpoint copy failed");
+            }
+        }
+        const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
+        if (t && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
+            return set_error(FD_EDEVICE, "hipEventRecord failed");
+        if ((rc = launch_tti_step(g, p, pm, pm, r, rm, rm, s))) return rc;
+        if (t) {
+            if (hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
+                return set_error(FD_EDEVICE, "hipEventRecord failed");
+            ++g->prof_used;
+        }
+        inj.vals = inj.n ? q_dev + (int64_t)n * inj.n : nullptr;
+        smp.out = smp.n ? d_dev + (int64_t)n * smp.n : nullptr;
+        if (inj.n && (rc = launch_sparse(g, rm, inj, none, s))) return rc;
+        if ((rc = launch_sparse(g, pm, inj, smp, s))) return rc;
+        std::swap(p, pm);
+        std::swap(r, rm);
+    }
+    if (nt % 2) {
+        if ((rc = launch_swap(st[0], st[1], g->L.field_elems, s))) return rc;
+        return launch_swap(st[2], st[3], g->L.field_elems, s);
+    }
+    return FD_OK;
+}
+
 int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const float *q_dev,
                const fd_sparse *rec, float *d_dev, int nt, float *const *ckpt_dev,
                int ckpt_every, void *stream)
@@ -370,6 +478,11 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
     if (!g || !state_dev || !state_dev[0] || !state_dev[1] || nt < 0)
         return set_error(FD_EINVAL, "fd_forward: bad argument");
     if (state_dev[0] == state_dev[1]) return set_error(FD_EINVAL, "fd_forward: states alias");
+    if (g->d.physics == FD_TTI &&
+        (!state_dev[2] || !state_dev[3] || state_dev[2] == state_dev[3] ||
+         state_dev[2] == state_dev[0] || state_dev[2] == state_dev[1] ||
+         state_dev[3] == state_dev[0] || state_dev[3] == state_dev[1]))
+        return set_error(FD_EINVAL, "fd_forward: TTI needs four distinct state fields");
     if (!g->model_loaded) return set_error(FD_EINVAL, "fd_forward: no model loaded");
     if (ckpt_dev && ckpt_every < 1) return set_error(FD_EINVAL, "fd_forward: ckpt_every < 1");
     int rc = validate_sparse(g, src, q_dev, "sources");
@@ -384,6 +497,8 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
                    nullptr, nullptr, (float)(1.0 / cell_volume(g))};
     SparseArgs smp{rec ? rec->n : 0, rec ? rec->base_dev : nullptr, rec ? rec->frac_dev : nullptr,
                    nullptr, nullptr, 1.0f};
+    if (g->d.physics == FD_TTI)
+        return forward_tti(g, state_dev, inj, smp, q_dev, d_dev, nt, ckpt_dev, ckpt_every, s);
     float *cur = state_dev[0], *prev = state_dev[1];
     for (int n = 0; n < nt; ++n) {
         if (ckpt_dev && n % ckpt_every == 0) {
@@ -417,6 +532,8 @@ int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const 
     if (!g->model_loaded) return set_error(FD_EINVAL, "fd_adjoint: no model loaded");
     if (g->d.boundary == FD_BC_EXTERNAL)
         return set_error(FD_ENOTSUP, "fd_adjoint: FD_BC_EXTERNAL is not supported");
+    if (g->d.physics != FD_ACOUSTIC)
+        return set_error(FD_ENOTSUP, "fd_adjoint: acoustic physics only");
     int rc = validate_sparse(g, rec, resid_dev, "receivers");
     if (rc) return rc;
     const bool grad = grad_m_dev != nullptr;

@@ -27,6 +27,7 @@ struct StepParams {
     float cy[kMaxR + 1];          // w_k / h_y^2 (zero in 2-D)
     float cx[kMaxR + 1];          // w_k / h_x^2
     float c0;                     // cz[0] + cy[0] + cx[0]
+    float dz[kMaxR], dy[kMaxR], dx[kMaxR];  // first-derivative a_k / h per axis (TTI)
     float gz, gy, gx;             // damping gamma_max per axis (1/s)
     float inv_nbl;                // 1 / nbl
     float half_dt;                // dt / 2
@@ -83,6 +84,7 @@ struct fd_grid {
     float *vdt2 = nullptr;        // padded v^2 dt^2
     float *tti[4] = {nullptr, nullptr, nullptr, nullptr};  // padded eps, delta, theta, phi
     float *facebuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    float *inter[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // TTI pass-1 output
     unsigned *scratch_u32 = nullptr;  // small device scratch (model checks)
     bool model_loaded = false;
     std::vector<hipEvent_t> prof_ev;  // armed step-kernel timing events (pairs)
@@ -111,5 +113,9 @@ int launch_build_vdt2(const fd_grid *g, const float *vel, float *vdt2, unsigned 
 int launch_imaging(const fd_grid *g, const float *lam, const float *up, const float *u0,
                    const float *um, float *grad, hipStream_t s);
 int launch_grad_to_vel(const fd_grid *g, const float *gm, float *gv, hipStream_t s);
+int launch_tti_model(const fd_grid *g, const float *vel, const float *const *tti, unsigned *flags,
+                     hipStream_t s);
+int launch_tti_step(const fd_grid *g, const float *p, const float *pm, float *pp, const float *r,
+                    const float *rm, float *rp, hipStream_t s);
 
 }  // namespace fd

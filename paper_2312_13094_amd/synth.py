@@ -14,6 +14,7 @@ Ricker source, hundreds of steps; problem-setup section).  Randomness uses
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -45,19 +46,17 @@ def ricker(nt: int, dt: float, f0: float, t0: float | None = None) -> np.ndarray
 def smooth_noise(shape, sigma: float, rng) -> np.ndarray:
     """N(0,1) noise smoothed by a periodic Gaussian filter of std `sigma` cells
     (applied in Fourier space), float64."""
+    import scipy.fft as sfft
     x = rng.standard_normal(shape)
-    X = np.fft.rfftn(x)
-    k2 = 0.0
+    workers = max(1, min(16, os.cpu_count() or 1))
+    X = sfft.rfftn(x, workers=workers)
+    del x
     for ax, n in enumerate(shape):
-        if ax == len(shape) - 1:
-            k = np.fft.rfftfreq(n)
-        else:
-            k = np.fft.fftfreq(n)
+        k = np.fft.rfftfreq(n) if ax == len(shape) - 1 else np.fft.fftfreq(n)
         sh = [1] * len(shape)
         sh[ax] = -1
-        k2 = k2 + (k.reshape(sh) * 2 * math.pi) ** 2
-    X *= np.exp(-0.5 * sigma * sigma * k2)
-    return np.fft.irfftn(X, s=shape, axes=list(range(len(shape))))
+        X *= np.exp(-0.5 * (sigma * 2 * math.pi * k) ** 2).reshape(sh)
+    return sfft.irfftn(X, s=shape, axes=list(range(len(shape))), workers=workers)
 
 
 def minmax(a: np.ndarray, lo: float, hi: float) -> np.ndarray:
@@ -160,3 +159,61 @@ def cfg_3d_layered(n: int = 512, nt: int = 500, seed: int = 2, so: int = 8, nbl:
     q = ricker(nt, dt, 15.0)[:, None]
     return Acoustic("acoustic3d_%dcube_so%d_layered" % (n, so), (n, n, n), (h, h, h), so, nbl,
                     dt, nt, vmax, 1, src, rec, q, vel_profile=prof)
+
+
+# First-derivative symbol peaks S1 = max_xi (2 sum_k a_k sin k xi)^2 of the
+# centred first-derivative stencils; the rotated TTI operators are products
+# of two first derivatives, stable for v sqrt(1+2 eps) dt sqrt(3 S1) / h <= 2.
+_STAB1 = {4: 1.8830, 8: 2.9950, 12: 3.6897}
+
+
+def tti_stable_dt(so: int, h: float, vmax: float, eps_max: float, frac: float = 0.5) -> float:
+    return frac * 2.0 * h / (vmax * math.sqrt(1.0 + 2.0 * eps_max) * math.sqrt(3.0 * _STAB1[so]))
+
+
+@dataclass
+class TTI:
+    """Pseudo-acoustic TTI workload: velocity, epsilon, delta, tilt theta and
+    azimuth phi fields, plus acquisition (source at the centre)."""
+    name: str
+    shape: tuple
+    spacing: tuple
+    so: int
+    nbl: int
+    dt: float
+    nt: int
+    vmax: float
+    eps_max: float
+    src: np.ndarray
+    rec: np.ndarray
+    q: np.ndarray
+    fields: dict = field(default=None, repr=False)   # v, eps, delta, theta, phi (float32)
+
+    @property
+    def points(self):
+        return int(np.prod(self.shape))
+
+
+def cfg_tti(n: int = 384, nt: int = 500, seed: int = 3, so: int = 12, nbl: int = 40) -> TTI:
+    """3-D TTI on an n^3 DOMAIN (headline n = 384, so 12, 500 steps): v, eps,
+    delta, theta, phi from Gaussian-filtered noise (sigma 8 cells, periodic)
+    min-max mapped to [1500, 4500] m/s, [0, 0.3], [0, 0.15], [0, pi/4],
+    [0, pi/4]; 40-point sponge, 20 Hz Ricker at the centre, h = 10 m."""
+    h = 10.0
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n)
+    ranges = [("v", 1500.0, 4500.0), ("eps", 0.0, 0.3), ("delta", 0.0, 0.15),
+              ("theta", 0.0, math.pi / 4), ("phi", 0.0, math.pi / 4)]
+    f = {}
+    for name, lo, hi in ranges:
+        f[name] = minmax(smooth_noise(shape, 8.0, rng), lo, hi).astype(np.float32)
+    vmax, eps_max = 4500.0, 0.3
+    dt = tti_stable_dt(so, h, vmax, eps_max)
+    c = (n / 2 - 0.5) * h
+    src = np.array([[c, c, c]])
+    s = n / 512.0
+    rz = round(45 * s)
+    rec = np.array([[rz * h, c, (i * (n - 1) / max(n - 1, 1)) * h] for i in range(n)])
+    q = ricker(nt, dt, 20.0)[:, None]
+    return TTI("tti3d_%dcube_so%d" % (n, so), shape, (h, h, h), so, nbl, dt, nt, vmax, eps_max,
+               src, rec, q, fields=f)
