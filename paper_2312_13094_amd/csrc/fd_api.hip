@@ -26,25 +26,6 @@ int check_launch(const char *what)
     return FD_OK;
 }
 
-// Makes the handle's device current for the duration of a call.
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-        if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (prev_ >= 0) (void)hipSetDevice(prev_);
-    }
-    bool ok() const { return ok_; }
-
-  private:
-    int prev_ = -1;
-    bool ok_ = true;
-};
-
 // FP64 centred second-derivative weights of order 2r (unit spacing):
 // w_k = 2 (-1)^(k+1) (r!)^2 / (k^2 (r-k)! (r+k)!), w_0 = -2 sum 1/k^2.
 static void d2_weights(int r, double *w)
@@ -83,6 +64,76 @@ static double d1_symbol_peak(int r)
         best = std::max(best, s * s);
     }
     return best;
+}
+
+static int64_t roundup(int64_t a, int64_t m);
+
+// Padded layout and per-launch step constants of a (sub)domain of extent n
+// (ny == 1 for 2-D) and spacing h, shared by single grids and batched shots.
+void make_geometry(const fd_grid_desc &d, int ndim, const int n[3], const double h[3], int r,
+                   fd_layout &L, StepParams &p)
+{
+    double w[kMaxR + 1];
+    d2_weights(r, w);
+    L.halo = r;
+    L.pitch_y = roundup(kXOff + n[2] + r, 32);
+    const int64_t Y = ndim == 3 ? n[1] + 2 * r : 1;
+    const int64_t Z = n[0] + 2 * r;
+    L.pitch_z = Y * L.pitch_y;
+    L.padded[0] = Z;
+    L.padded[1] = Y;
+    L.padded[2] = L.pitch_y;
+    L.offset = r * L.pitch_z + (ndim == 3 ? r : 0) * L.pitch_y + kXOff;
+    L.field_elems = Z * L.pitch_z;
+    L.field_bytes = (size_t)L.field_elems * sizeof(float);
+
+    p.nz = n[0];
+    p.ny = n[1];
+    p.nx = n[2];
+    p.nbl = d.nbl;
+    p.pitch_y = L.pitch_y;
+    p.pitch_z = L.pitch_z;
+    p.offset = L.offset;
+    for (int k = 0; k <= kMaxR; ++k) {
+        const double wk = k <= r ? w[k] : 0.0;
+        p.cz[k] = (float)(wk / (h[0] * h[0]));
+        p.cx[k] = (float)(wk / (h[2] * h[2]));
+        p.cy[k] = ndim == 3 ? (float)(wk / (h[1] * h[1])) : 0.0f;
+    }
+    double a1[kMaxR];
+    d1_weights(r, a1);
+    for (int k = 0; k < kMaxR; ++k) {
+        const double ak = k < r ? a1[k] : 0.0;
+        p.dz[k] = (float)(ak / h[0]);
+        p.dy[k] = (float)(ak / h[1]);
+        p.dx[k] = (float)(ak / h[2]);
+    }
+    p.c0 = (float)(w[0] / (h[0] * h[0]) + w[0] / (h[2] * h[2]) +
+                   (ndim == 3 ? w[0] / (h[1] * h[1]) : 0.0));
+    const double lnR = std::log(1.0e3);
+    auto gmax = [&](double h) { return d.nbl > 0 ? 3.0 * d.vmax * lnR / (2.0 * d.nbl * h) : 0.0; };
+    p.gz = (float)gmax(h[0]);
+    p.gy = ndim == 3 ? (float)gmax(h[1]) : 0.0f;
+    p.gx = (float)gmax(h[2]);
+    p.inv_nbl = d.nbl > 0 ? 1.0f / (float)d.nbl : 0.0f;
+    p.half_dt = (float)(0.5 * d.dt);
+
+}
+
+// Leapfrog stability: v dt sqrt(S sum 1/h^2) <= 2 with S the bound of the
+// stencil's symbol (TTI: the squared first-derivative peak times 1 + 2 eps).
+int check_stability(const fd_grid_desc &d, int ndim, const double h[3], int r)
+{
+    double w[kMaxR + 1];
+    d2_weights(r, w);
+    double S = -w[0];
+    for (int k = 1; k <= r; ++k) S += 2.0 * std::fabs(w[k]);
+    double ih2 = 1.0 / (h[0] * h[0]) + 1.0 / (h[2] * h[2]);
+    if (ndim == 3) ih2 += 1.0 / (h[1] * h[1]);
+    if (d.physics == FD_TTI) S = d1_symbol_peak(r) * (1.0 + 2.0 * d.eps_max);
+    if (d.vmax * d.dt * std::sqrt(S * ih2) > 2.0 * (1.0 + 1e-12))
+        return set_error(FD_EUNSTABLE, "time step exceeds the leapfrog stability limit");
+    return FD_OK;
 }
 
 static void prof_release(fd_grid *g);
@@ -208,65 +259,13 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
         }
     }
 
-    // stability: v dt sqrt(S sum 1/h^2) <= 2 with S the symbol bound of the stencil
-    double w[kMaxR + 1];
-    d2_weights(r, w);
-    double S = -w[0];
-    for (int k = 1; k <= r; ++k) S += 2.0 * std::fabs(w[k]);
-    double ih2 = 1.0 / (g->h[0] * g->h[0]) + 1.0 / (g->h[2] * g->h[2]);
-    if (d.ndim == 3) ih2 += 1.0 / (g->h[1] * g->h[1]);
-    if (d.physics == FD_TTI) S = d1_symbol_peak(r) * (1.0 + 2.0 * d.eps_max);
-    if (d.vmax * d.dt * std::sqrt(S * ih2) > 2.0 * (1.0 + 1e-12)) {
+    if (check_stability(d, g->ndim, g->h, r) != FD_OK) {
         delete g;
-        return set_error(FD_EUNSTABLE, "time step exceeds the leapfrog stability limit");
+        return FD_EUNSTABLE;
     }
 
-    // layout
-    fd_layout &L = g->L;
-    L.halo = r;
-    L.pitch_y = roundup(kXOff + g->n[2] + r, 32);
-    const int64_t Y = d.ndim == 3 ? g->n[1] + 2 * r : 1;
-    const int64_t Z = g->n[0] + 2 * r;
-    L.pitch_z = Y * L.pitch_y;
-    L.padded[0] = Z;
-    L.padded[1] = Y;
-    L.padded[2] = L.pitch_y;
-    L.offset = r * L.pitch_z + (d.ndim == 3 ? r : 0) * L.pitch_y + kXOff;
-    L.field_elems = Z * L.pitch_z;
-    L.field_bytes = (size_t)L.field_elems * sizeof(float);
-
-    // step constants
-    StepParams &p = g->sp;
-    p.nz = g->n[0];
-    p.ny = g->n[1];
-    p.nx = g->n[2];
-    p.nbl = d.nbl;
-    p.pitch_y = L.pitch_y;
-    p.pitch_z = L.pitch_z;
-    p.offset = L.offset;
-    for (int k = 0; k <= kMaxR; ++k) {
-        const double wk = k <= r ? w[k] : 0.0;
-        p.cz[k] = (float)(wk / (g->h[0] * g->h[0]));
-        p.cx[k] = (float)(wk / (g->h[2] * g->h[2]));
-        p.cy[k] = d.ndim == 3 ? (float)(wk / (g->h[1] * g->h[1])) : 0.0f;
-    }
-    double a1[kMaxR];
-    d1_weights(r, a1);
-    for (int k = 0; k < kMaxR; ++k) {
-        const double ak = k < r ? a1[k] : 0.0;
-        p.dz[k] = (float)(ak / g->h[0]);
-        p.dy[k] = (float)(ak / g->h[1]);
-        p.dx[k] = (float)(ak / g->h[2]);
-    }
-    p.c0 = (float)(w[0] / (g->h[0] * g->h[0]) + w[0] / (g->h[2] * g->h[2]) +
-                   (d.ndim == 3 ? w[0] / (g->h[1] * g->h[1]) : 0.0));
-    const double lnR = std::log(1.0e3);
-    auto gmax = [&](double h) { return d.nbl > 0 ? 3.0 * d.vmax * lnR / (2.0 * d.nbl * h) : 0.0; };
-    p.gz = (float)gmax(g->h[0]);
-    p.gy = d.ndim == 3 ? (float)gmax(g->h[1]) : 0.0f;
-    p.gx = (float)gmax(g->h[2]);
-    p.inv_nbl = d.nbl > 0 ? 1.0f / (float)d.nbl : 0.0f;
-    p.half_dt = (float)(0.5 * d.dt);
+    make_geometry(d, g->ndim, g->n, g->h, r, g->L, g->sp);
+    const fd_layout &L = g->L;
 
     g->tune = d.ndim == 3 ? Tuning{4, 4, 64, 1} : Tuning{0, 0, 0, 0};
 

@@ -1,0 +1,401 @@
+// Host side of the batched multi-shot gradient: per-shot workspaces, the
+// device shot table, and the capture of one gradient's whole schedule into
+// a hipGraph (forward with checkpoints, per-segment recomputation, adjoint
+// with the fused imaging condition, ordered reduction into the full model).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "batch_internal.h"
+
+namespace {
+
+struct ShotHost {
+    int n[3] = {0, 0, 0};
+    int org[3] = {0, 0, 0};
+    fd_layout L{};
+    fd::StepParams p{};
+    float *ws = nullptr;
+    int ns = 0, nr = 0;
+    int32_t *sbase = nullptr, *rbase = nullptr;
+    float *sfrac = nullptr, *rfrac = nullptr;
+    int ntx = 0, nty = 0, nzc = 0, block0 = 0;
+};
+
+}  // namespace
+
+struct fd_batch {
+    fd_grid_desc d{};
+    int nshots = 0, nt = 0, k = 1, nck = 0, nfields = 0, r = 0;
+    double h[3] = {0, 0, 0};
+    int64_t full[3] = {0, 0, 0};
+    std::vector<ShotHost> sh;
+    fd::BatchShot *table = nullptr;
+    fd::Tuning tune{4, 4, 64, 1};
+    int total_blocks = 0;
+    const float *vel_full = nullptr;
+    unsigned *scratch = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> key;
+    size_t bytes = 0;
+    int64_t max_stride = 0, max_pts = 0;
+    bool model_loaded = false;
+};
+
+namespace fd {
+namespace {
+
+void drop_graph(fd_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->key.clear();
+}
+
+void layout_blocks(fd_batch *b)
+{
+    const int ty = b->tune.by * b->tune.ry;
+    int acc = 0;
+    for (ShotHost &s : b->sh) {
+        s.ntx = (s.n[2] + 63) / 64;
+        s.nty = (s.n[1] + ty - 1) / ty;
+        s.nzc = (s.n[0] + b->tune.nzb - 1) / b->tune.nzb;
+        s.block0 = acc;
+        acc += s.ntx * s.nty * s.nzc;
+    }
+    b->total_blocks = acc;
+}
+
+int upload_table(fd_batch *b, const float *const *q, const float *const *dobs, float *const *d)
+{
+    std::vector<BatchShot> t(b->nshots);
+    for (int i = 0; i < b->nshots; ++i) {
+        const ShotHost &s = b->sh[i];
+        BatchShot &e = t[i];
+        e.p = s.p;
+        e.base = s.ws;
+        e.stride = s.L.field_elems;
+        e.ntx = s.ntx;
+        e.nty = s.nty;
+        e.nzc = s.nzc;
+        e.block0 = s.block0;
+        for (int a = 0; a < 3; ++a) e.org[a] = s.org[a];
+        e.ns = s.ns;
+        e.nr = s.nr;
+        e.sbase = s.sbase;
+        e.sfrac = s.sfrac;
+        e.rbase = s.rbase;
+        e.rfrac = s.rfrac;
+        e.q = q ? q[i] : nullptr;
+        e.dobs = dobs ? dobs[i] : nullptr;
+        e.d = d ? d[i] : nullptr;
+    }
+    if (hipMemcpy(b->table, t.data(), sizeof(BatchShot) * t.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return set_error(FD_EDEVICE, "shot table upload failed");
+    return FD_OK;
+}
+
+void free_batch(fd_batch *b)
+{
+    drop_graph(b);
+    for (ShotHost &s : b->sh) {
+        (void)hipFree(s.ws);
+        (void)hipFree(s.sbase);
+        (void)hipFree(s.sfrac);
+        (void)hipFree(s.rbase);
+        (void)hipFree(s.rfrac);
+    }
+    (void)hipFree(b->table);
+    (void)hipFree(b->scratch);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+// the whole gradient schedule, enqueued on s (captured once into a graph)
+int enqueue_schedule(fd_batch *b, float *grad_v, hipStream_t s)
+{
+    const BatchShot *T = b->table;
+    const int ns = b->nshots;
+    const int k = b->k;
+    const float hinv = (float)(1.0 / (b->h[0] * b->h[1] * b->h[2]));
+    const double dt = b->d.dt;
+    const float inv_dt2 = (float)(1.0 / (dt * dt)), inv_2dt = (float)(0.5 / dt);
+    const int slot0 = kCkpt0 + 2 * b->nck;
+    int rc;
+#define FD_TRY(x) \
+    if ((rc = (x))) return rc
+    for (int f : {(int)kFA, (int)kFB, (int)kLA, (int)kLB, (int)kGrad})
+        FD_TRY(launch_batch_zero(T, ns, b->max_stride, f, s));
+    int cur = kFA, prev = kFB;
+    for (int n = 0; n < b->nt; ++n) {
+        if (n % k == 0) {
+            FD_TRY(launch_batch_copy(T, ns, b->max_stride, cur, kCkpt0 + 2 * (n / k), s));
+            FD_TRY(launch_batch_copy(T, ns, b->max_stride, prev, kCkpt0 + 2 * (n / k) + 1, s));
+        }
+        FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, cur, prev, prev, s));
+        FD_TRY(launch_batch_sparse(T, ns, 0, n, prev, hinv, s));
+        std::swap(cur, prev);
+    }
+    int lam = kLA, lamo = kLB;
+    for (int j = b->nck - 1; j >= 0; --j) {
+        const int lo = j * k, hi = std::min(b->nt, (j + 1) * k);
+        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j, slot0 + 1, s));
+        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j + 1, slot0, s));
+        for (int i = 0; i < hi - lo; ++i) {
+            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, slot0 + i + 1,
+                                     slot0 + i, slot0 + i + 2, s));
+            FD_TRY(launch_batch_sparse(T, ns, 1, lo + i, slot0 + i + 2, hinv, s));
+        }
+        for (int n = hi - 1; n >= lo; --n) {
+            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, lam, lamo, lamo, s));
+            FD_TRY(launch_batch_sparse(T, ns, 2, n, lamo, hinv, s));
+            std::swap(lam, lamo);
+            const int i = n - lo;
+            FD_TRY(launch_batch_imaging(T, ns, b->max_pts, lam, slot0 + i + 2, slot0 + i + 1,
+                                        slot0 + i, inv_dt2, inv_2dt, s));
+        }
+    }
+    FD_TRY(launch_batch_reduce(T, ns, b->full, b->vel_full, grad_v, s));
+#undef FD_TRY
+    return FD_OK;
+}
+
+}  // namespace
+}  // namespace fd
+
+using namespace fd;
+
+extern "C" {
+
+int fd_batch_create(const fd_grid_desc *common, int nshots, const int64_t *shapes,
+                    const int64_t *origins, const int64_t *full_shape, int nt, int ckpt_every,
+                    fd_batch **out)
+{
+    if (!common || !shapes || !origins || !full_shape || !out || nshots < 1 || nshots > 1024 ||
+        nt < 1 || ckpt_every < 1)
+        return set_error(FD_EINVAL, "fd_batch_create: bad argument");
+    *out = nullptr;
+    const fd_grid_desc &d = *common;
+    if (d.space_order < 2 || d.space_order > 16 || d.space_order % 2)
+        return set_error(FD_EINVAL, "space_order must be even, 2..16");
+    if (!(d.dt > 0.0) || !(d.vmax > 0.0) || d.nbl < 0)
+        return set_error(FD_EINVAL, "dt, vmax must be > 0 and nbl >= 0");
+    double h[3];
+    for (int a = 0; a < 3; ++a) {
+        h[a] = d.spacing[a];
+        if (!(h[a] > 0.0)) return set_error(FD_EINVAL, "spacing must be > 0");
+        if (full_shape[a] < 1) return set_error(FD_EINVAL, "bad full shape");
+    }
+    const int r = d.space_order / 2;
+    fd_grid_desc dd = d;
+    dd.physics = FD_ACOUSTIC;
+    dd.boundary = FD_BC_ZERO;
+    dd.ndim = 3;
+    if (check_stability(dd, 3, h, r)) return FD_EUNSTABLE;
+
+    fd_batch *b = new fd_batch();
+    b->d = dd;
+    b->nshots = nshots;
+    b->nt = nt;
+    b->k = std::min(ckpt_every, nt);
+    b->nck = (nt + b->k - 1) / b->k;
+    b->nfields = kCkpt0 + 2 * b->nck + b->k + 2;
+    b->r = r;
+    for (int a = 0; a < 3; ++a) {
+        b->h[a] = h[a];
+        b->full[a] = full_shape[a];
+    }
+    b->sh.resize(nshots);
+    for (int i = 0; i < nshots; ++i) {
+        ShotHost &s = b->sh[i];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t n = shapes[3 * i + a], o = origins[3 * i + a];
+            if (n < std::max(2, r) || 2 * d.nbl > n || o < 0 || o + n > full_shape[a]) {
+                delete b;
+                return set_error(FD_EINVAL, "shot " + std::to_string(i) +
+                                                ": aperture outside the model or too small");
+            }
+            s.n[a] = (int)n;
+            s.org[a] = (int)o;
+        }
+        make_geometry(dd, 3, s.n, h, r, s.L, s.p);
+        b->max_stride = std::max<int64_t>(b->max_stride, s.L.field_elems);
+        b->max_pts = std::max<int64_t>(b->max_pts, (int64_t)s.n[0] * s.n[1] * s.n[2]);
+    }
+    layout_blocks(b);
+    DeviceGuard dg(d.device);
+    if (!dg.ok()) {
+        delete b;
+        return set_error(FD_EDEVICE, "cannot select device");
+    }
+    for (ShotHost &s : b->sh) {
+        const size_t bytes = s.L.field_bytes * (size_t)b->nfields;
+        if (hipMalloc(&s.ws, bytes) != hipSuccess) {
+            free_batch(b);
+            return set_error(FD_ENOMEM, "shot workspace allocation failed");
+        }
+        if (hipMemset(s.ws, 0, bytes) != hipSuccess) {
+            free_batch(b);
+            return set_error(FD_EDEVICE, "hipMemset failed");
+        }
+        b->bytes += bytes;
+    }
+    if (hipMalloc(&b->table, sizeof(BatchShot) * nshots) != hipSuccess ||
+        hipMalloc(&b->scratch, 256) != hipSuccess || hipStreamCreate(&b->cap) != hipSuccess) {
+        free_batch(b);
+        return set_error(FD_ENOMEM, "batch allocation failed");
+    }
+    *out = b;
+    return FD_OK;
+}
+
+void fd_batch_destroy(fd_batch *b)
+{
+    if (!b) return;
+    DeviceGuard dg(b->d.device);
+    free_batch(b);
+}
+
+size_t fd_batch_device_bytes(const fd_batch *b) { return b ? b->bytes : 0; }
+
+int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int xcd)
+{
+    if (!b) return set_error(FD_EINVAL, "fd_batch_set_tile: null handle");
+    const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
+                       (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
+    if (!known || nzb < 1) return set_error(FD_EINVAL, "unsupported tile shape");
+    DeviceGuard dg(b->d.device);
+    drop_graph(b);
+    b->tune = Tuning{by, ry, nzb, xcd ? 1 : 0};
+    layout_blocks(b);
+    return FD_OK;
+}
+
+int fd_batch_set_geometry(fd_batch *b, int shot, const double *src_m, int ns, const double *rec_m,
+                          int nr)
+{
+    if (!b || shot < 0 || shot >= b->nshots || ns < 0 || nr < 0 || (ns && !src_m) ||
+        (nr && !rec_m))
+        return set_error(FD_EINVAL, "fd_batch_set_geometry: bad argument");
+    ShotHost &s = b->sh[shot];
+    auto prep = [&](const double *c, int n, std::vector<int32_t> &bs, std::vector<float> &fr) {
+        bs.resize(3 * (size_t)n);
+        fr.resize(3 * (size_t)n);
+        for (int p = 0; p < n; ++p)
+            for (int a = 0; a < 3; ++a) {
+                const double x = c[3 * p + a] / b->h[a];
+                if (!(x >= 0.0) || x > (double)(s.n[a] - 1)) return false;
+                int64_t i = (int64_t)std::floor(x);
+                if (i > s.n[a] - 2) i = s.n[a] - 2;
+                bs[3 * p + a] = (int32_t)i;
+                fr[3 * p + a] = (float)(x - (double)i);
+            }
+        return true;
+    };
+    std::vector<int32_t> sb, rb;
+    std::vector<float> sf, rf;
+    if (!prep(src_m, ns, sb, sf) || !prep(rec_m, nr, rb, rf))
+        return set_error(FD_EINVAL, "shot " + std::to_string(shot) + ": sparse point outside aperture");
+    DeviceGuard dg(b->d.device);
+    drop_graph(b);
+    for (void *p : {(void *)s.sbase, (void *)s.sfrac, (void *)s.rbase, (void *)s.rfrac})
+        (void)hipFree(p);
+    s.sbase = s.rbase = nullptr;
+    s.sfrac = s.rfrac = nullptr;
+    auto up = [](void **dst, const void *src, size_t bytes) {
+        if (bytes == 0) return true;
+        return hipMalloc(dst, bytes) == hipSuccess &&
+               hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up((void **)&s.sbase, sb.data(), sb.size() * 4) ||
+        !up((void **)&s.sfrac, sf.data(), sf.size() * 4) ||
+        !up((void **)&s.rbase, rb.data(), rb.size() * 4) ||
+        !up((void **)&s.rfrac, rf.data(), rf.size() * 4))
+        return set_error(FD_ENOMEM, "geometry upload failed");
+    s.ns = ns;
+    s.nr = nr;
+    return FD_OK;
+}
+
+int fd_batch_set_model(fd_batch *b, const float *vel_full_dev, void *stream)
+{
+    if (!b || !vel_full_dev) return set_error(FD_EINVAL, "fd_batch_set_model: bad argument");
+    DeviceGuard dg(b->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    drop_graph(b);
+    int rc = upload_table(b, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    if (hipMemsetAsync(b->scratch, 0, sizeof(unsigned), s) != hipSuccess)
+        return set_error(FD_EDEVICE, "hipMemsetAsync failed");
+    if ((rc = launch_batch_vdt2(b->table, b->nshots, b->max_pts, b->full, vel_full_dev,
+                                (float)(b->d.dt * b->d.dt), b->scratch, s)))
+        return rc;
+    unsigned bits = 0;
+    if (hipMemcpyAsync(&bits, b->scratch, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error(FD_EDEVICE, "model check failed");
+    float vmax;
+    std::memcpy(&vmax, &bits, sizeof(float));
+    if (!(vmax <= (float)b->d.vmax * (1.0f + 1e-6f))) {
+        b->model_loaded = false;
+        return set_error(FD_EUNSTABLE, "velocity model exceeds vmax or is not positive");
+    }
+    b->vel_full = vel_full_dev;
+    b->model_loaded = true;
+    return FD_OK;
+}
+
+int fd_batch_gradient(fd_batch *b, const float *const *q_dev, const float *const *dobs_dev,
+                      float *const *d_dev, float *grad_v_dev, void *stream)
+{
+    if (!b || !q_dev || !dobs_dev || !d_dev || !grad_v_dev)
+        return set_error(FD_EINVAL, "fd_batch_gradient: bad argument");
+    if (!b->model_loaded) return set_error(FD_EINVAL, "fd_batch_gradient: no model loaded");
+    for (int i = 0; i < b->nshots; ++i) {
+        const ShotHost &s = b->sh[i];
+        if ((s.ns && !q_dev[i]) || (s.nr && (!dobs_dev[i] || !d_dev[i])))
+            return set_error(FD_EINVAL, "fd_batch_gradient: null per-shot pointer");
+    }
+    DeviceGuard dg(b->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<const void *> key;
+    for (int i = 0; i < b->nshots; ++i) {
+        key.push_back(q_dev[i]);
+        key.push_back(dobs_dev[i]);
+        key.push_back(d_dev[i]);
+    }
+    key.push_back(grad_v_dev);
+    key.push_back(b->vel_full);
+    if (!b->exec || key != b->key) {
+        if (hipStreamSynchronize(s) != hipSuccess) return set_error(FD_EDEVICE, "sync failed");
+        drop_graph(b);
+        int rc = upload_table(b, q_dev, dobs_dev, d_dev);
+        if (rc) return rc;
+        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return set_error(FD_EDEVICE, "graph capture failed to start");
+        rc = enqueue_schedule(b, grad_v_dev, b->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || !g) return set_error(FD_EDEVICE, "graph capture failed");
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(b);
+            return set_error(FD_EDEVICE, "graph instantiation failed");
+        }
+        b->key = key;
+    }
+    if (hipGraphLaunch(b->exec, s) != hipSuccess) return set_error(FD_EDEVICE, "graph launch failed");
+    return FD_OK;
+}
+
+}  // extern "C"

@@ -52,6 +52,28 @@ __device__ inline float damp_a(const StepParams &p, int z, int y, int x)
     return p.half_dt * g;
 }
 
+// Node (z, y, x) and multilinear weight of corner c of a sparse point's
+// cell; bit 2/1/0 of c selects the upper node along z/y/x (2-D: bits 1/0 for
+// z/x).
+__device__ inline void corner(const int ndim, const int32_t *base, const float *frac,
+                              const int c, int &z, int &y, int &x, float &w)
+{
+    if (ndim == 3) {
+        const int bz = (c >> 2) & 1, by = (c >> 1) & 1, bx = c & 1;
+        z = base[0] + bz;
+        y = base[1] + by;
+        x = base[2] + bx;
+        w = (bz ? frac[0] : 1.0f - frac[0]) * (by ? frac[1] : 1.0f - frac[1]) *
+            (bx ? frac[2] : 1.0f - frac[2]);
+    } else {
+        const int bz = (c >> 1) & 1, bx = c & 1;
+        z = base[0] + bz;
+        y = 0;
+        x = base[1] + bx;
+        w = (bz ? frac[0] : 1.0f - frac[0]) * (bx ? frac[1] : 1.0f - frac[1]);
+    }
+}
+
 // Tile choice for the z-marching 3-D kernel.
 struct Tuning {
     int by;        // waves per block (block = 64 x by threads)
@@ -92,6 +114,31 @@ struct fd_grid {
 };
 
 namespace fd {
+
+// Makes the handle's device current for the duration of a call.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev_ >= 0) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = -1;
+    bool ok_ = true;
+};
+
+// geometry shared by single grids and batched shots (fd_api.hip)
+void make_geometry(const fd_grid_desc &d, int ndim, const int n[3], const double h[3], int r,
+                   fd_layout &L, StepParams &p);
+// stability check of a descriptor (FD_OK or FD_EUNSTABLE with the message set)
+int check_stability(const fd_grid_desc &d, int ndim, const double h[3], int r);
 
 // error helpers (fd_api.hip)
 int set_error(int code, const std::string &msg);

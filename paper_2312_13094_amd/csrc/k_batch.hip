@@ -1,0 +1,283 @@
+// Batched multi-shot kernels: every launch covers all shots of a batch.
+//
+// k_batch_zmarch is a work list over (shot, tile): logical block b belongs
+// to the shot whose block range contains it, and runs the same z-marching
+// step body as the single-grid kernel on that shot's aperture.  Apertures
+// of different sizes therefore share one launch per time step.  Field
+// roles are passed as slot indices into each shot's workspace, so one
+// captured graph node serves all shots.  The remaining kernels put the
+// shot index on blockIdx.y.
+#include "batch_internal.h"
+#include "zmarch.h"
+
+namespace fd {
+
+template <int R, int BY, int RY>
+__global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__restrict__ shots,
+                                                          const int nshots, const int total,
+                                                          const int iu, const int ium,
+                                                          const int iup, const int nzb,
+                                                          const int remap)
+{
+    __shared__ float lds[ZTile<R, BY, RY>::LDS];
+    int b = blockIdx.x;
+    if (remap) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
+    if (b >= total) return;
+    int s = 0;
+    for (int k = 1; k < nshots; ++k)
+        if (shots[k].block0 <= b) s = k;
+    const BatchShot &S = shots[s];
+    int lb = b - S.block0;
+    const int tx = lb % S.ntx;
+    lb /= S.ntx;
+    const int ty = lb % S.nty;
+    const int zc = lb / S.nty;
+    float *base = S.base;
+    const int64_t st = S.stride;
+    zmarch_body<R, BY, RY>(base + iu * st, base + ium * st, base + iup * st, base + kVdt2 * st,
+                           S.p, tx, ty, zc, nzb, lds);
+}
+
+template <int R, int BY, int RY>
+static void batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+                       int ium, int iup, hipStream_t s)
+{
+    const int remap = t.xcd ? 1 : 0;
+    const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
+    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s, shots, nshots,
+                       total, iu, ium, iup, t.nzb, remap);
+}
+
+template <int R>
+static int batch_step_r(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+                        int ium, int iup, hipStream_t s)
+{
+    if (t.by == 4 && t.ry == 4) batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 2) batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 8) batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 8 && t.ry == 2) batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 8 && t.ry == 4) batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 2 && t.ry == 8) batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 1) batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, s);
+    else return set_error(FD_EINVAL, "unsupported tile shape");
+    return FD_OK;
+}
+
+int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, int r,
+                      const Tuning &t, int iu, int ium, int iup, hipStream_t s)
+{
+    int rc;
+    switch (r) {
+    case 1: rc = batch_step_r<1>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 2: rc = batch_step_r<2>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 3: rc = batch_step_r<3>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 4: rc = batch_step_r<4>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 5: rc = batch_step_r<5>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 6: rc = batch_step_r<6>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 7: rc = batch_step_r<7>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 8: rc = batch_step_r<8>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    default: return set_error(FD_EINVAL, "unsupported stencil radius");
+    }
+    if (rc) return rc;
+    return check_launch("batched step");
+}
+
+// One block per shot: injection (atomics), device fence + barrier, sampling.
+__global__ __launch_bounds__(256) void k_batch_sparse(const BatchShot *__restrict__ shots,
+                                                      const int mode, const int n, const int f,
+                                                      const float hinv)
+{
+    const BatchShot &S = shots[blockIdx.x];
+    const StepParams &p = S.p;
+    float *u = S.base + f * S.stride;
+    const float *vdt2 = S.base + kVdt2 * S.stride;
+    const int64_t PY = p.pitch_y, PZ = p.pitch_z;
+    // injection set: sources (modes 0, 1) or receivers (mode 2)
+    const bool rec_inj = mode == 2;
+    const int ni = rec_inj ? S.nr : S.ns;
+    const int32_t *ib = rec_inj ? S.rbase : S.sbase;
+    const float *ifr = rec_inj ? S.rfrac : S.sfrac;
+    const float scale = rec_inj ? 1.0f : hinv;
+    for (int e = threadIdx.x; e < ni * 8; e += blockDim.x) {
+        const int pt = e >> 3, c = e & 7;
+        int z, y, x;
+        float w;
+        corner(3, ib + pt * 3, ifr + pt * 3, c, z, y, x, w);
+        const float val = rec_inj ? S.d[(int64_t)n * S.nr + pt] - S.dobs[(int64_t)n * S.nr + pt]
+                                  : S.q[(int64_t)n * S.ns + pt];
+        const int64_t i = p.offset + (int64_t)z * PZ + (int64_t)y * PY + x;
+        const float a = damp_a(p, z, y, x);
+        atomicAdd(u + i, scale * w * val * vdt2[i] / (1.0f + a));
+    }
+    if (mode != 0) return;
+    __threadfence();
+    __syncthreads();
+    for (int pt = threadIdx.x; pt < S.nr; pt += blockDim.x) {
+        float acc = 0.0f;
+        for (int c = 0; c < 8; ++c) {
+            int z, y, x;
+            float w;
+            corner(3, S.rbase + pt * 3, S.rfrac + pt * 3, c, z, y, x, w);
+            acc += w * u[p.offset + (int64_t)z * PZ + (int64_t)y * PY + x];
+        }
+        S.d[(int64_t)n * S.nr + pt] = acc;
+    }
+}
+
+int launch_batch_sparse(const BatchShot *shots_dev, int nshots, int mode, int n, int f,
+                        float hinv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_sparse, dim3(nshots), dim3(256), 0, s, shots_dev, mode, n, f, hinv);
+    return check_launch("batched sparse");
+}
+
+__global__ __launch_bounds__(256) void k_batch_copy(const BatchShot *__restrict__ shots,
+                                                    const int fsrc, const int fdst)
+{
+    const BatchShot &S = shots[blockIdx.y];
+    const float4 *a = reinterpret_cast<const float4 *>(S.base + fsrc * S.stride);
+    float4 *b = reinterpret_cast<float4 *>(S.base + fdst * S.stride);
+    const int64_t n4 = S.stride / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+int launch_batch_copy(const BatchShot *shots_dev, int nshots, int64_t max_stride, int fsrc,
+                      int fdst, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((max_stride / 4 + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_batch_copy, dim3(nb, nshots), dim3(256), 0, s, shots_dev, fsrc, fdst);
+    return check_launch("batched copy");
+}
+
+__global__ __launch_bounds__(256) void k_batch_zero(const BatchShot *__restrict__ shots,
+                                                    const int f)
+{
+    const BatchShot &S = shots[blockIdx.y];
+    float4 *a = reinterpret_cast<float4 *>(S.base + f * S.stride);
+    const int64_t n4 = S.stride / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+int launch_batch_zero(const BatchShot *shots_dev, int nshots, int64_t max_stride, int f,
+                      hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((max_stride / 4 + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_batch_zero, dim3(nb, nshots), dim3(256), 0, s, shots_dev, f);
+    return check_launch("batched zero");
+}
+
+// g -= lambda * [((u+ - u) - (u - u-)) / dt^2 + gamma (u+ - u-) / (2 dt)]
+__global__ __launch_bounds__(256) void k_batch_imaging(const BatchShot *__restrict__ shots,
+                                                       const int flam, const int fup,
+                                                       const int fu, const int fum,
+                                                       const float inv_dt2, const float inv_2dt)
+{
+    const BatchShot &S = shots[blockIdx.y];
+    const StepParams &p = S.p;
+    const int64_t n = (int64_t)p.nz * p.ny * p.nx;
+    const float *lam = S.base + flam * S.stride, *up = S.base + fup * S.stride;
+    const float *u0 = S.base + fu * S.stride, *um = S.base + fum * S.stride;
+    float *g = S.base + kGrad * S.stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % p.nx);
+        const int64_t t = i / p.nx;
+        const int y = (int)(t % p.ny);
+        const int z = (int)(t / p.ny);
+        const int64_t j = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y + x;
+        float gam = 0.0f;
+        if (p.nbl > 0)
+            gam = sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) + sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) +
+                  sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy);
+        const float a = up[j], b = u0[j], c = um[j];
+        g[j] -= lam[j] * (((a - b) - (b - c)) * inv_dt2 + gam * (a - c) * inv_2dt);
+    }
+}
+
+int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_pts, int flam,
+                         int fup, int fu, int fum, float inv_dt2, float inv_2dt, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((max_pts + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_batch_imaging, dim3(nb, nshots), dim3(256), 0, s, shots_dev, flam, fup,
+                       fu, fum, inv_dt2, inv_2dt);
+    return check_launch("batched imaging");
+}
+
+// Full-model gradient: for each point, add the shots covering it in shot
+// order, then apply dJ/dv = dJ/dm * (-2 / v^3).
+__global__ __launch_bounds__(256) void k_batch_reduce(const BatchShot *__restrict__ shots,
+                                                      const int nshots, const int64_t fz,
+                                                      const int64_t fy, const int64_t fx,
+                                                      const float *__restrict__ vel,
+                                                      float *__restrict__ gv)
+{
+    const int64_t n = fz * fy * fx;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % fx);
+        const int64_t t = i / fx;
+        const int y = (int)(t % fy);
+        const int z = (int)(t / fy);
+        float acc = 0.0f;
+        for (int s = 0; s < nshots; ++s) {
+            const BatchShot &S = shots[s];
+            const int lz = z - S.org[0], ly = y - S.org[1], lx = x - S.org[2];
+            if (lz >= 0 && lz < S.p.nz && ly >= 0 && ly < S.p.ny && lx >= 0 && lx < S.p.nx)
+                acc += S.base[kGrad * S.stride + S.p.offset + (int64_t)lz * S.p.pitch_z +
+                              (int64_t)ly * S.p.pitch_y + lx];
+        }
+        const float v = vel[i];
+        gv[i] = acc * (-2.0f / (v * v * v));
+    }
+}
+
+int launch_batch_reduce(const BatchShot *shots_dev, int nshots, const int64_t full[3],
+                        const float *vel_full, float *grad_v, hipStream_t s)
+{
+    const int64_t n = full[0] * full[1] * full[2];
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_batch_reduce, dim3(nb), dim3(256), 0, s, shots_dev, nshots, full[0],
+                       full[1], full[2], vel_full, grad_v);
+    return check_launch("batched gradient reduction");
+}
+
+// v^2 dt^2 of each aperture, cut from the full model
+__global__ __launch_bounds__(256) void k_batch_vdt2(const BatchShot *__restrict__ shots,
+                                                    const int64_t fy, const int64_t fx,
+                                                    const float *__restrict__ vel,
+                                                    const float dt2, unsigned *vmax_bits)
+{
+    const BatchShot &S = shots[blockIdx.y];
+    const StepParams &p = S.p;
+    const int64_t n = (int64_t)p.nz * p.ny * p.nx;
+    float *vd = S.base + kVdt2 * S.stride;
+    unsigned mx = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % p.nx);
+        const int64_t t = i / p.nx;
+        const int y = (int)(t % p.ny);
+        const int z = (int)(t / p.ny);
+        const float v = vel[((int64_t)(z + S.org[0]) * fy + (y + S.org[1])) * fx + (x + S.org[2])];
+        vd[p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y + x] = v * v * dt2;
+        const unsigned bits = (v > 0.0f) ? __float_as_uint(v) : 0x7f800000u;
+        mx = bits > mx ? bits : mx;
+    }
+    atomicMax(vmax_bits, mx);
+}
+
+int launch_batch_vdt2(const BatchShot *shots_dev, int nshots, int64_t max_pts,
+                      const int64_t full[3], const float *vel_full, float dt2,
+                      unsigned *vmax_bits, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((max_pts + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_batch_vdt2, dim3(nb, nshots), dim3(256), 0, s, shots_dev, full[1],
+                       full[2], vel_full, dt2, vmax_bits);
+    return check_launch("batched model");
+}
+
+}  // namespace fd

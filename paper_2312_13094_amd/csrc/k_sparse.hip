@@ -14,25 +14,6 @@
 
 namespace fd {
 
-__device__ inline void corner(const int ndim, const int32_t *base, const float *frac,
-                              const int c, int &z, int &y, int &x, float &w)
-{
-    if (ndim == 3) {
-        const int bz = (c >> 2) & 1, by = (c >> 1) & 1, bx = c & 1;
-        z = base[0] + bz;
-        y = base[1] + by;
-        x = base[2] + bx;
-        w = (bz ? frac[0] : 1.0f - frac[0]) * (by ? frac[1] : 1.0f - frac[1]) *
-            (bx ? frac[2] : 1.0f - frac[2]);
-    } else {
-        const int bz = (c >> 1) & 1, bx = c & 1;
-        z = base[0] + bz;
-        y = 0;
-        x = base[1] + bx;
-        w = (bz ? frac[0] : 1.0f - frac[0]) * (bx ? frac[1] : 1.0f - frac[1]);
-    }
-}
-
 __global__ __launch_bounds__(256) void k_sparse(float *u, const float *__restrict__ vdt2,
                                                 const StepParams p, const int ndim,
                                                 const SparseArgs inj, const SparseArgs smp)

@@ -1,0 +1,169 @@
+// The z-marching body of the 3-D acoustic step, shared by the single-grid
+// kernel (k_acoustic.hip) and the batched multi-shot kernel (k_batch.hip).
+//
+// A block of 64 x BY threads owns a 64 x (BY*RY) column tile and marches
+// along z over one chunk of nzb planes.  Each thread keeps the 2R+1 z values
+// of its RY columns in registers (a queue shifted once per plane), so every
+// u value enters the chip once per chunk; the current plane plus an R-wide
+// x/y ring is staged in LDS, double buffered (one barrier per plane).  Loads
+// for plane z+1 are issued before plane z is computed.
+#pragma once
+
+#include "fd_internal.h"
+
+namespace fd {
+
+template <int R, int BY, int RY>
+struct ZTile {
+    static constexpr int TX = 64, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
+    static constexpr int LDS = 2 * LY * LX;   // floats, double buffered
+};
+
+// One block's z-march over tile (tx, ty) and z chunk zc of a grid described
+// by p; u -> up with up possibly aliasing um (in place).  `lds` holds
+// ZTile<R,BY,RY>::LDS floats.
+template <int R, int BY, int RY>
+__device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const float *um,
+                                            float *up, const float *__restrict__ vdt2,
+                                            const StepParams &p, const int tx, const int ty,
+                                            const int zc, const int nzb, float *lds)
+{
+    constexpr int TX = 64, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
+    constexpr int NT = 64 * BY;
+    constexpr int NHY = 2 * R * TX;   // y-halo values per plane
+    constexpr int NHX = 2 * R * TY;   // x-halo values per plane
+    constexpr int HY = (NHY + NT - 1) / NT;
+    constexpr int HX = (NHX + NT - 1) / NT;
+    const int lane = threadIdx.x, wy = threadIdx.y;
+    const int tid = wy * 64 + lane;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int x = x0 + lane;
+    const int yb = y0 + wy * RY;
+    const int z0 = zc * nzb;
+    const int z1 = min(z0 + nzb, p.nz);
+    const int64_t PY = p.pitch_y, PZ = p.pitch_z;
+    const float *uo = u + p.offset;      // DOMAIN origin of u
+    const float *umo = um + p.offset;
+    const float *vo = vdt2 + p.offset;
+    float *upo = up + p.offset;
+
+    // which of this thread's rows are loadable (inside DOMAIN + halo) and
+    // which are written (inside DOMAIN)
+    const bool xl = x < p.nx + R;
+    bool rl[RY], ro[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        rl[j] = xl && (yb + j) < p.ny + R;
+        ro[j] = x < p.nx && (yb + j) < p.ny;
+    }
+
+    // halo descriptors, fixed over z: element offset within a plane, LDS slot
+    int64_t hyo[HY], hxo[HX];
+    int hys[HY], hxs[HX];
+    bool hyk[HY], hxk[HX];
+#pragma unroll
+    for (int k = 0; k < HY; ++k) {
+        const int e = tid + k * NT;
+        const int row = e / TX, col = e % TX;
+        const int yy = row < R ? y0 - R + row : y0 + TY + (row - R);
+        const int ly = row < R ? row : TY + row;
+        const int xx = x0 + col;
+        hyk[k] = e < NHY && yy < p.ny + R && xx < p.nx + R;
+        hyo[k] = (int64_t)yy * PY + xx;
+        hys[k] = ly * LX + col + R;
+    }
+#pragma unroll
+    for (int k = 0; k < HX; ++k) {
+        const int e = tid + k * NT;
+        const int row = e / (2 * R), c = e % (2 * R);
+        const int yy = y0 + row;
+        const int xx = c < R ? x0 - R + c : x0 + TX + (c - R);
+        const int lx = c < R ? c : TX + c;
+        hxk[k] = e < NHX && yy < p.ny + R && xx < p.nx + R;
+        hxo[k] = (int64_t)yy * PY + xx;
+        hxs[k] = (row + R) * LX + lx;
+    }
+
+    // z queue: q[j][k] = u(z - R + k, yb + j, x)
+    float q[RY][2 * R + 1];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int64_t col = (int64_t)(yb + j) * PY + x;
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k)
+            q[j][k + 1] = rl[j] ? uo[(int64_t)(z0 - R + k) * PZ + col] : 0.0f;
+    }
+
+    // prefetch registers for the next plane
+    float nf[RY], nm[RY], nv[RY], nhy[HY], nhx[HX];
+    auto prefetch = [&](int z) {
+        const int64_t pz = (int64_t)z * PZ;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int64_t col = (int64_t)(yb + j) * PY + x;
+            nf[j] = rl[j] ? uo[pz + R * PZ + col] : 0.0f;
+            nm[j] = ro[j] ? umo[pz + col] : 0.0f;
+            nv[j] = ro[j] ? vo[pz + col] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < HY; ++k) nhy[k] = hyk[k] ? uo[pz + hyo[k]] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < HX; ++k) nhx[k] = hxk[k] ? uo[pz + hxo[k]] : 0.0f;
+    };
+    if (z0 < z1) prefetch(z0);
+
+    for (int z = z0; z < z1; ++z) {
+        float cm[RY], cv[RY], chy[HY], chx[HX];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) q[j][k] = q[j][k + 1];
+            q[j][2 * R] = nf[j];
+            cm[j] = nm[j];
+            cv[j] = nv[j];
+        }
+#pragma unroll
+        for (int k = 0; k < HY; ++k) chy[k] = nhy[k];
+#pragma unroll
+        for (int k = 0; k < HX; ++k) chx[k] = nhx[k];
+        if (z + 1 < z1) prefetch(z + 1);
+
+        float *t = lds + (z & 1) * (LY * LX);
+#pragma unroll
+        for (int j = 0; j < RY; ++j) t[(wy * RY + j + R) * LX + lane + R] = q[j][R];
+#pragma unroll
+        for (int k = 0; k < HY; ++k)
+            if (tid + k * NT < NHY) t[hys[k]] = chy[k];
+#pragma unroll
+        for (int k = 0; k < HX; ++k)
+            if (tid + k * NT < NHX) t[hxs[k]] = chx[k];
+        __syncthreads();
+
+        const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
+        const float ax = p.nbl > 0 ? sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const float *c = t + (wy * RY + j + R) * LX + lane + R;
+            float lz = 0.0f, ly = 0.0f, lx = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                lz += p.cz[k] * (q[j][R + k] + q[j][R - k]);
+                ly += p.cy[k] * (c[k * LX] + c[-k * LX]);
+                lx += p.cx[k] * (c[k] + c[-k]);
+            }
+            const float uc = q[j][R];
+            const float lap = p.c0 * uc + lz + ly + lx;
+            const int y = yb + j;
+            // same summation order as damp_a(): (z + x) + y
+            const float ay = p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
+            const float a = p.half_dt * ((az + ax) + ay);
+            if (ro[j])
+                upo[(int64_t)z * PZ + (int64_t)y * PY + x] =
+                    (2.0f * uc - (1.0f - a) * cm[j] + cv[j] * lap) / (1.0f + a);
+        }
+    }
+}
+
+
+
+}  // namespace fd

@@ -245,3 +245,83 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Batched multi-shot gradient (``fd_batch``): uneven apertures advanced
+    together, the whole schedule replayed as one graph launch."""
+
+    def __init__(self, spacing, so, dt, vmax, nbl, shapes, origins, full_shape, nt, ckpt_every,
+                 device=0):
+        L = lib()
+        _bind_batch(L)
+        d = GridDesc()
+        d.ndim = 3
+        for k in range(3):
+            d.spacing[k] = float(spacing[k])
+        d.space_order, d.nbl, d.dt, d.vmax, d.device = so, nbl, dt, vmax, device
+        self.nshots = len(shapes)
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.origins = [tuple(int(v) for v in o) for o in origins]
+        self.full_shape = tuple(int(v) for v in full_shape)
+        self.nt, self.device = nt, device
+        sh = (ctypes.c_int64 * (3 * self.nshots))(*[v for s in self.shapes for v in s])
+        og = (ctypes.c_int64 * (3 * self.nshots))(*[v for o in self.origins for v in o])
+        fs = (ctypes.c_int64 * 3)(*self.full_shape)
+        h = ctypes.c_void_p()
+        _check(L.fd_batch_create(ctypes.byref(d), self.nshots, sh, og, fs, int(nt),
+                                 int(ckpt_every), ctypes.byref(h)))
+        self.handle = h
+        self.nrec = [0] * self.nshots
+
+    @property
+    def device_bytes(self):
+        return int(lib().fd_batch_device_bytes(self.handle))
+
+    def set_tile(self, by, ry, nzb, xcd=1):
+        _check(lib().fd_batch_set_tile(self.handle, by, ry, nzb, xcd))
+
+    def set_geometry(self, shot, src, rec):
+        src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+        rec = np.ascontiguousarray(rec, dtype=np.float64).reshape(-1, 3)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().fd_batch_set_geometry(self.handle, shot, src.ctypes.data_as(dp), src.shape[0],
+                                           rec.ctypes.data_as(dp), rec.shape[0]))
+        self.nrec[shot] = rec.shape[0]
+
+    def set_model(self, vel_full):
+        self._vel = vel_full
+        _check(lib().fd_batch_set_model(self.handle, _ptr(vel_full), _stream(self.device)))
+
+    def gradient(self, q, dobs, d, grad_v):
+        _check(lib().fd_batch_gradient(self.handle, _ptr_array(q), _ptr_array(dobs), _ptr_array(d),
+                                       _ptr(grad_v), _stream(self.device)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bind_batch(L):
+    if getattr(L, "_batch_bound", False):
+        return
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    P = ctypes.POINTER
+    L.fd_batch_create.argtypes = [P(GridDesc), i, P(ctypes.c_int64), P(ctypes.c_int64),
+                                  P(ctypes.c_int64), i, i, P(vp)]
+    L.fd_batch_destroy.argtypes = [vp]
+    L.fd_batch_destroy.restype = None
+    L.fd_batch_device_bytes.argtypes = [vp]
+    L.fd_batch_device_bytes.restype = ctypes.c_size_t
+    L.fd_batch_set_tile.argtypes = [vp, i, i, i, i]
+    L.fd_batch_set_geometry.argtypes = [vp, i, P(ctypes.c_double), i, P(ctypes.c_double), i]
+    L.fd_batch_set_model.argtypes = [vp, vp, vp]
+    L.fd_batch_gradient.argtypes = [vp, P(vp), P(vp), P(vp), vp, vp]
+    L._batch_bound = True

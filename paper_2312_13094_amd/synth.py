@@ -217,3 +217,70 @@ def cfg_tti(n: int = 384, nt: int = 500, seed: int = 3, so: int = 12, nbl: int =
     q = ricker(nt, dt, 20.0)[:, None]
     return TTI("tti3d_%dcube_so%d" % (n, so), shape, (h, h, h), so, nbl, dt, nt, vmax, eps_max,
                src, rec, q, fields=f)
+
+
+@dataclass
+class FWIBatch:
+    """Batched-gradient workload: a full model (layered + Gaussian anomaly),
+    its layered starting model, and per-shot apertures with acquisition."""
+    name: str
+    full_shape: tuple
+    spacing: tuple
+    so: int
+    nbl: int
+    dt: float
+    nt: int
+    ckpt_every: int
+    vmax: float
+    shapes: list
+    origins: list
+    src: list          # per shot [1][3] metres in aperture coordinates
+    rec: list          # per shot [nr][3]
+    q: np.ndarray      # [nt][1]
+    profile: np.ndarray = field(default=None, repr=False)
+    anomaly: tuple = (0.6, 0.5, 0.5, 12.0, 300.0)   # centre fractions (z,y,x), sigma cells, dv
+
+    def true_velocity(self) -> np.ndarray:
+        v = self.start_velocity().astype(np.float64)
+        fz, fy, fx, sig, dv = self.anomaly
+        nz, ny, nx = self.full_shape
+        z = (np.arange(nz) - fz * nz)[:, None, None]
+        y = (np.arange(ny) - fy * ny)[None, :, None]
+        x = (np.arange(nx) - fx * nx)[None, None, :]
+        v += dv * np.exp(-(z * z + y * y + x * x) / (2 * sig * sig))
+        return np.minimum(v, self.vmax).astype(np.float32)
+
+    def start_velocity(self) -> np.ndarray:
+        p = self.profile.reshape(-1, 1, 1)
+        return np.ascontiguousarray(np.broadcast_to(p, self.full_shape)).astype(np.float32)
+
+
+def cfg_fwi_batch(n: int = 512, nshots: int = 16, side_lo: int = 24, side_hi: int = 40,
+                  unit: int = 8, nt: int = 800, ckpt_every: int = 50, seed: int = 4,
+                  so: int = 8, nbl: int = 40, sigma: float = 12.0) -> FWIBatch:
+    """16 shots (seeds 4000+i) with cube apertures of side unit * U{side_lo..side_hi}
+    (192..320 at the defaults), placed uniformly inside an n^3 layered model
+    (seed 4) with a +300 m/s Gaussian anomaly (sigma 12 cells) at
+    (0.6 nz, ny/2, nx/2); source 44 cells deep at the aperture centre,
+    receivers 42 cells deep along x; so 8, 800 steps, checkpoint every 50."""
+    h = 10.0
+    prof = layered_profile(n, seed)
+    vmax = 4500.0
+    dt = stable_dt(so, 3, h, vmax)
+    shapes, origins, srcs, recs = [], [], [], []
+    for i in range(nshots):
+        rng = np.random.default_rng(4000 + i)
+        s = unit * int(rng.integers(side_lo, side_hi + 1))
+        s = min(s, n)
+        o = [int(rng.integers(0, n - s + 1)) for _ in range(3)]
+        shapes.append((s, s, s))
+        origins.append(tuple(o))
+        zs = min(44, s - 2)
+        zr = min(42, s - 2)
+        c = (s // 2) * h
+        srcs.append(np.array([[zs * h, c, c]]))
+        recs.append(np.array([[zr * h, c, x * h] for x in range(s)]))
+    q = ricker(nt, dt, 15.0)[:, None]
+    return FWIBatch("fwi_batch_%dshots_%dcube" % (nshots, n), (n, n, n), (h, h, h), so, nbl, dt,
+                    nt, ckpt_every, vmax, shapes, origins, srcs, recs, q, profile=prof,
+                    anomaly=(0.6, 0.5, 0.5, sigma, 300.0))

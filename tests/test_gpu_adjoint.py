@@ -157,3 +157,25 @@ def test_gradient_requires_checkpoints():
     with pytest.raises(FD.FdError):
         g.adjoint([g.field(), g.field()], R, r, S, None, None, 10, grad_m=gm)
     g.close()
+
+
+def test_autograd_function_returns_velocity_gradient():
+    """FWIGradient (torch.autograd.Function over fd_forward / fd_adjoint) gives
+    dJ/dv of J = 1/2 |d - d_obs|^2 matching the FP64 oracle's."""
+    import torch
+    from paper_2312_13094_amd.fwi import ShotProblem, fwi_gradient
+    rng, c = _setup((28, 30, 64), 8, 5, 0, 26, nsrc=1, nrec=30, vlo=1800.0, vhi=2600.0)
+    nt = 60
+    q = (synth.ricker(nt, c["dt"], 20.0)[:, None] * 1e3).astype(np.float32)
+    og = O.Grid(c["shape"], c["spacing"], so=8, dt=c["dt"], nbl=5, vmax=c["vmax"], bc=0)
+    v64 = c["v"].astype(np.float64)
+    _, _, dobs, _ = O.forward(og, v64 * 1.02, c["src"], q.astype(np.float64), c["rec"], nt)
+    _, _, od, hist = O.forward(og, v64, c["src"], q.astype(np.float64), c["rec"], nt, history=True)
+    _, _, _, ogm = O.adjoint(og, v64, c["rec"], od - dobs, c["src"], nt, hist=hist)
+    ogv = ogm * (-2.0 / v64 ** 3)
+    pb = ShotProblem(c["shape"], c["spacing"], 8, c["dt"], c["vmax"], 5, nt, c["src"], c["rec"], q,
+                     ckpt_every=11)
+    J, gv = fwi_gradient(to_dev(c["v"]), pb, to_dev(dobs.astype(np.float32)))
+    torch.cuda.synchronize()
+    assert abs(J.item() - 0.5 * np.sum((od - dobs) ** 2)) <= 1e-3 * 0.5 * np.sum((od - dobs) ** 2)
+    assert rel_l2(gv.double().cpu().numpy(), ogv) <= 2e-3
