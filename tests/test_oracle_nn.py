@@ -1,0 +1,97 @@
+"""Pins of the network oracle: library cross-correlation, finite differences,
+closed-form GELU values, the first Adam step, BF16 rounding."""
+import math
+
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import nn as N
+
+
+def test_conv3d_is_library_correlation():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, 5, 6, 7))
+    w = rng.standard_normal((4, 3, 3, 3, 3))
+    b = rng.standard_normal(4)
+    y = N.conv3d(x, w, b)
+    for co in range(4):
+        ref = sum(signal.correlate(x[ci], w[co, ci], mode="same") for ci in range(3)) + b[co]
+        np.testing.assert_allclose(y[co], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_conv3d_dgrad_wgrad_finite_differences():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 4, 3, 5))
+    w = rng.standard_normal((3, 2, 3, 3, 3))
+    b = rng.standard_normal(3)
+    gy = rng.standard_normal((3, 4, 3, 5))
+    f = lambda xx, ww, bb: np.sum(gy * N.conv3d(xx, ww, bb))
+    gx = N.conv3d_dgrad(gy, w)
+    gw, gb = N.conv3d_wgrad(x, gy)
+    eps = 1e-6
+    for idx in [(0, 1, 2, 3), (1, 0, 0, 0), (1, 3, 2, 4)]:
+        d = np.zeros_like(x)
+        d[idx] = eps
+        fd = (f(x + d, w, b) - f(x - d, w, b)) / (2 * eps)
+        assert abs(fd - gx[idx]) <= 1e-6 * max(1, abs(fd))
+    for idx in [(0, 1, 0, 2, 1), (2, 0, 1, 1, 1), (1, 1, 2, 0, 2)]:
+        d = np.zeros_like(w)
+        d[idx] = eps
+        fd = (f(x, w + d, b) - f(x, w - d, b)) / (2 * eps)
+        assert abs(fd - gw[idx]) <= 1e-6 * max(1, abs(fd))
+    np.testing.assert_allclose(gb, gy.sum(axis=(1, 2, 3)))
+
+
+def test_gelu_values_and_derivative():
+    # GELU(0) = 0, GELU(x) -> x for large x, GELU(-x) = GELU(x) - x
+    assert N.gelu(np.array(0.0)) == 0.0
+    assert abs(N.gelu(np.array(8.0)) - 8.0) < 1e-12
+    x = np.linspace(-4, 4, 33)
+    np.testing.assert_allclose(N.gelu(-x), N.gelu(x) - x, atol=1e-14)
+    # Phi(1) = 0.8413447460685429 (standard normal table)
+    assert abs(N.gelu(np.array(1.0)) - 0.8413447460685429) < 1e-15
+    h = 1e-6
+    np.testing.assert_allclose(N.gelu_grad(x), (N.gelu(x + h) - N.gelu(x - h)) / (2 * h),
+                               rtol=1e-7, atol=1e-9)
+
+
+def test_network_gradients_finite_differences():
+    rng = np.random.default_rng(2)
+    shapes = [(16, 3, 3, 3, 3), (16,), (16, 16, 3, 3, 3), (16,), (1, 16, 3, 3, 3), (1,)]
+    p = [rng.standard_normal(s) * 0.2 for s in shapes]
+    net = N.Net(*p)
+    x = rng.standard_normal((3, 4, 4, 3))
+    t = rng.standard_normal((1, 4, 4, 3))
+    loss, grads = net.loss_and_grads(x, t)
+    eps = 1e-6
+    for k, idx in [(0, (3, 1, 0, 2, 1)), (1, (5,)), (2, (7, 9, 1, 1, 0)), (3, (15,)),
+                   (4, (0, 4, 2, 2, 2)), (5, (0,))]:
+        pp = [a.copy() for a in p]
+        pm = [a.copy() for a in p]
+        pp[k][idx] += eps
+        pm[k][idx] -= eps
+        fd = (N.Net(*pp).loss_and_grads(x, t)[0] - N.Net(*pm).loss_and_grads(x, t)[0]) / (2 * eps)
+        assert abs(fd - grads[k][idx]) <= 1e-6 * max(1e-3, abs(fd)), (k, fd, grads[k][idx])
+
+
+def test_adam_first_step_is_signed_lr():
+    """With m0 = v0 = 0, the bias-corrected first update is -lr * g/(|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = N.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-12)
+    np.testing.assert_allclose(p, -0.01 * np.sign(g), rtol=1e-8)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_bf16_rounding():
+    a = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -3.1415926, 65504.0, 1e-40],
+                 dtype=np.float32)
+    r = N.bf16_round(a)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                      # tie -> even
+    assert r[2] == 1.0 + 2 ** -7            # above the tie -> up
+    assert abs(r[3] + 3.140625) < 1e-12
+    assert r[4] == 65536.0
+    # representable bf16 values are fixed points
+    np.testing.assert_array_equal(N.bf16_round(r.astype(np.float32)), r)
