@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--tile", type=str, default="", help="by,ry,nzb,xcd override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 2 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -96,6 +98,12 @@ def main():
     from paper_2312_13094_amd import fd, synth
 
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)   # 2 GiB read, 2 GiB write
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     c = synth.cfg_3d_layered(n=args.n, nt=args.nt)
     g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, boundary=c.boundary)
     if args.tile:

@@ -93,8 +93,9 @@ __global__ __launch_bounds__(256) void k_tti_pass2(
     const float a = damp_a(sp, z, y, x);
     const float inv = 1.0f / (1.0f + a);
     const float cc = c[i], cp = cpp[i], cxx = cx[i];
-    const float pn = (2.0f * p[i] - (1.0f - a) * pm[i] + cp * h1 + cxx * h2) * inv;
-    const float rn = (2.0f * r[i] - (1.0f - a) * rm[i] + cxx * h1 + cc * h2) * inv;
+    const float pc = p[i], rc = r[i];
+    const float pn = pc + ((1.0f - a) * (pc - pm[i]) + cp * h1 + cxx * h2) * inv;
+    const float rn = rc + ((1.0f - a) * (rc - rm[i]) + cxx * h1 + cc * h2) * inv;
     pp[i] = pn;
     rp[i] = rn;
 }

@@ -159,7 +159,7 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
             const float a = p.half_dt * ((az + ax) + ay);
             if (ro[j])
                 upo[(int64_t)z * PZ + (int64_t)y * PY + x] =
-                    (2.0f * uc - (1.0f - a) * cm[j] + cv[j] * lap) / (1.0f + a);
+                    uc + ((1.0f - a) * (uc - cm[j]) + cv[j] * lap) / (1.0f + a);
         }
     }
 }

@@ -234,7 +234,10 @@ def _symbol(w, theta):
 def test_headline_512_plane_wave_500_steps():
     """512^3, so 8, loopback (periodic) halos every step, 500 steps: the
     discrete plane wave cos(k.x - w t) with sin^2(w dt/2) = -(v dt)^2/4 sum
-    sigma(k_a h)/h^2 is exact; FP32 stays within 1e-4 relative L2."""
+    sigma(k_a h)/h^2 is exact; FP32 stays within 1e-4 relative L2.  The
+    wavenumber sits in the workload's band (about 15 Hz at 3 km/s): FP32
+    rounding in a leapfrog grows like sqrt(steps) eps / (w dt), so a far
+    lower-frequency mode would measure that growth rather than the kernels."""
     import torch
     FD = _fd()
     n, so, h, v, nt = 512, 8, 10.0, 3000.0, 500
@@ -242,7 +245,7 @@ def test_headline_512_plane_wave_500_steps():
     g = FD.Grid((n, n, n), (h,) * 3, so, dt, 4500.0, nbl=0, boundary=FD.FD_BC_LOOPBACK)
     g.set_model(torch.full((n, n, n), v, dtype=torch.float32, device="cuda"))
     w = O.d2_weights(so)  # FP64 weights, pinned by the oracle tests
-    m = (5, 3, 7)
+    m = (15, 12, 17)
     k = [2 * math.pi * mi / (n * h) for mi in m]
     s2 = -(v * dt) ** 2 / 4 * sum(_symbol(w, kk * h) / h ** 2 for kk in k)
     om = 2 * math.asin(math.sqrt(s2)) / dt
