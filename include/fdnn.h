@@ -1,0 +1,105 @@
+/*
+ * fdnn.h -- C ABI of the learned coarse-grid correction network (part of
+ * libfd.so; not in the paper: it corrects a 2x-coarser low-order propagation
+ * of the acoustic equation of the appendix "Isotropic acoustic" toward the
+ * fine high-order one).
+ *
+ * Network: conv3x3x3(3->16) - GELU - conv3x3x3(16->16) - GELU -
+ * conv3x3x3(16->1), cross-correlation with zero "same" padding, GELU in the
+ * erf form.  BF16 weights and activations, FP32 accumulation on MFMA
+ * (v_mfma_f32_16x16x32_bf16), FP32 master weights and Adam moments.
+ *
+ * Conventions as fd.h (status codes, fd_last_error, caller-owned device
+ * memory, asynchronous on `stream`, no allocation in any call).
+ *
+ * Layouts:
+ *   params  FP32, nn_param_count() values: w1[16][3][27], b1[16],
+ *           w2[16][16][27], b2[16], w3[1][16][27], b3[1]; the tap index is
+ *           dz*9 + dy*3 + dx (the kernel's offset along z, y, x, each 0..2).
+ *   packed  nn_packed_bytes() bytes: BF16 MFMA fragments of every layer
+ *           (forward and data-gradient), rebuilt by nn_pack_weights.
+ *   act8 / act16  channels-last BF16 (uint16 bit patterns) [nz][ny][nx][C],
+ *           C = 8 or 16 (unused channels are zero).
+ *   FP32 fields are addressed through an nn_view: element (z, y, x) at
+ *           offset + z*pitch_z + y*pitch_y + x (a dense array, or a libfd
+ *           padded field with its fd_layout).
+ */
+#ifndef FDNN_H
+#define FDNN_H
+
+#include <stdint.h>
+
+#include "fd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int64_t offset, pitch_y, pitch_z;
+} nn_view;
+
+int64_t nn_param_count(void);
+int64_t nn_packed_bytes(void);
+
+/* Bytes of the workspace nn_wgrad needs for a volume of nz*ny*nx points. */
+int64_t nn_wgrad_workspace_bytes(int nz, int ny, int nx);
+
+/* params (FP32) -> packed BF16 fragments (round to nearest even). */
+int nn_pack_weights(const float *params_dev, void *packed_dev, void *stream);
+
+/* x[p] = (a[p] * sa, b[p] * sb, c[p], 0, 0, 0, 0, 0) as BF16, with
+ * sa = sb = 1 / scale_dev[0] if scale_dev is non-NULL (else 1). */
+int nn_pack_input(int nz, int ny, int nx, const float *a, nn_view va, const float *b,
+                  nn_view vb, const float *c, nn_view vc, const float *scale_dev, void *x8_dev,
+                  void *stream);
+
+/* scale_dev[0] = sqrt(mean(u^2)) + 1e-30 over the volume; flag_dev[0] (may
+ * be NULL) is set to 1 if any value is not finite, left unchanged otherwise.
+ * scale_dev must hold nn_rms_scratch_floats() floats, 8-byte aligned (the
+ * rest is scratch for per-block partial sums, reduced in a fixed order). */
+int nn_rms(int nz, int ny, int nx, const float *u, nn_view vu, float *scale_dev,
+           unsigned *flag_dev, void *stream);
+int64_t nn_rms_scratch_floats(void);
+
+/* Forward layer 1 or 2: act16 = GELU(conv(x) + b); z16 (pre-activation,
+ * may be NULL) is kept for training.  layer 1 reads act8, layer 2 act16. */
+int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const void *packed_dev,
+                 const float *params_dev, void *z16_dev, void *a16_dev, void *stream);
+
+/* Forward layer 3 (16 -> 1): y = conv(a16) + b3.  If y_dense_dev is
+ * non-NULL it receives y (dense [nz][ny][nx]); if out_dev is non-NULL,
+ * out[vout] = base[vbase] + s * y with s = scale_dev[0] (or 1 if NULL). */
+int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_dev,
+                const float *params_dev, float *y_dense_dev, const float *base_dev,
+                nn_view vbase, float *out_dev, nn_view vout, const float *scale_dev,
+                void *stream);
+
+/* MSE over the volume: loss_dev[0] += mean((y - t)^2) (float atomics),
+ * gy8[p] = (2 (y - t) / N, 0, ..., 0) as BF16. */
+int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev, void *gy8_dev,
+           float *loss_dev, void *stream);
+
+/* Data gradient through layer 3 (gin = gy8) or layer 2 (gin = gz16),
+ * multiplied by GELU'(z) of the previous layer: gz_out16 = (W^T * gin) .
+ * GELU'(z16_prev). */
+int nn_dgrad_gelu(int layer, int nz, int ny, int nx, const void *gin_dev,
+                  const void *packed_dev, const void *z16_prev_dev, void *gz_out16_dev,
+                  void *stream);
+
+/* Weight and bias gradient of layer 1, 2 or 3 (overwrites the layer's
+ * slice of grads_dev, same layout as params): x = act8 (layer 1) or act16,
+ * g = gz16 (layers 1, 2) or gy8 (layer 3).  Per-block partial sums in
+ * workspace, then an ordered reduction (deterministic). */
+int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
+             void *workspace_dev, float *grads_dev, void *stream);
+
+/* Adam on all parameters (t is the 1-based step). */
+int nn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int t,
+            float lr, float beta1, float beta2, float eps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDNN_H */

@@ -1,0 +1,626 @@
+// Learned coarse-grid correction network on gfx950 MFMA.
+//
+// conv3x3x3(3->16) - GELU - conv3x3x3(16->16) - GELU - conv3x3x3(16->1), zero
+// "same" padding, BF16 operands, FP32 accumulation.
+//
+// Forward and data-gradient convolutions are one implicit-GEMM kernel on
+// v_mfma_f32_16x16x32_bf16 with the 16 output channels on M and 16
+// consecutive x points on N; K runs over (tap, input channel) in steps of 32.
+// Activations are channels-last BF16, so every lane feeds its B fragment
+// with one 16-byte LDS read (8 channels of one neighbour point) from a
+// 10 x 10 x 18-point halo tile, while the A fragments (weights) of all K
+// steps stay in registers for the whole block.  Epilogues are fused: bias +
+// GELU (keeping the pre-activation for training), the residual update of
+// the coarse wavefield, or the GELU derivative of the data gradient.
+//
+// Weight gradients contract over points: M = output channels, N = input
+// channels, K = 32 points along x; the tiles are staged channel-major in
+// LDS, each wave owns a subset of the 27 taps, and per-block partial sums
+// are reduced in a fixed order by a second kernel (deterministic).
+#include <hip/hip_runtime.h>
+
+#include "../../include/fdnn.h"
+#include "fd_internal.h"
+
+namespace fd {
+namespace nn {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+// parameter layout (floats)
+constexpr int kW1 = 0, kB1 = 1296, kW2 = 1312, kB2 = 8224, kW3 = 8240, kB3 = 8672, kNP = 8673;
+// packed fragment sets (each step is 64 lanes x 8 BF16 = 1 KiB)
+constexpr int kF1 = 0, kF2 = 7, kF3 = 21, kD3 = 35, kD2 = 42, kSteps = 56;
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float x)
+{
+    return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float x)
+{
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
+           x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ---------------------------------------------------------------------------
+// weight packing: FP32 parameters -> BF16 A fragments
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int flip_tap(int t)
+{
+    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+    return (2 - dz) * 9 + (2 - dy) * 3 + (2 - dx);
+}
+
+__global__ __launch_bounds__(256) void k_pack_weights(const float *__restrict__ P, uint16_t *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // element of kSteps*64*8
+    if (e >= kSteps * 512) return;
+    const int step = e / 512, lane = (e / 8) % 64, j = e % 8;
+    const int m = lane & 15;
+    int set, s, cin;
+    if (step < kF2) { set = 0; s = step - kF1; cin = 8; }
+    else if (step < kF3) { set = 1; s = step - kF2; cin = 16; }
+    else if (step < kD3) { set = 2; s = step - kF3; cin = 16; }
+    else if (step < kD2) { set = 3; s = step - kD3; cin = 8; }
+    else { set = 4; s = step - kD2; cin = 16; }
+    const int k = 32 * s + 8 * (lane >> 4) + j;
+    const int tap = k / cin, c = k % cin;
+    float w = 0.0f;
+    if (tap < 27) {
+        switch (set) {
+        case 0:   // layer 1 forward: M = co (16), K = (tap, ci < 3)
+            if (c < 3) w = P[kW1 + (m * 3 + c) * 27 + tap];
+            break;
+        case 1:   // layer 2 forward
+            w = P[kW2 + (m * 16 + c) * 27 + tap];
+            break;
+        case 2:   // layer 3 forward: only output channel 0
+            if (m == 0) w = P[kW3 + c * 27 + tap];
+            break;
+        case 3:   // through layer 3: M = ci of layer 3, K = (flipped tap, co < 1)
+            if (c == 0) w = P[kW3 + m * 27 + flip_tap(tap)];
+            break;
+        default:  // through layer 2: M = ci, K = (flipped tap, co)
+            w = P[kW2 + (c * 16 + m) * 27 + flip_tap(tap)];
+            break;
+        }
+    }
+    out[e] = f2bf(w);
+}
+
+// ---------------------------------------------------------------------------
+// implicit-GEMM 3x3x3 convolution
+// ---------------------------------------------------------------------------
+enum Epi { EPI_GELU = 0, EPI_GELU_Z = 1, EPI_OUT = 2, EPI_DGRAD = 3 };
+
+constexpr int TXC = 16, TYC = 8, TZC = 8;                   // output tile
+constexpr int HXC = TXC + 2, HYC = TYC + 2, HZC = TZC + 2;  // halo tile
+
+struct ConvArgs {
+    int nz, ny, nx;
+    const uint16_t *in;       // channels-last [n][CIN]
+    const uint16_t *frag;     // STEPS x 64 lanes x 8 BF16
+    const float *bias;        // 16 (EPI_GELU*), 1 (EPI_OUT), NULL (EPI_DGRAD)
+    uint16_t *a16;            // GELU output
+    uint16_t *z16;            // pre-activation out (EPI_GELU_Z) / previous z in (EPI_DGRAD)
+    float *ydense;            // EPI_OUT: dense y (may be NULL)
+    const float *base;        // EPI_OUT: residual base (may be NULL with out NULL)
+    nn_view vbase;
+    float *out;
+    nn_view vout;
+    const float *scale;       // EPI_OUT: s = scale[0] (NULL = 1)
+};
+
+template <int CIN, int STEPS, int EPI>
+__global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t tile[HZC * HYC * HXC * CIN];
+    const int ntx = (a.nx + TXC - 1) / TXC, nty = (a.ny + TYC - 1) / TYC;
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int tz = b / nty;
+    const int x0 = tx * TXC, y0 = ty * TYC, z0 = tz * TZC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // weights: all K steps resident in registers
+    bf16x8 af[STEPS];
+    const bf16x8 *fr = reinterpret_cast<const bf16x8 *>(a.frag);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) af[s] = fr[s * 64 + lane];
+
+    // halo tile, 16-byte chunks (8 channels)
+    constexpr int CH = CIN / 8;
+    constexpr int NCHUNK = HZC * HYC * HXC * CH;
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
+    uint4 *dst = reinterpret_cast<uint4 *>(tile);
+    for (int c = tid; c < NCHUNK; c += 256) {
+        const int pt = c / CH, ch = c % CH;
+        const int hx = pt % HXC, hy = (pt / HXC) % HYC, hz = pt / (HXC * HYC);
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+            v = src[(((int64_t)gz * a.ny + gy) * a.nx + gx) * CH + ch];
+        dst[c] = v;
+    }
+    __syncthreads();
+
+    const int n = lane & 15, g = lane >> 4;
+    // 64 rows of 16 points; wave w takes rows w, w+4, ...
+    for (int row = wave; row < TZC * TYC; row += 4) {
+        const int zl = row / TYC, yl = row % TYC;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            const int kb = 32 * s + 8 * g;
+            int tap = kb / CIN;
+            const int c0 = kb % CIN;
+            tap = tap > 26 ? 26 : tap;              // padding steps: zero weights
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+            const int off = (((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx)) * CIN + c0;
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(tile + off);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bv, acc, 0, 0, 0);
+        }
+        const int x = x0 + n, y = y0 + yl, z = z0 + zl;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
+        if (EPI == EPI_OUT) {
+            if (g == 0) {
+                const float yv = acc[0] + a.bias[0];
+                if (a.ydense) a.ydense[p] = yv;
+                if (a.out) {
+                    const float s = a.scale ? a.scale[0] : 1.0f;
+                    const int64_t ib = a.vbase.offset + z * a.vbase.pitch_z + y * a.vbase.pitch_y + x;
+                    const int64_t io = a.vout.offset + z * a.vout.pitch_z + y * a.vout.pitch_y + x;
+                    a.out[io] = a.base[ib] + s * yv;
+                }
+            }
+        } else {
+            uint16_t o[4];
+            if (EPI == EPI_DGRAD) {
+                const uint2 zp = *reinterpret_cast<const uint2 *>(a.z16 + p * 16 + 4 * g);
+                const uint16_t zz[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
+                                        (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = f2bf(acc[j] * gelu_grad(bf2f(zz[j])));
+                *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
+                    make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+            } else {
+                uint16_t zo[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float zv = acc[j] + a.bias[4 * g + j];
+                    const uint16_t zb = f2bf(zv);
+                    zo[j] = zb;
+                    // GELU of the stored (BF16) pre-activation, so training and
+                    // its backward see the same value
+                    o[j] = f2bf(gelu(bf2f(zb)));
+                }
+                *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
+                    make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+                if (EPI == EPI_GELU_Z)
+                    *reinterpret_cast<uint2 *>(a.z16 + p * 16 + 4 * g) =
+                        make_uint2(zo[0] | ((uint32_t)zo[1] << 16), zo[2] | ((uint32_t)zo[3] << 16));
+            }
+        }
+    }
+}
+
+template <int CIN, int STEPS, int EPI>
+static int conv(const ConvArgs &a, hipStream_t s)
+{
+    const int nb = ((a.nx + TXC - 1) / TXC) * ((a.ny + TYC - 1) / TYC) * ((a.nz + TZC - 1) / TZC);
+    hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI>), dim3(nb), dim3(256), 0, s, a);
+    return check_launch("nn conv");
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient
+// ---------------------------------------------------------------------------
+constexpr int TXW = 32, TYW = 4, TZW = 4;                    // points per tile
+constexpr int HXW = TXW + 2, HYW = TYW + 2, HZW = TZW + 2;
+constexpr int WG_PART = 27 * 256 + 16;                       // floats per block partial
+constexpr int WG_BLOCKS = 512;                               // persistent blocks
+
+template <int CIN, int GC>
+__global__ __launch_bounds__(256) void k_wgrad(const int nz, const int ny, const int nx,
+                                               const uint16_t *__restrict__ x,
+                                               const uint16_t *__restrict__ gsrc,
+                                               float *__restrict__ part)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t gt[16][TZW * TYW * TXW];     // channel-major g
+    __shared__ __attribute__((aligned(16))) uint16_t xt[16][HZW * HYW * HXW];     // channel-major x
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntx = (nx + TXW - 1) / TXW, nty = (ny + TYW - 1) / TYW, ntz = (nz + TZW - 1) / TZW;
+    const int ntiles = ntx * nty * ntz;
+    const int m = lane & 15, g = lane >> 4;
+    // this wave's taps: wave, wave + 4, ... (7 or 6 taps)
+    floatx4 acc[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float dbacc = 0.0f;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+        const int x0 = tx * TXW, y0 = ty * TYW, z0 = tz * TZW;
+        __syncthreads();   // previous tile's reads done
+        for (int e = tid; e < 16 * TZW * TYW * TXW; e += 256) {
+            const int c = e / (TZW * TYW * TXW), pt = e % (TZW * TYW * TXW);
+            const int px = pt % TXW, py = (pt / TXW) % TYW, pz = pt / (TXW * TYW);
+            const int gx = x0 + px, gy = y0 + py, gz = z0 + pz;
+            uint16_t v = 0;
+            if (c < GC && gx < nx && gy < ny && gz < nz)
+                v = gsrc[(((int64_t)gz * ny + gy) * nx + gx) * GC + c];
+            gt[c][pt] = v;
+        }
+        for (int e = tid; e < 16 * HZW * HYW * HXW; e += 256) {
+            const int c = e / (HZW * HYW * HXW), pt = e % (HZW * HYW * HXW);
+            const int hx = pt % HXW, hy = (pt / HXW) % HYW, hz = pt / (HXW * HYW);
+            const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+            uint16_t v = 0;
+            if (c < CIN && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+                v = x[(((int64_t)gz * ny + gy) * nx + gx) * CIN + c];
+            xt[c][pt] = v;
+        }
+        __syncthreads();
+        if (wave == 0 && lane < 16) {
+            float sacc = 0.0f;
+            for (int pt = 0; pt < TZW * TYW * TXW; ++pt) sacc += bf2f(gt[lane][pt]);
+            dbacc += sacc;
+        }
+        for (int row = 0; row < TZW * TYW; ++row) {
+            const int zl = row / TYW, yl = row % TYW;
+            bf16x8 av;
+            {
+                const uint16_t *gp = &gt[m][row * TXW + 8 * g];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) av[j] = __builtin_bit_cast(__bf16, gp[j]);
+            }
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                const int tap = wave + 4 * i;
+                if (tap < 27) {
+                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                    const uint16_t *xp = &xt[m][((zl + dz) * HYW + (yl + dy)) * HXW + 8 * g + dx];
+                    bf16x8 bv;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bv[j] = __builtin_bit_cast(__bf16, xp[j]);
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // C[co][ci]: lane holds co = 4 g + j, ci = m
+    float *pb = part + (int64_t)blockIdx.x * WG_PART;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int tap = wave + 4 * i;
+        if (tap < 27)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pb[tap * 256 + (4 * g + j) * 16 + m] = acc[i][j];
+    }
+    if (wave == 0 && lane < 16) pb[27 * 256 + lane] = dbacc;
+}
+
+// grads[layer slice] = sum over blocks (in block order)
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part,
+                                                      const int nparts, const int cin_real,
+                                                      const int cout_real, float *wout,
+                                                      float *bout)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // co * cin_real * 27 + ci * 27 + tap
+    const int nw = cout_real * cin_real * 27;
+    if (e < nw) {
+        const int tap = e % 27, ci = (e / 27) % cin_real, co = e / (27 * cin_real);
+        float s = 0.0f;
+        for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * WG_PART + tap * 256 + co * 16 + ci];
+        wout[e] = s;
+    } else if (e < nw + cout_real) {
+        const int co = e - nw;
+        float s = 0.0f;
+        for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * WG_PART + 27 * 256 + co];
+        bout[co] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_input(const int nz, const int ny, const int nx,
+                                                    const float *a, const nn_view va,
+                                                    const float *b, const nn_view vb,
+                                                    const float *c, const nn_view vc,
+                                                    const float *scale, uint16_t *x8)
+{
+    const int64_t n = (int64_t)nz * ny * nx;
+    const float inv = scale ? 1.0f / scale[0] : 1.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int64_t t = i / nx;
+        const int y = (int)(t % ny), z = (int)(t / ny);
+        const float va_ = a[va.offset + z * va.pitch_z + y * va.pitch_y + x] * inv;
+        const float vb_ = b[vb.offset + z * vb.pitch_z + y * vb.pitch_y + x] * inv;
+        const float vc_ = c[vc.offset + z * vc.pitch_z + y * vc.pitch_y + x];
+        uint4 o;
+        o.x = f2bf(va_) | ((uint32_t)f2bf(vb_) << 16);
+        o.y = f2bf(vc_);
+        o.z = 0u;
+        o.w = 0u;
+        reinterpret_cast<uint4 *>(x8)[i] = o;
+    }
+}
+
+constexpr int kRmsBlocks = 256;
+
+// stage 1: per-block sums of squares (double) and non-finite flags
+__global__ __launch_bounds__(256) void k_rms_part(const int nz, const int ny, const int nx,
+                                                  const float *u, const nn_view vu, double *part,
+                                                  unsigned *flag)
+{
+    __shared__ double red[256];
+    const int64_t n = (int64_t)nz * ny * nx;
+    double s = 0.0;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int64_t t = i / nx;
+        const int y = (int)(t % ny), z = (int)(t / ny);
+        const float v = u[vu.offset + z * vu.pitch_z + y * vu.pitch_y + x];
+        if (!isfinite(v)) bad = true;
+        s += (double)v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (bad && flag) flag[0] = 1u;
+}
+
+// stage 2: ordered sum of the block sums -> sqrt(mean) (deterministic)
+__global__ __launch_bounds__(64) void k_rms_final(const double *part, const int64_t n,
+                                                  float *scale)
+{
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < kRmsBlocks; ++b) s += part[b];
+        scale[0] = (float)sqrt(s / (double)n) + 1e-30f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mse(const int64_t n, const float *__restrict__ y,
+                                             const float *__restrict__ t, uint16_t *gy8,
+                                             float *loss)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    const float inv = 1.0f / (float)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = y[i] - t[i];
+        s += d * d;
+        uint4 o = make_uint4(f2bf(2.0f * d * inv), 0u, 0u, 0u);
+        reinterpret_cast<uint4 *>(gy8)[i] = o;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, red[0] * inv);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *p, const float *__restrict__ g, float *m,
+                                              float *v, const float c1, const float c2,
+                                              const float lr, const float b1, const float b2,
+                                              const float eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNP) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace nn
+}  // namespace fd
+
+using namespace fd;
+using namespace fd::nn;
+
+extern "C" {
+
+int64_t nn_param_count(void) { return kNP; }
+int64_t nn_packed_bytes(void) { return (int64_t)kSteps * 64 * 8 * 2; }
+
+int64_t nn_wgrad_workspace_bytes(int nz, int ny, int nx)
+{
+    (void)nz;
+    (void)ny;
+    (void)nx;
+    return (int64_t)WG_BLOCKS * WG_PART * (int64_t)sizeof(float);
+}
+
+int nn_pack_weights(const float *params_dev, void *packed_dev, void *stream)
+{
+    if (!params_dev || !packed_dev) return set_error(FD_EINVAL, "nn_pack_weights: null pointer");
+    hipLaunchKernelGGL(k_pack_weights, dim3((kSteps * 512 + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, params_dev, (uint16_t *)packed_dev);
+    return check_launch("nn pack weights");
+}
+
+static bool bad_shape(int nz, int ny, int nx) { return nz < 1 || ny < 1 || nx < 1; }
+
+int nn_pack_input(int nz, int ny, int nx, const float *a, nn_view va, const float *b, nn_view vb,
+                  const float *c, nn_view vc, const float *scale_dev, void *x8_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !a || !b || !c || !x8_dev)
+        return set_error(FD_EINVAL, "nn_pack_input: bad argument");
+    const int64_t n = (int64_t)nz * ny * nx;
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_pack_input, dim3(nb), dim3(256), 0, (hipStream_t)stream, nz, ny, nx, a,
+                       va, b, vb, c, vc, scale_dev, (uint16_t *)x8_dev);
+    return check_launch("nn pack input");
+}
+
+int nn_rms(int nz, int ny, int nx, const float *u, nn_view vu, float *scale_dev,
+           unsigned *flag_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !u || !scale_dev) return set_error(FD_EINVAL, "nn_rms: bad argument");
+    // scale_dev[0] is the result; the double-aligned block sums live from
+    // scale_dev + 2 on (see fdnn.h: nn_rms_scratch_floats)
+    double *part = reinterpret_cast<double *>(scale_dev + 2);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_rms_part, dim3(kRmsBlocks), dim3(256), 0, s, nz, ny, nx, u, vu, part,
+                       flag_dev);
+    hipLaunchKernelGGL(k_rms_final, dim3(1), dim3(64), 0, s, part, (int64_t)nz * ny * nx,
+                       scale_dev);
+    return check_launch("nn rms");
+}
+
+int64_t nn_rms_scratch_floats(void) { return 2 + 2 * kRmsBlocks; }
+
+int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const void *packed_dev,
+                 const float *params_dev, void *z16_dev, void *a16_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !x_dev || !packed_dev || !params_dev || !a16_dev ||
+        (layer != 1 && layer != 2))
+        return set_error(FD_EINVAL, "nn_conv_gelu: bad argument");
+    ConvArgs a{};
+    a.nz = nz;
+    a.ny = ny;
+    a.nx = nx;
+    a.in = (const uint16_t *)x_dev;
+    a.a16 = (uint16_t *)a16_dev;
+    a.z16 = (uint16_t *)z16_dev;
+    const uint16_t *pk = (const uint16_t *)packed_dev;
+    hipStream_t s = (hipStream_t)stream;
+    if (layer == 1) {
+        a.frag = pk + kF1 * 512;
+        a.bias = params_dev + kB1;
+        return z16_dev ? conv<8, 7, EPI_GELU_Z>(a, s) : conv<8, 7, EPI_GELU>(a, s);
+    }
+    a.frag = pk + kF2 * 512;
+    a.bias = params_dev + kB2;
+    return z16_dev ? conv<16, 14, EPI_GELU_Z>(a, s) : conv<16, 14, EPI_GELU>(a, s);
+}
+
+int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_dev,
+                const float *params_dev, float *y_dense_dev, const float *base_dev, nn_view vbase,
+                float *out_dev, nn_view vout, const float *scale_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !a16_dev || !packed_dev || !params_dev ||
+        (out_dev && !base_dev) || (!out_dev && !y_dense_dev))
+        return set_error(FD_EINVAL, "nn_conv_out: bad argument");
+    ConvArgs a{};
+    a.nz = nz;
+    a.ny = ny;
+    a.nx = nx;
+    a.in = (const uint16_t *)a16_dev;
+    a.frag = (const uint16_t *)packed_dev + kF3 * 512;
+    a.bias = params_dev + kB3;
+    a.ydense = y_dense_dev;
+    a.base = base_dev;
+    a.vbase = vbase;
+    a.out = out_dev;
+    a.vout = vout;
+    a.scale = scale_dev;
+    return conv<16, 14, EPI_OUT>(a, (hipStream_t)stream);
+}
+
+int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev, void *gy8_dev,
+           float *loss_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !y_dev || !t_dev || !gy8_dev || !loss_dev)
+        return set_error(FD_EINVAL, "nn_mse: bad argument");
+    const int64_t n = (int64_t)nz * ny * nx;
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, (hipStream_t)stream, n, y_dev, t_dev,
+                       (uint16_t *)gy8_dev, loss_dev);
+    return check_launch("nn mse");
+}
+
+int nn_dgrad_gelu(int layer, int nz, int ny, int nx, const void *gin_dev, const void *packed_dev,
+                  const void *z16_prev_dev, void *gz_out16_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !gin_dev || !packed_dev || !z16_prev_dev || !gz_out16_dev ||
+        (layer != 2 && layer != 3))
+        return set_error(FD_EINVAL, "nn_dgrad_gelu: bad argument");
+    ConvArgs a{};
+    a.nz = nz;
+    a.ny = ny;
+    a.nx = nx;
+    a.in = (const uint16_t *)gin_dev;
+    a.z16 = (uint16_t *)z16_prev_dev;
+    a.a16 = (uint16_t *)gz_out16_dev;
+    const uint16_t *pk = (const uint16_t *)packed_dev;
+    hipStream_t s = (hipStream_t)stream;
+    if (layer == 3) {
+        a.frag = pk + kD3 * 512;
+        return conv<8, 7, EPI_DGRAD>(a, s);
+    }
+    a.frag = pk + kD2 * 512;
+    return conv<16, 14, EPI_DGRAD>(a, s);
+}
+
+int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
+             void *workspace_dev, float *grads_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !x_dev || !g_dev || !workspace_dev || !grads_dev ||
+        layer < 1 || layer > 3)
+        return set_error(FD_EINVAL, "nn_wgrad: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    float *part = (float *)workspace_dev;
+    const uint16_t *x = (const uint16_t *)x_dev, *g = (const uint16_t *)g_dev;
+    const int ntiles = ((nx + TXW - 1) / TXW) * ((ny + TYW - 1) / TYW) * ((nz + TZW - 1) / TZW);
+    const int nbk = std::min(WG_BLOCKS, ntiles);
+    int cin_real, cout_real, woff, boff;
+    if (layer == 1) {
+        hipLaunchKernelGGL((k_wgrad<8, 16>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
+        cin_real = 3; cout_real = 16; woff = kW1; boff = kB1;
+    } else if (layer == 2) {
+        hipLaunchKernelGGL((k_wgrad<16, 16>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
+        cin_real = 16; cout_real = 16; woff = kW2; boff = kB2;
+    } else {
+        hipLaunchKernelGGL((k_wgrad<16, 8>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
+        cin_real = 16; cout_real = 1; woff = kW3; boff = kB3;
+    }
+    int rc = check_launch("nn wgrad");
+    if (rc) return rc;
+    const int nout = cout_real * cin_real * 27 + cout_real;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 255) / 256), dim3(256), 0, s, part, nbk,
+                       cin_real, cout_real, grads_dev + woff, grads_dev + boff);
+    return check_launch("nn wgrad reduce");
+}
+
+int nn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int t, float lr,
+            float beta1, float beta2, float eps, void *stream)
+{
+    if (!params_dev || !grads_dev || !m_dev || !v_dev || t < 1)
+        return set_error(FD_EINVAL, "nn_adam: bad argument");
+    const float c1 = 1.0f - (float)std::pow((double)beta1, t);
+    const float c2 = 1.0f - (float)std::pow((double)beta2, t);
+    hipLaunchKernelGGL(k_adam, dim3((kNP + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       params_dev, grads_dev, m_dev, v_dev, c1, c2, lr, beta1, beta2, eps);
+    return check_launch("nn adam");
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+"""GPU BF16-MFMA network kernels against the FP64 network oracle evaluated on
+the same BF16-rounded operands.  Outputs stored in BF16 are compared within
+BF16 rounding (relative L2 <= 5e-3); FP32 outputs (layer-3 output, weight
+gradients) within 1e-4 relative L2 (FP32 accumulation order only)."""
+import numpy as np
+import pytest
+
+from oracle import nn as N
+from gpu_helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (11, 13, 37)     # several 16 x 8 x 8 tiles plus ragged edges
+
+
+def _bits(a):
+    """float -> BF16 bit patterns (round to nearest even) as int16."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return r.view(np.int16)
+
+
+def _from_bits(t, c):
+    """device int16 BF16 bits [n*c] -> float64 [c][nz][ny][nx]"""
+    b = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    a = b.view(np.float32).astype(np.float64).reshape(SHAPE + (c,))
+    return np.moveaxis(a, -1, 0)
+
+
+def _cl(a):
+    """[c][...] -> channels-last flat"""
+    return np.ascontiguousarray(np.moveaxis(np.asarray(a), 0, -1)).ravel()
+
+
+def _net(params):
+    from paper_2312_13094_amd import nn
+    return nn.Net(SHAPE, params)
+
+
+def _params(seed=0, scale=0.3):
+    from paper_2312_13094_amd import nn
+    rng = np.random.default_rng(seed)
+    p = nn.init_params(seed, gain=1.0)
+    p[1296:1312] = rng.standard_normal(16) * 0.1
+    p[8224:8240] = rng.standard_normal(16) * 0.1
+    p[8240:8672] *= 20.0 * scale
+    p[8672] = 0.05
+    return p
+
+
+def _oracle_params(p):
+    from paper_2312_13094_amd import nn
+    w1, b1, w2, b2, w3, b3 = nn.split_params(p)
+    return (N.bf16_round(w1), b1.astype(np.float64), N.bf16_round(w2), b2.astype(np.float64),
+            N.bf16_round(w3), b3.astype(np.float64))
+
+
+def _input(seed=1):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal(SHAPE).astype(np.float32) for _ in range(3)]
+
+
+def test_forward_layers_match_oracle():
+    import torch
+    from paper_2312_13094_amd import nn
+    p = _params()
+    net = _net(p)
+    a, b, c = _input()
+    dv = nn.dense_view(SHAPE)
+    ta, tb, tc = (torch.from_numpy(v).cuda() for v in (a, b, c))
+    net.pack_input(ta, dv, tb, dv, tc, dv)
+    net.forward(keep=True)
+    torch.cuda.synchronize()
+    w1, b1, w2, b2, w3, b3 = _oracle_params(p)
+    x = np.stack([N.bf16_round(v) for v in (a, b, c)])
+    np.testing.assert_array_equal(_from_bits(net.x8, 8)[:3], x)
+    z1 = N.conv3d(x, w1, b1)
+    assert rel_l2(_from_bits(net.z1, 16), z1) <= 5e-3
+    # the next layers from the oracle's own BF16-rounded activations
+    a1 = N.bf16_round(N.gelu(N.bf16_round(z1)))
+    assert rel_l2(_from_bits(net.a1, 16), a1) <= 5e-3
+    z2 = N.conv3d(a1, w2, b2)
+    assert rel_l2(_from_bits(net.z2, 16), z2) <= 1e-2
+    a2 = N.bf16_round(N.gelu(N.bf16_round(z2)))
+    y = N.conv3d(a2, w3, b3)[0]
+    assert rel_l2(net.y.cpu().numpy().reshape(SHAPE), y) <= 2e-2
+
+
+def test_output_layer_fp32_and_residual():
+    """Layer 3 alone on a known BF16 activation: FP32 output within 1e-4, and
+    the fused residual update out = base + s * y through a padded view."""
+    import torch
+    from paper_2312_13094_amd import nn
+    p = _params(3)
+    net = _net(p)
+    rng = np.random.default_rng(4)
+    a2 = rng.standard_normal((16,) + SHAPE).astype(np.float32)
+    net.a2.copy_(torch.from_numpy(_bits(_cl(a2))))
+    L = nn.lib()
+    nz, ny, nx = SHAPE
+    # padded destination: pitch 48, 2-point margins
+    pz, py = (ny + 4) * 48, 48
+    off = 2 * pz + 2 * py + 3
+    base = torch.from_numpy(rng.standard_normal((nz + 4) * pz).astype(np.float32)).cuda()
+    out = torch.full_like(base, 7.0)
+    scale = torch.zeros(int(L.nn_rms_scratch_floats()), device="cuda")
+    scale[0] = 2.5
+    vb = nn.View(off, py, pz)
+    nn._chk(L.nn_conv_out(nz, ny, nx, nn._p(net.a2), nn._p(net.packed), nn._p(net.params),
+                          nn._p(net.y), nn._p(base), vb, nn._p(out), vb, nn._p(scale), nn._s()))
+    torch.cuda.synchronize()
+    w3, b3 = _oracle_params(p)[4:]
+    y = N.conv3d(N.bf16_round(a2), w3, b3)[0]
+    got = net.y.cpu().numpy().reshape(SHAPE)
+    assert rel_l2(got, y) <= 1e-4
+    o = out.cpu().numpy()
+    bs = base.cpu().numpy()
+    idx = off + np.arange(nz)[:, None, None] * pz + np.arange(ny)[None, :, None] * py + \
+        np.arange(nx)[None, None, :]
+    np.testing.assert_allclose(o[idx], bs[idx] + 2.5 * got, rtol=1e-6, atol=1e-6)
+    mask = np.ones(o.size, bool)
+    mask[idx.ravel()] = False
+    assert np.all(o[mask] == 7.0)
+
+
+@pytest.mark.parametrize("layer", [1, 2, 3])
+def test_weight_gradients_match_oracle(layer):
+    import torch
+    from paper_2312_13094_amd import nn
+    rng = np.random.default_rng(10 + layer)
+    cin, gc = {1: (8, 16), 2: (16, 16), 3: (16, 8)}[layer]
+    cin_real, co_real = {1: (3, 16), 2: (16, 16), 3: (16, 1)}[layer]
+    x = np.zeros((cin,) + SHAPE, np.float32)
+    x[:cin_real] = rng.standard_normal((cin_real,) + SHAPE)
+    g = np.zeros((gc,) + SHAPE, np.float32)
+    g[:co_real] = rng.standard_normal((co_real,) + SHAPE)
+    net = _net(_params())
+    xt = torch.from_numpy(_bits(_cl(x))).cuda()
+    gt = torch.from_numpy(_bits(_cl(g))).cuda()
+    net.grads.zero_()
+    nz, ny, nx = SHAPE
+    nn._chk(nn.lib().nn_wgrad(layer, nz, ny, nx, nn._p(xt), nn._p(gt), nn._p(net.ws),
+                              nn._p(net.grads), nn._s()))
+    torch.cuda.synchronize()
+    gw, gb = N.conv3d_wgrad(N.bf16_round(x[:cin_real]), N.bf16_round(g[:co_real]))
+    parts = nn.split_params(net.grads.cpu().numpy())
+    w_got, b_got = parts[2 * layer - 2], parts[2 * layer - 1]
+    assert rel_l2(w_got, gw) <= 1e-4
+    assert rel_l2(b_got, gb) <= 1e-4
+
+
+@pytest.mark.parametrize("layer", [2, 3])
+def test_data_gradients_match_oracle(layer):
+    import torch
+    from paper_2312_13094_amd import nn
+    rng = np.random.default_rng(20 + layer)
+    p = _params(5)
+    net = _net(p)
+    w = _oracle_params(p)[2 * layer - 2]
+    co_real, gcin = (16, 16) if layer == 2 else (1, 8)
+    gin = np.zeros((gcin,) + SHAPE, np.float32)
+    gin[:co_real] = rng.standard_normal((co_real,) + SHAPE)
+    zprev = rng.standard_normal((16,) + SHAPE).astype(np.float32)
+    gt = torch.from_numpy(_bits(_cl(gin))).cuda()
+    zt = torch.from_numpy(_bits(_cl(zprev))).cuda()
+    out = torch.zeros(int(np.prod(SHAPE)) * 16, dtype=torch.int16, device="cuda")
+    nz, ny, nx = SHAPE
+    nn._chk(nn.lib().nn_dgrad_gelu(layer, nz, ny, nx, nn._p(gt), nn._p(net.packed), nn._p(zt),
+                                   nn._p(out), nn._s()))
+    torch.cuda.synchronize()
+    ref = N.conv3d_dgrad(N.bf16_round(gin[:co_real]), w) * N.gelu_grad(N.bf16_round(zprev))
+    assert rel_l2(_from_bits(out, 16), ref) <= 5e-3
+
+
+def test_mse_and_adam():
+    import torch
+    from paper_2312_13094_amd import nn
+    rng = np.random.default_rng(7)
+    net = _net(_params())
+    y = rng.standard_normal(SHAPE).astype(np.float32)
+    t = rng.standard_normal(SHAPE).astype(np.float32)
+    net.y.copy_(torch.from_numpy(y.ravel()))
+    net.loss.zero_()
+    nz, ny, nx = SHAPE
+    tt = torch.from_numpy(t.ravel()).cuda()
+    nn._chk(nn.lib().nn_mse(nz, ny, nx, nn._p(net.y), nn._p(tt), nn._p(net.g8), nn._p(net.loss),
+                            nn._s()))
+    torch.cuda.synchronize()
+    assert abs(net.loss.item() - N.mse(y.astype(np.float64), t)) <= 1e-5 * N.mse(y, t)
+    g = _from_bits(net.g8, 8)
+    ref = 2 * (y.astype(np.float64) - t) / y.size
+    assert rel_l2(g[0], ref) <= 5e-3 and np.all(g[1:] == 0)
+    # Adam: three steps against the textbook update
+    p0 = net.params.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(p0)
+    v = np.zeros_like(p0)
+    p = p0.copy()
+    for step in range(1, 4):
+        gr = rng.standard_normal(p0.size)
+        net.grads.copy_(torch.from_numpy(gr.astype(np.float32)))
+        net.adam(lr=1e-2)
+        p, m, v = N.adam_step(p, gr.astype(np.float32).astype(np.float64), m, v, step, lr=1e-2)
+    torch.cuda.synchronize()
+    assert np.abs(net.params.cpu().numpy() - p).max() <= 1e-5
+
+
+def test_end_to_end_gradient_and_training():
+    """All parameter gradients of the MSE through the three layers agree with
+    the FP64 oracle network (which keeps activations in FP64, so only BF16
+    activation rounding separates them), and a short Adam run on a fixed
+    target reduces the loss."""
+    import torch
+    from paper_2312_13094_amd import nn
+    p = _params(8, scale=0.5)
+    net = _net(p)
+    a, b, c = _input(9)
+    rng = np.random.default_rng(9)
+    t = (0.5 * a + 0.1 * rng.standard_normal(SHAPE)).astype(np.float32)
+    dv = nn.dense_view(SHAPE)
+    ins = [torch.from_numpy(v).cuda() for v in (a, b, c)]
+    net.pack_input(ins[0], dv, ins[1], dv, ins[2], dv)
+    tt = torch.from_numpy(t.ravel()).cuda()
+    net.loss.zero_()
+    net.forward(keep=True)
+    net.backward(tt)
+    torch.cuda.synchronize()
+    onet = N.Net(*_oracle_params(p))
+    x = np.stack([N.bf16_round(v) for v in (a, b, c)])
+    oloss, ograds = onet.loss_and_grads(x, t[None].astype(np.float64))
+    assert abs(net.loss.item() - oloss) <= 2e-2 * oloss
+    got = nn.split_params(net.grads.cpu().numpy())
+    for k in range(6):
+        assert rel_l2(got[k], ograds[k]) <= 5e-2, k
+    losses = []
+    for _ in range(60):
+        net.loss.zero_()
+        net.forward(keep=True)
+        net.backward(tt)
+        net.adam(lr=3e-3)
+        losses.append(net.loss.item())
+    assert losses[-1] < 0.5 * losses[0]
