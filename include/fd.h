@@ -168,6 +168,12 @@ int fd_adjoint(fd_grid *g, float *const *state_dev,
                float *const *ckpt_dev, int ckpt_every, float *const *slot_dev,
                float *grad_m_dev, void *stream);
 
+/* Interpolate field_dev (a padded field of this handle) at the prepared
+ * points `rec` into out_dev[rec->n] (multilinear, as fd_forward samples its
+ * receivers).  Enqueues one kernel on `stream`; allocates nothing. */
+int fd_sample(const fd_grid *g, const float *field_dev, const fd_sparse *rec, float *out_dev,
+              void *stream);
+
 /* grad_v = grad_m * (-2 / v^3) for the loaded model (both DOMAIN-shaped). */
 int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *grad_v_dev,
                             void *stream);

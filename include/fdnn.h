@@ -75,10 +75,11 @@ int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_
                 nn_view vbase, float *out_dev, nn_view vout, const float *scale_dev,
                 void *stream);
 
-/* MSE over the volume: loss_dev[0] += mean((y - t)^2) (float atomics),
- * gy8[p] = (2 (y - t) / N, 0, ..., 0) as BF16. */
-int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev, void *gy8_dev,
-           float *loss_dev, void *stream);
+/* MSE over the volume against the target t / s (s = scale_dev[0], or 1 if
+ * scale_dev is NULL): loss_dev[0] += mean((y - t/s)^2) (float atomics),
+ * gy8[p] = (2 (y - t/s) / N, 0, ..., 0) as BF16. */
+int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,
+           const float *scale_dev, void *gy8_dev, float *loss_dev, void *stream);
 
 /* Data gradient through layer 3 (gin = gy8) or layer 2 (gin = gz16),
  * multiplied by GELU'(z) of the previous layer: gz_out16 = (W^T * gin) .

@@ -601,6 +601,17 @@ int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const 
     return FD_OK;
 }
 
+int fd_sample(const fd_grid *g, const float *field_dev, const fd_sparse *rec, float *out_dev,
+              void *stream)
+{
+    if (!g || !field_dev || !rec || !out_dev || rec->n < 0 || !rec->base_dev || !rec->frac_dev)
+        return set_error(FD_EINVAL, "fd_sample: bad argument");
+    DeviceGuard dg(g->d.device);
+    const SparseArgs none{0, nullptr, nullptr, nullptr, nullptr, 0.0f};
+    SparseArgs smp{rec->n, rec->base_dev, rec->frac_dev, nullptr, out_dev, 1.0f};
+    return launch_sparse(g, const_cast<float *>(field_dev), none, smp, (hipStream_t)stream);
+}
+
 int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *grad_v_dev,
                             void *stream)
 {

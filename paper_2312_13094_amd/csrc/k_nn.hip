@@ -403,15 +403,17 @@ __global__ __launch_bounds__(64) void k_rms_final(const double *part, const int6
 }
 
 __global__ __launch_bounds__(256) void k_mse(const int64_t n, const float *__restrict__ y,
-                                             const float *__restrict__ t, uint16_t *gy8,
+                                             const float *__restrict__ t,
+                                             const float *__restrict__ scale, uint16_t *gy8,
                                              float *loss)
 {
     __shared__ float red[256];
     float s = 0.0f;
     const float inv = 1.0f / (float)n;
+    const float ts = scale ? 1.0f / scale[0] : 1.0f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float d = y[i] - t[i];
+        const float d = y[i] - t[i] * ts;
         s += d * d;
         uint4 o = make_uint4(f2bf(2.0f * d * inv), 0u, 0u, 0u);
         reinterpret_cast<uint4 *>(gy8)[i] = o;
@@ -546,15 +548,15 @@ int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_
     return conv<16, 14, EPI_OUT>(a, (hipStream_t)stream);
 }
 
-int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev, void *gy8_dev,
-           float *loss_dev, void *stream)
+int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,
+           const float *scale_dev, void *gy8_dev, float *loss_dev, void *stream)
 {
     if (bad_shape(nz, ny, nx) || !y_dev || !t_dev || !gy8_dev || !loss_dev)
         return set_error(FD_EINVAL, "nn_mse: bad argument");
     const int64_t n = (int64_t)nz * ny * nx;
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 2048);
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, (hipStream_t)stream, n, y_dev, t_dev,
-                       (uint16_t *)gy8_dev, loss_dev);
+                       scale_dev, (uint16_t *)gy8_dev, loss_dev);
     return check_launch("nn mse");
 }
 

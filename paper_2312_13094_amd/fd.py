@@ -71,6 +71,7 @@ def lib():
     L.fd_adjoint.argtypes = [vp, P(vp), P(SparseC), vp, P(SparseC), vp, vp, i, P(vp), i, P(vp),
                              vp, vp]
     L.fd_gradient_to_velocity.argtypes = [vp, vp, vp, vp]
+    L.fd_sample.argtypes = [vp, vp, P(SparseC), vp, vp]
     L.fd_halo_face_elems.argtypes = [vp, i]
     L.fd_halo_face_elems.restype = i64
     L.fd_pack_halo.argtypes = [vp, vp, ctypes.c_uint, P(vp), vp]
@@ -213,6 +214,10 @@ class Grid:
             ctypes.byref(src.c) if src else None, _ptr(q), _ptr(qadj), int(nt),
             _ptr_array(ckpt), int(ckpt_every), _ptr_array(slots), _ptr(grad_m),
             _stream(self.device)))
+
+    def sample(self, field, rec, out):
+        _check(lib().fd_sample(self.handle, _ptr(field), ctypes.byref(rec.c), _ptr(out),
+                               _stream(self.device)))
 
     def gradient_to_velocity(self, grad_m, grad_v):
         _check(lib().fd_gradient_to_velocity(self.handle, _ptr(grad_m), _ptr(grad_v),

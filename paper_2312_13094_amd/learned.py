@@ -1,0 +1,226 @@
+"""Learned coarse-grid correction: orchestration of libfd calls.
+
+A space-order-4 propagation on a 2x coarser grid with a 2x larger time step
+is corrected after every coarse step by the 3-layer BF16 network of
+``fdnn.h`` toward the space-order-8 fine-grid solution:
+
+    u~(n+1) = coarse leapfrog step of (u(n), u(n-1))            [fd_forward]
+    s       = rms(u(n))                                          [nn_rms]
+    u(n+1)  = u~(n+1) + s * N(u~(n+1)/s, u(n)/s, (v - 3000)/1500) [nn_* kernels]
+
+Training data come from the plain solver: fine solves are restricted to the
+coarse nodes (even fine indices) at coarse times, the coarse step is taken
+from the restricted states, and the network learns the one-step residual
+(teacher forcing).  The plain fine solve is both the reference for the
+trace error and the fallback when the corrected run turns non-finite.
+
+This module only allocates caller-side buffers and sequences library calls;
+every arithmetic step runs in libfd's kernels (restriction to the coarse
+nodes is a strided device copy).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import fd as FD
+from . import nn as NN
+from .synth import Learned
+
+
+def _restrict(g_fine, f, out):
+    """Fine padded field -> dense coarse volume (values at even fine indices)."""
+    out.copy_(g_fine.domain(f)[::2, ::2, ::2])
+
+
+@dataclass
+class Sample:
+    ut: torch.Tensor       # coarse step result u~(n+1), dense
+    u0: torch.Tensor       # u(n), dense
+    target: torch.Tensor   # restricted fine u(n+1) - u~(n+1), dense
+    model: int             # index into the model list
+
+
+@dataclass
+class RunResult:
+    traces: np.ndarray     # [nt_coarse][nrec]
+    seconds: float
+    fallback: bool = False
+    info: dict = field(default_factory=dict)
+
+
+class LearnedCorrector:
+    def __init__(self, cfg: Learned, params=None, device: int = 0):
+        self.cfg = c = cfg
+        self.dev = torch.device("cuda", device)
+        nf, nc = c.n_fine, c.n_coarse
+        self.fine = FD.Grid((nf,) * 3, (c.h_fine,) * 3, c.so_fine, c.dt_fine, c.vmax,
+                            nbl=c.nbl_fine, device=device)
+        self.coarse = FD.Grid((nc,) * 3, (c.h_coarse,) * 3, c.so_coarse, c.dt_coarse, c.vmax,
+                              nbl=c.nbl_coarse, device=device)
+        self.net = NN.Net((nc,) * 3, params, device)
+        src, rec = c.src_fine(), c.rec_fine()          # physical coordinates, shared
+        self.Sf, self.Rf = self.fine.sparse(src), self.fine.sparse(rec)
+        self.Sc, self.Rc = self.coarse.sparse(src), self.coarse.sparse(rec)
+        self.qf = torch.from_numpy(c.q_fine()).to(self.dev)
+        self.qc = torch.from_numpy(c.q_coarse()).to(self.dev)
+        self.vhat = torch.zeros((nc,) * 3, dtype=torch.float32, device=self.dev)
+        self.fa, self.fb = self.fine.field(), self.fine.field()
+        self.ca, self.cb = self.coarse.field(), self.coarse.field()
+        self.cview = NN.grid_view(self.coarse)
+        self.dview = NN.dense_view((nc,) * 3)
+
+    # -- models -------------------------------------------------------------
+    def set_model(self, vel_fine: np.ndarray):
+        vf = torch.from_numpy(np.ascontiguousarray(vel_fine, dtype=np.float32)).to(self.dev)
+        self.fine.set_model(vf)
+        vc = vf[::2, ::2, ::2].contiguous()
+        self.coarse.set_model(vc)
+        # network input channel: (v - 3000) / 1500
+        self.vhat.copy_(vc).sub_(3000.0).div_(1500.0)
+
+    # -- plain solvers ---------------------------------------------------------
+    def fine_solve(self, snapshot_steps=()):
+        """Plain fine run.  Returns (traces at coarse times [nt_c][nr],
+        seconds, {fine step k: restricted u(k)} for k in snapshot_steps)."""
+        c = self.cfg
+        self.fa.zero_()
+        self.fb.zero_()
+        d = torch.zeros((c.nt_fine, self.Rf.n), dtype=torch.float32, device=self.dev)
+        snaps = {}
+        stops = sorted(set(int(k) for k in snapshot_steps if 0 < k <= c.nt_fine))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k0 = 0
+        for k in stops + [c.nt_fine]:
+            if k > k0:
+                self.fine.forward([self.fa, self.fb], self.Sf, self.qf[k0:], self.Rf, d[k0:], k - k0)
+                k0 = k
+            if k in stops:
+                out = torch.empty((c.n_coarse,) * 3, dtype=torch.float32, device=self.dev)
+                _restrict(self.fine, self.fa, out)
+                snaps[k] = out
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        # coarse step n samples u at fine step 2n + 2, i.e. fine trace index 2n + 1
+        tr = d[1::2].double().cpu().numpy()
+        return tr, secs, snaps
+
+    def coarse_solve(self):
+        """Plain coarse run (no correction)."""
+        c = self.cfg
+        self.ca.zero_()
+        self.cb.zero_()
+        d = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32, device=self.dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.coarse.forward([self.ca, self.cb], self.Sc, self.qc, self.Rc, d, c.nt_coarse)
+        torch.cuda.synchronize()
+        return d.double().cpu().numpy(), time.perf_counter() - t0
+
+    # -- learned run ---------------------------------------------------------
+    def coarse_step(self, n):
+        """ca, cb = (u(n), u(n-1)) -> (u~(n+1), u(n))."""
+        self.coarse.forward([self.ca, self.cb], self.Sc, self.qc[n:n + 1], None, None, 1)
+
+    def correct(self):
+        """ca <- ca + s * N(ca/s, cb/s, vhat) with s = rms(cb)."""
+        net = self.net
+        net.rms(self.cb, self.cview)
+        net.pack_input(self.ca, self.cview, self.cb, self.cview, self.vhat, self.dview,
+                       scale=net.scale)
+        net.forward(keep=False, out=self.ca, base=self.ca, vbase=self.cview, vout=self.cview,
+                    scale=net.scale, ydense=False)
+
+    def learned_solve(self, guard=True):
+        """Corrected coarse run; falls back to the plain fine solve if the
+        corrected wavefield turns non-finite."""
+        c = self.cfg
+        self.ca.zero_()
+        self.cb.zero_()
+        self.net.flag.zero_()
+        d = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32, device=self.dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(c.nt_coarse):
+            self.coarse_step(n)
+            self.correct()
+            self.coarse.sample(self.ca, self.Rc, d[n])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        tr = d.double().cpu().numpy()
+        bad = bool(self.net.flag.item()) or not np.isfinite(tr).all()
+        if guard and bad:
+            ftr, fsecs, _ = self.fine_solve()
+            return RunResult(ftr, secs + fsecs, fallback=True, info={"learned_seconds": secs})
+        return RunResult(tr, secs)
+
+    # -- training data and training -----------------------------------------
+    def make_samples(self, seeds, coarse_steps, model_store):
+        """Teacher-forcing samples for every seed and coarse step n in
+        coarse_steps (1 <= n < nt_coarse)."""
+        c = self.cfg
+        samples = []
+        for seed in seeds:
+            self.set_model(c.velocity(seed))
+            model_store.append(self.vhat.clone())
+            mi = len(model_store) - 1
+            ks = []
+            for n in coarse_steps:
+                ks += [2 * n - 2, 2 * n, 2 * n + 2]
+            _, _, snaps = self.fine_solve(snapshot_steps=[k for k in ks if k > 0])
+            zero = torch.zeros((c.n_coarse,) * 3, dtype=torch.float32, device=self.dev)
+            for n in coarse_steps:
+                um = snaps.get(2 * n - 2, zero)
+                u0 = snaps[2 * n]
+                up = snaps[2 * n + 2]
+                self.ca.zero_()
+                self.cb.zero_()
+                self.coarse.domain(self.ca).copy_(u0)
+                self.coarse.domain(self.cb).copy_(um)
+                self.coarse_step(n)
+                ut = self.coarse.domain(self.ca).contiguous()
+                samples.append(Sample(ut, u0.clone(), (up - ut).contiguous(), mi))
+        return samples
+
+    def train(self, samples, models, iters, lr=1e-3, seed=0, log_every=0):
+        """Adam on the one-step MSE of the scaled residual; returns the loss history."""
+        rng = np.random.default_rng(seed)
+        net = self.net
+        hist = []
+        for it in range(iters):
+            s = samples[int(rng.integers(len(samples)))]
+            net.rms(s.u0, self.dview)
+            net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
+                           scale=net.scale)
+            net.loss.zero_()
+            net.forward(keep=True)
+            net.backward(s.target, scale=net.scale)
+            net.adam(lr=lr)
+            if log_every and (it % log_every == 0 or it == iters - 1):
+                hist.append((it, net.loss.item()))
+        return hist
+
+    def sample_loss(self, samples, models):
+        """Mean one-step loss of the current network over `samples` (and of the
+        uncorrected coarse step, i.e. the target's own scaled energy)."""
+        net = self.net
+        tot, base = 0.0, 0.0
+        for s in samples:
+            net.rms(s.u0, self.dview)
+            net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
+                           scale=net.scale)
+            net.forward(keep=True)
+            net.loss.zero_()
+            net.backward(s.target, scale=net.scale)
+            tot += net.loss.item()
+            sc = net.scale[0].item()
+            base += float(torch.mean((s.target / sc) ** 2).item())
+        return tot / len(samples), base / len(samples)
+
+
+def trace_error(a, ref):
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))

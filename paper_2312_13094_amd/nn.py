@@ -48,7 +48,7 @@ def lib():
         L.nn_rms.argtypes = [i, i, i, vp, View, vp, vp, vp]
         L.nn_conv_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp]
         L.nn_conv_out.argtypes = [i, i, i, vp, vp, vp, vp, vp, View, vp, View, vp, vp]
-        L.nn_mse.argtypes = [i, i, i, vp, vp, vp, vp, vp]
+        L.nn_mse.argtypes = [i, i, i, vp, vp, vp, vp, vp, vp]
         L.nn_dgrad_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
         L.nn_wgrad.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
         L.nn_adam.argtypes = [vp, vp, vp, vp, i, f, f, f, f, vp]
@@ -166,11 +166,12 @@ class Net:
                            _p(self.y) if ydense else None, _p(base), vbase or dv, _p(out),
                            vout or dv, _p(scale), _s()))
 
-    def backward(self, target):
-        """MSE against `target` (dense FP32) and all parameter gradients."""
+    def backward(self, target, scale=None):
+        """MSE against target / scale[0] (dense FP32) and all parameter gradients."""
         nz, ny, nx = self.shape
         L = lib()
-        _chk(L.nn_mse(nz, ny, nx, _p(self.y), _p(target), _p(self.g8), _p(self.loss), _s()))
+        _chk(L.nn_mse(nz, ny, nx, _p(self.y), _p(target), _p(scale), _p(self.g8), _p(self.loss),
+                      _s()))
         _chk(L.nn_wgrad(3, nz, ny, nx, _p(self.a2), _p(self.g8), _p(self.ws), _p(self.grads), _s()))
         _chk(L.nn_dgrad_gelu(3, nz, ny, nx, _p(self.g8), _p(self.packed), _p(self.z2),
                              _p(self.g16a), _s()))

@@ -284,3 +284,91 @@ def cfg_fwi_batch(n: int = 512, nshots: int = 16, side_lo: int = 24, side_hi: in
     return FWIBatch("fwi_batch_%dshots_%dcube" % (nshots, n), (n, n, n), (h, h, h), so, nbl, dt,
                     nt, ckpt_every, vmax, shapes, origins, srcs, recs, q, profile=prof,
                     anomaly=(0.6, 0.5, 0.5, sigma, 300.0))
+
+
+@dataclass
+class Learned:
+    """Learned-correction workload: a fine high-order grid and a 2x coarser
+    low-order grid over the same region, with models, source and receivers
+    on coarse nodes (which are also fine nodes)."""
+    name: str
+    n_fine: int
+    h_fine: float
+    so_fine: int
+    so_coarse: int
+    nbl_fine: int
+    dt_fine: float
+    nt_fine: int
+    vmax: float
+    src_idx: tuple          # fine-grid index of the source (even)
+    rec_z: int              # fine-grid depth index of the receiver line (even)
+    f0: float
+    train_seeds: list
+    test_seeds: list
+
+    @property
+    def n_coarse(self):
+        return self.n_fine // 2
+
+    @property
+    def h_coarse(self):
+        return 2 * self.h_fine
+
+    @property
+    def dt_coarse(self):
+        return 2 * self.dt_fine
+
+    @property
+    def nt_coarse(self):
+        return self.nt_fine // 2
+
+    @property
+    def nbl_coarse(self):
+        return self.nbl_fine // 2
+
+    def velocity(self, seed: int) -> np.ndarray:
+        """Fine-grid model: layered (8-12 layers) plus 0-3 Gaussian anomalies of
+        +-10-20 %, sigma 8-24 fine cells, clipped to [1500, 4500] m/s."""
+        n = self.n_fine
+        v = np.broadcast_to(layered_profile(n, seed).reshape(-1, 1, 1), (n, n, n)).astype(np.float64)
+        rng = np.random.default_rng(seed + 100000)
+        k = int(rng.integers(0, 4))
+        zz = np.arange(n)[:, None, None]
+        yy = np.arange(n)[None, :, None]
+        xx = np.arange(n)[None, None, :]
+        for _ in range(k):
+            c = rng.uniform(0.2 * n, 0.8 * n, 3)
+            sig = rng.uniform(8, 24) * n / 256.0
+            amp = rng.uniform(0.10, 0.20) * rng.choice([-1.0, 1.0])
+            g = np.exp(-((zz - c[0]) ** 2 + (yy - c[1]) ** 2 + (xx - c[2]) ** 2) / (2 * sig * sig))
+            v = v * (1.0 + amp * g)
+        return np.clip(v, 1500.0, 4500.0).astype(np.float32)
+
+    def src_fine(self):
+        return np.array([[i * self.h_fine for i in self.src_idx]])
+
+    def rec_fine(self):
+        n = self.n_fine
+        return np.array([[self.rec_z * self.h_fine, (n // 2) * self.h_fine, 2 * i * self.h_fine]
+                         for i in range(n // 2)])
+
+    def q_fine(self):
+        return ricker(self.nt_fine, self.dt_fine, self.f0)[:, None]
+
+    def q_coarse(self):
+        return ricker(self.nt_coarse, self.dt_coarse, self.f0)[:, None]
+
+
+def cfg_learned(n_fine: int = 256, nt_fine: int = 1000, ntrain: int = 64, ntest: int = 8) -> Learned:
+    """Fine 256^3 (h = 10 m, so 8, 40-point layer, dt at 0.5 CFL) and coarse
+    128^3 (h = 20 m, so 4, 20-point layer, 2 dt); 1000 fine / 500 coarse
+    steps; 15 Hz Ricker near the top centre; 128 receivers on coarse nodes
+    near the top; training seeds 5000.., held-out seeds 5100.."""
+    h = 10.0
+    vmax = 4500.0
+    dt = stable_dt(8, 3, h, vmax)
+    s = n_fine / 256.0
+    src = (2 * round(24 * s), n_fine // 2, n_fine // 2)
+    return Learned("learned_%dfine_%dcoarse" % (n_fine, n_fine // 2), n_fine, h, 8, 4,
+                   2 * round(20 * s), dt, nt_fine, vmax, src, 2 * round(26 * s), 15.0,
+                   list(range(5000, 5000 + ntrain)), list(range(5100, 5100 + ntest)))

@@ -184,8 +184,8 @@ def test_mse_and_adam():
     net.loss.zero_()
     nz, ny, nx = SHAPE
     tt = torch.from_numpy(t.ravel()).cuda()
-    nn._chk(nn.lib().nn_mse(nz, ny, nx, nn._p(net.y), nn._p(tt), nn._p(net.g8), nn._p(net.loss),
-                            nn._s()))
+    nn._chk(nn.lib().nn_mse(nz, ny, nx, nn._p(net.y), nn._p(tt), None, nn._p(net.g8),
+                            nn._p(net.loss), nn._s()))
     torch.cuda.synchronize()
     assert abs(net.loss.item() - N.mse(y.astype(np.float64), t)) <= 1e-5 * N.mse(y, t)
     g = _from_bits(net.g8, 8)
