@@ -74,6 +74,148 @@ def cpu_baseline(c, budget_s):
                       "(%.1f s)" % ("x".join(map(str, c.shape)), nt, c.nt, dt)}
 
 
+def bench_tti(args):
+    """Pseudo-acoustic TTI, 384^3, so 12, 500 steps (Gpts/s; the step is the
+    two rotated-operator passes)."""
+    import torch
+
+    from paper_2312_13094_amd import fd, synth
+    n = args.n if args.n != 512 else 384
+    c = synth.cfg_tti(n=n, nt=args.nt)
+    g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, physics=fd.FD_TTI,
+                eps_max=c.eps_max)
+    f = {k: torch.from_numpy(v).cuda() for k, v in c.fields.items()}
+    g.set_model(f["v"], [f["eps"], f["delta"], f["theta"], f["phi"]])
+    del f
+    st = [g.field() for _ in range(4)]
+    S, R = g.sparse(c.src), g.sparse(c.rec)
+    q = torch.from_numpy(c.q).cuda()
+    d = torch.zeros((c.nt, R.n), device="cuda")
+    for _ in range(args.warmup):
+        g.forward(st, S, q, R, d, c.nt)
+    torch.cuda.synchronize()
+    g.profile_begin(args.steps * c.nt)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.forward(st, S, q, R, d, c.nt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, nl = g.profile_end()
+    gpts = c.points * c.nt * args.steps / wall / 1e9
+    avg = kms / max(nl, 1)
+    alg = 44 * c.points
+    return {"metric": "Gpts/s, 3D so-12 TTI", "value": round(gpts, 3), "unit": "Gpts/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": c.name + "_%dsteps" % c.nt, "shape": list(c.shape),
+                       "space_order": c.so, "time_steps": c.nt},
+            "roofline": {"bound": "hbm", "achieved": round(alg / (avg * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": "k_tti_pass1 + k_tti_pass2 (one step)",
+                         "avg_launch_ms": round(avg, 5), "launches_timed": nl,
+                         "algorithmic_bytes_per_launch": alg}}
+
+
+def bench_fwi(args):
+    """Batched FWI gradient: 16 shots, apertures 192^3..320^3 inside a 512^3
+    layered + anomaly model, so 8, 800 steps, checkpoint every 50, one graph."""
+    import numpy as np
+    import torch
+
+    from paper_2312_13094_amd import fd, synth
+    c = synth.cfg_fwi_batch(nt=args.nt if args.nt != 500 else 800)
+    vtrue = torch.from_numpy(c.true_velocity()).cuda()
+    ns = len(c.shapes)
+    dobs = []
+    for s in range(ns):   # observed data from the true model, one shot at a time
+        g = fd.Grid(c.shapes[s], c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl)
+        sl = tuple(slice(o, o + n) for o, n in zip(c.origins[s], c.shapes[s]))
+        g.set_model(vtrue[sl].contiguous())
+        S, R = g.sparse(c.src[s]), g.sparse(c.rec[s])
+        d = torch.zeros((c.nt, R.n), device="cuda")
+        g.forward([g.field(), g.field()], S, torch.from_numpy(c.q).cuda(), R, d, c.nt)
+        dobs.append(d)
+        g.close()
+    del vtrue
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    b = fd.Batch(c.spacing, c.so, c.dt, c.vmax, c.nbl, c.shapes, c.origins, c.full_shape, c.nt,
+                 c.ckpt_every)
+    for s in range(ns):
+        b.set_geometry(s, c.src[s], c.rec[s])
+    vstart = torch.from_numpy(c.start_velocity()).cuda()
+    b.set_model(vstart)
+    q = [torch.from_numpy(c.q).cuda() for _ in range(ns)]
+    d = [torch.zeros_like(x) for x in dobs]
+    gv = torch.zeros(c.full_shape, device="cuda")
+    b.gradient(q, dobs, d, gv)      # capture + instantiate + first run (warm-up)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t_setup
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.gradient(q, dobs, d, gv)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    pts = sum(int(np.prod(s)) for s in c.shapes)
+    fz, fy, fx = (int(0.6 * c.full_shape[0]), c.full_shape[1] // 2, c.full_shape[2] // 2)
+    anomaly = float(gv[fz - 5:fz + 6, fy - 5:fy + 6, fx - 5:fx + 6].sum().item())
+    return {"metric": "FWI gradient wall time, 16 uneven shots (effective Gpts/s)",
+            "value": round(pts * c.nt / wall / 1e9, 3), "unit": "Gpts/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": c.name, "shots": ns, "aperture_sides": [s[0] for s in c.shapes],
+                       "time_steps": c.nt, "ckpt_every": c.ckpt_every,
+                       "device_gib": round(b.device_bytes / 2 ** 30, 1),
+                       "setup_s": round(setup, 2),
+                       "gradient_sum_over_anomaly": anomaly}}
+
+
+def bench_learned(args):
+    """Learned coarse correction vs the plain fine solve: train on solver data,
+    then time both on held-out models and report trace errors."""
+    import numpy as np
+    import torch
+
+    from paper_2312_13094_amd import learned as LC
+    from paper_2312_13094_amd import synth
+    c = synth.cfg_learned(ntrain=args.train_models, ntest=8)
+    lc = LC.LearnedCorrector(c)
+    models = []
+    steps = list(range(20, c.nt_coarse - 2, 20))
+    t0 = time.perf_counter()
+    train = lc.make_samples(c.train_seeds, steps, models)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lc.train(train, models, iters=args.train_iters, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rows = []
+    for seed in c.test_seeds:
+        lc.set_model(c.velocity(seed))
+        ref, t_fine, _ = lc.fine_solve()
+        plain, t_plain = lc.coarse_solve()
+        res = lc.learned_solve()
+        rows.append((LC.trace_error(plain, ref), LC.trace_error(res.traces, ref), t_fine,
+                     res.seconds, t_plain, res.fallback))
+    r = np.array([x[:5] for x in rows])
+    return {"metric": "learned vs plain time at same err (wall ms, held-out mean)",
+            "value": round(float(r[:, 3].mean() * 1e3), 3), "unit": "ms",
+            "n_gpus": 1, "steps": len(rows), "warmup": 0,
+            "ms_per_step": round(float(r[:, 3].mean() * 1e3), 3), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
+            "config": {"workload": c.name, "fine_ms": round(float(r[:, 2].mean() * 1e3), 3),
+                       "plain_coarse_ms": round(float(r[:, 4].mean() * 1e3), 3),
+                       "trace_err_learned": [round(float(x), 4) for x in r[:, 1]],
+                       "trace_err_plain_coarse": [round(float(x), 4) for x in r[:, 0]],
+                       "fallbacks": int(sum(x[5] for x in rows)),
+                       "train_models": args.train_models, "train_iters": args.train_iters,
+                       "samples": len(train), "data_s": round(t_data, 1),
+                       "train_s": round(t_train, 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +228,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 2 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--workload", default="acoustic",
+                    choices=["acoustic", "tti", "fwi", "learned"],
+                    help="acoustic = the headline line; the others print their own line")
+    ap.add_argument("--train-models", type=int, default=64)
+    ap.add_argument("--train-iters", type=int, default=3000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -93,15 +240,21 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload != "acoustic":
+        fn = {"tti": bench_tti, "fwi": bench_fwi, "learned": bench_learned}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
+
     import torch
 
     from paper_2312_13094_amd import fd, synth
 
     dev = torch.device("cuda", 0)
     if args.calibrate_copy:
-        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)   # 2 GiB read, 2 GiB write
+        # the library's plain copy kernel over 2 GiB: reference for HBM counters
+        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        fd.copy_floats(dst, src)
         torch.cuda.synchronize()
         del src, dst
     c = synth.cfg_3d_layered(n=args.n, nt=args.nt)

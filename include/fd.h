@@ -108,11 +108,24 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
 
 /* Select the 3-D step kernel's tile: blocks of 64 x by threads, each thread
  * computing ry consecutive rows (tile 64 x by*ry points), nzb planes per
- * block, xcd != 0 remaps blocks so each XCD sweeps a contiguous tile range.
- * by = 0 selects the one-thread-per-point kernel.  Supported (by, ry):
- * (4,1) (4,2) (4,4) (4,8) (8,2) (8,4) (2,8).  Results do not depend on the
- * tile (same arithmetic per point). */
-int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd);
+ * block.  flags (0..7): bit 0 remaps blocks so each XCD sweeps a contiguous
+ * tile range, bit 1 keeps two planes of loads in flight instead of one,
+ * bit 2 stores u+ with the non-temporal hint.  by = 0 selects the
+ * one-thread-per-point kernel.  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
+ * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
+ * arithmetic per point). */
+int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int flags);
+
+/* Autotuner: pick the 3-D step kernel's tile for this handle by timed
+ * search (each candidate (by, ry, nzb, xcd) launched a few times on scratch
+ * fields of this handle's shape, fastest kept), then apply it.  With
+ * cache_path non-NULL the choice is looked up first in that JSON file (an
+ * object mapping "arch|so|nz|ny|nx" to [by, ry, nzb, xcd]) and appended on
+ * a miss.  Writes the chosen tile to out4 (may be NULL) and the best
+ * measured milliseconds per launch to ms_out (may be NULL; 0 on a cache
+ * hit).  Allocates two scratch fields for the search (setup call);
+ * synchronises `stream`.  2-D grids keep the one-thread-per-point kernel. */
+int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, void *stream);
 
 /* Multilinear weights of sparse points (paper, "Sparse data" paragraph:
  * injection and interpolation at points off the grid).  coords_m is host
@@ -202,6 +215,12 @@ int fd_unpack_halo(const fd_grid *g, float *field_dev, unsigned face_mask,
  * memory. */
 int fd_profile_begin(fd_grid *g, int max_launches);
 int fd_profile_end(fd_grid *g, double *total_ms, int *launches);
+
+/* dst[0..n) = src[0..n) on the device (float4 streaming kernel when both
+ * pointers are 16-byte aligned and n % 4 == 0).  Used for checkpoint copies
+ * (a kernel, so graph captures stay free of copy nodes) and as the plain
+ * copy of known size that calibrates HBM byte counters. */
+int fd_copy_floats(float *dst_dev, const float *src_dev, int64_t n, void *stream);
 
 /* Thread-local description of the calling thread's last error ("" if none). */
 const char *fd_last_error(void);

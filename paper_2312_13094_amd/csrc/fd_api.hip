@@ -267,7 +267,7 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     make_geometry(d, g->ndim, g->n, g->h, r, g->L, g->sp);
     const fd_layout &L = g->L;
 
-    g->tune = d.ndim == 3 ? Tuning{4, 4, 64, 1} : Tuning{0, 0, 0, 0};
+    g->tune = d.ndim == 3 ? Tuning{4, 4, 64, 0} : Tuning{0, 0, 0, 0};
 
     DeviceGuard dg(d.device);
     if (!dg.ok()) {
@@ -334,8 +334,9 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
     if (g->ndim != 3) return set_error(FD_EINVAL, "tiles apply to 3-D grids");
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
                        (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
-    if (!known || nzb < 1) return set_error(FD_EINVAL, "unsupported tile shape");
-    g->tune = Tuning{by, ry, nzb, xcd ? 1 : 0};
+    if (!known || nzb < 1 || xcd < 0 || xcd > 7)
+        return set_error(FD_EINVAL, "unsupported tile shape");
+    g->tune = Tuning{by, ry, nzb, xcd};
     return FD_OK;
 }
 
@@ -442,9 +443,7 @@ static int forward_tti(fd_grid *g, float *const *st, SparseArgs inj, SparseArgs 
             const float *src4[4] = {p, pm, r, rm};
             for (int i = 0; i < 4; ++i) {
                 if (!c[i]) return set_error(FD_EINVAL, "fd_forward: null checkpoint buffer");
-                if (hipMemcpyAsync(c[i], src4[i], g->L.field_bytes, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess)
-                    return set_error(FD_EDEVICE, "checkpoint copy failed");
+                if ((rc = launch_copy(c[i], src4[i], g->L.field_elems, s))) return rc;
             }
         }
         const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
@@ -503,9 +502,9 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
         if (ckpt_dev && n % ckpt_every == 0) {
             float *c0 = ckpt_dev[2 * (n / ckpt_every)], *c1 = ckpt_dev[2 * (n / ckpt_every) + 1];
             if (!c0 || !c1) return set_error(FD_EINVAL, "fd_forward: null checkpoint buffer");
-            if (hipMemcpyAsync(c0, cur, g->L.field_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(c1, prev, g->L.field_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return set_error(FD_EDEVICE, "checkpoint copy failed");
+            if ((rc = launch_copy(c0, cur, g->L.field_elems, s)) ||
+                (rc = launch_copy(c1, prev, g->L.field_elems, s)))
+                return rc;
         }
         if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, cur, s))) return rc;
         if ((rc = timed_step(g, cur, prev, prev, s))) return rc;
@@ -566,11 +565,9 @@ int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const 
             // recompute u^(lo-1) .. u^hi into slots 0 .. hi-lo+1
             float *c0 = ckpt_dev[2 * j], *c1 = ckpt_dev[2 * j + 1];
             if (!c0 || !c1) return set_error(FD_EINVAL, "fd_adjoint: null checkpoint buffer");
-            if (hipMemcpyAsync(slot_dev[1], c0, g->L.field_bytes, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess ||
-                hipMemcpyAsync(slot_dev[0], c1, g->L.field_bytes, hipMemcpyDeviceToDevice, s) !=
-                    hipSuccess)
-                return set_error(FD_EDEVICE, "checkpoint restore failed");
+            if ((rc = launch_copy(slot_dev[1], c0, g->L.field_elems, s)) ||
+                (rc = launch_copy(slot_dev[0], c1, g->L.field_elems, s)))
+                return rc;
             for (int i = 0; i < hi - lo; ++i) {
                 float *cur = slot_dev[i + 1], *prv = slot_dev[i], *out = slot_dev[i + 2];
                 if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, cur, s)))
@@ -619,6 +616,137 @@ int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *gr
     if (!g->model_loaded) return set_error(FD_EINVAL, "no model loaded");
     DeviceGuard dg(g->d.device);
     return launch_grad_to_vel(g, grad_m_dev, grad_v_dev, (hipStream_t)stream);
+}
+
+// -- autotuner ---------------------------------------------------------------
+
+static std::string tune_key(const fd_grid *g)
+{
+    hipDeviceProp_t prop{};
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, g->d.device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    return arch + "|" + std::to_string(g->d.space_order) + "|" + std::to_string(g->n[0]) + "|" +
+           std::to_string(g->n[1]) + "|" + std::to_string(g->n[2]);
+}
+
+// read "key": [a, b, c, d] from a flat JSON object written by tune_store
+static bool tune_lookup(const char *path, const std::string &key, int t[4])
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+    std::fclose(f);
+    const std::string pat = "\"" + key + "\"";
+    const size_t at = txt.find(pat);
+    if (at == std::string::npos) return false;
+    return std::sscanf(txt.c_str() + at + pat.size(), " : [ %d , %d , %d , %d ]", &t[0], &t[1],
+                       &t[2], &t[3]) == 4;
+}
+
+static void tune_store(const char *path, const std::string &key, const int t[4])
+{
+    std::string txt;
+    if (FILE *f = std::fopen(path, "r")) {
+        char buf[4096];
+        size_t n;
+        while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+        std::fclose(f);
+    }
+    const size_t close = txt.rfind('}');
+    std::string body = close == std::string::npos ? std::string() : txt.substr(0, close);
+    while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
+    char entry[256];
+    std::snprintf(entry, sizeof entry, "  \"%s\": [%d, %d, %d, %d]", key.c_str(), t[0], t[1], t[2],
+                  t[3]);
+    if (body.empty() || body == "{") body = "{\n" + std::string(entry);
+    else body += ",\n" + std::string(entry);
+    body += "\n}\n";
+    const std::string tmp = std::string(path) + ".tmp";
+    if (FILE *f = std::fopen(tmp.c_str(), "w")) {
+        std::fwrite(body.data(), 1, body.size(), f);
+        std::fclose(f);
+        std::rename(tmp.c_str(), path);
+    }
+}
+
+int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, void *stream)
+{
+    if (!g) return set_error(FD_EINVAL, "fd_autotune: null handle");
+    if (g->ndim != 3 || g->d.physics != FD_ACOUSTIC) {
+        if (out4) out4[0] = out4[1] = out4[2] = out4[3] = 0;
+        if (ms_out) *ms_out = 0.0;
+        return FD_OK;
+    }
+    if (!g->model_loaded) return set_error(FD_EINVAL, "fd_autotune: load a model first");
+    DeviceGuard dg(g->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = tune_key(g);
+    int best[4] = {g->tune.by, g->tune.ry, g->tune.nzb, g->tune.flags};
+    if (cache_path && tune_lookup(cache_path, key, best) &&
+        fd_set_tile(g, best[0], best[1], best[2], best[3]) == FD_OK) {
+        if (out4) std::memcpy(out4, best, sizeof best);
+        if (ms_out) *ms_out = 0.0;
+        return FD_OK;
+    }
+    float *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, g->L.field_bytes) != hipSuccess || hipMalloc(&b, g->L.field_bytes) != hipSuccess) {
+        (void)hipFree(a);
+        return set_error(FD_ENOMEM, "fd_autotune: scratch allocation failed");
+    }
+    (void)hipMemsetAsync(a, 0, g->L.field_bytes, s);
+    (void)hipMemsetAsync(b, 0, g->L.field_bytes, s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const Tuning saved = g->tune;
+    const int cand[7][2] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {2, 8}};
+    const int nzbs[3] = {32, 64, 128};
+    double best_ms = 1e30;
+    int rc = FD_OK;
+    for (const auto &c : cand)
+        for (int nzb : nzbs)
+            for (int xcd = 0; xcd < 8; ++xcd) {
+                g->tune = Tuning{c[0], c[1], nzb, xcd};
+                if ((rc = launch_step(g, a, b, b, s))) break;   // warm-up
+                (void)hipEventRecord(e0, s);
+                for (int i = 0; i < 3; ++i)
+                    if ((rc = launch_step(g, i % 2 ? b : a, i % 2 ? a : b, i % 2 ? a : b, s))) break;
+                (void)hipEventRecord(e1, s);
+                if (rc || hipEventSynchronize(e1) != hipSuccess) break;
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms / 3.0 < best_ms) {
+                    best_ms = ms / 3.0;
+                    best[0] = c[0];
+                    best[1] = c[1];
+                    best[2] = nzb;
+                    best[3] = xcd;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    g->tune = saved;
+    if (rc) return rc;
+    fd_set_tile(g, best[0], best[1], best[2], best[3]);
+    if (cache_path) tune_store(cache_path, key, best);
+    if (out4) std::memcpy(out4, best, sizeof best);
+    if (ms_out) *ms_out = best_ms;
+    return FD_OK;
+}
+
+int fd_copy_floats(float *dst_dev, const float *src_dev, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!dst_dev || !src_dev))) return set_error(FD_EINVAL, "fd_copy_floats: bad argument");
+    return launch_copy(dst_dev, src_dev, n, (hipStream_t)stream);
 }
 
 int fd_profile_begin(fd_grid *g, int max_launches)

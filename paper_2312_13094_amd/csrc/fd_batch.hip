@@ -32,7 +32,7 @@ struct fd_batch {
     int64_t full[3] = {0, 0, 0};
     std::vector<ShotHost> sh;
     fd::BatchShot *table = nullptr;
-    fd::Tuning tune{4, 4, 64, 1};
+    fd::Tuning tune{4, 4, 64, 0};
     int total_blocks = 0;
     const float *vel_full = nullptr;
     unsigned *scratch = nullptr;
@@ -269,10 +269,11 @@ int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int xcd)
     if (!b) return set_error(FD_EINVAL, "fd_batch_set_tile: null handle");
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
                        (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
-    if (!known || nzb < 1) return set_error(FD_EINVAL, "unsupported tile shape");
+    if (!known || nzb < 1 || xcd < 0 || xcd > 7)
+        return set_error(FD_EINVAL, "unsupported tile shape");
     DeviceGuard dg(b->d.device);
     drop_graph(b);
-    b->tune = Tuning{by, ry, nzb, xcd ? 1 : 0};
+    b->tune = Tuning{by, ry, nzb, xcd & 7};
     layout_blocks(b);
     return FD_OK;
 }

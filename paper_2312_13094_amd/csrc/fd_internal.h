@@ -79,8 +79,10 @@ struct Tuning {
     int by;        // waves per block (block = 64 x by threads)
     int ry;        // rows per thread (tile height = by * ry)
     int nzb;       // planes per block (z chunk)
-    int xcd;       // 1: XCD-aware block remap
+    int flags;     // bit 0: XCD-aware block remap; bit 1: prefetch two planes
+                   // ahead; bit 2: non-temporal stores of u+
 };
+constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4;
 
 // One set of sparse points bound to a step.
 struct SparseArgs {
@@ -155,6 +157,7 @@ int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *cons
 int launch_unpack(const fd_grid *g, float *field, unsigned mask, const float *const *buf,
                   hipStream_t s);
 int launch_swap(float *a, float *b, int64_t n, hipStream_t s);
+int launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 int launch_build_vdt2(const fd_grid *g, const float *vel, float *vdt2, unsigned *vmax_bits,
                       hipStream_t s);
 int launch_imaging(const fd_grid *g, const float *lam, const float *up, const float *u0,

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_acoustic_simple(const float *__restrict
     up[i] = c + ((1.0f - a) * (c - um[i]) + vdt2[i] * lap) / (1.0f + a);
 }
 
-template <int R, int BY, int RY>
+template <int R, int BY, int RY, int PF, bool NTS>
 __global__ __launch_bounds__(64 * BY) void k_acoustic_zmarch(
     const float *__restrict__ u, const float *um, float *up, const float *__restrict__ vdt2,
     const StepParams p, const int ntx, const int nty, const int nzb, const int remap)
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(64 * BY) void k_acoustic_zmarch(
     const int ty = b % nty;
     const int zc = b / nty;
 
-    zmarch_body<R, BY, RY>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
+    zmarch_body<R, BY, RY, PF, NTS>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -120,17 +120,28 @@ int launch_step_simple(const fd_grid *g, const float *u, const float *um, float 
     return check_launch("acoustic step (simple)");
 }
 
-template <int R, int BY, int RY>
-static void zmarch(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+template <int R, int BY, int RY, int PF, bool NTS>
+static void zmarch_v(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
 {
     const StepParams &p = g->sp;
     constexpr int TY = BY * RY;
     const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
     const int ntx = (p.nx + 63) / 64, nty = (p.ny + TY - 1) / TY, nzc = (p.nz + nzb - 1) / nzb;
     const unsigned nb = (unsigned)ntx * nty * nzc;
-    const int remap = (g->tune.xcd && nb % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s, u, um, up,
-                       g->vdt2, p, ntx, nty, nzb, remap);
+    const int remap = ((g->tune.flags & kTileXcd) && nb % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS>), dim3(nb), dim3(64, BY), 0, s, u,
+                       um, up, g->vdt2, p, ntx, nty, nzb, remap);
+}
+
+template <int R, int BY, int RY>
+static void zmarch(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+{
+    const int f = g->tune.flags;
+    const bool pf2 = f & kTilePf2, nts = f & kTileNts;
+    if (pf2 && nts) zmarch_v<R, BY, RY, 2, true>(g, u, um, up, s);
+    else if (pf2) zmarch_v<R, BY, RY, 2, false>(g, u, um, up, s);
+    else if (nts) zmarch_v<R, BY, RY, 1, true>(g, u, um, up, s);
+    else zmarch_v<R, BY, RY, 1, false>(g, u, um, up, s);
 }
 
 template <int R>

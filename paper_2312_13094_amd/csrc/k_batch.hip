@@ -12,7 +12,7 @@
 
 namespace fd {
 
-template <int R, int BY, int RY>
+template <int R, int BY, int RY, int PF, bool NTS>
 __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__restrict__ shots,
                                                           const int nshots, const int total,
                                                           const int iu, const int ium,
@@ -34,18 +34,29 @@ __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__res
     const int zc = lb / S.nty;
     float *base = S.base;
     const int64_t st = S.stride;
-    zmarch_body<R, BY, RY>(base + iu * st, base + ium * st, base + iup * st, base + kVdt2 * st,
-                           S.p, tx, ty, zc, nzb, lds);
+    zmarch_body<R, BY, RY, PF, NTS>(base + iu * st, base + ium * st, base + iup * st,
+                                    base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
+}
+
+template <int R, int BY, int RY, int PF, bool NTS>
+static void batch_step_v(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+                         int ium, int iup, hipStream_t s)
+{
+    const int remap = (t.flags & kTileXcd) ? 1 : 0;
+    const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
+    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, PF, NTS>), dim3(nb), dim3(64, BY), 0, s, shots,
+                       nshots, total, iu, ium, iup, t.nzb, remap);
 }
 
 template <int R, int BY, int RY>
 static void batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
                        int ium, int iup, hipStream_t s)
 {
-    const int remap = t.xcd ? 1 : 0;
-    const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
-    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s, shots, nshots,
-                       total, iu, ium, iup, t.nzb, remap);
+    const bool pf2 = t.flags & kTilePf2, nts = t.flags & kTileNts;
+    if (pf2 && nts) batch_step_v<R, BY, RY, 2, true>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (pf2) batch_step_v<R, BY, RY, 2, false>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (nts) batch_step_v<R, BY, RY, 1, true>(shots, nshots, total, t, iu, ium, iup, s);
+    else batch_step_v<R, BY, RY, 1, false>(shots, nshots, total, t, iu, ium, iup, s);
 }
 
 template <int R>

@@ -16,8 +16,12 @@ struct FaceJob {
     int cnt[6][3];        // slab extent (z, y, x)
     int start[6][3];      // DOMAIN coordinate of the slab origin
     int elems[6];
+    int vec[6];           // 1: rows are whole float4 chunks on both sides
 };
 
+// One face per blockIdx.y; rows along x are copied as float4 chunks when the
+// slab's x extent and origin are multiples of 4 (rows of a padded field are
+// 128-byte aligned, buffers are dense), else element by element.
 template <bool UNPACK>
 __global__ __launch_bounds__(256) void k_faces(float *field, const FaceJob job,
                                                const int64_t offset, const int64_t PY,
@@ -29,6 +33,23 @@ __global__ __launch_bounds__(256) void k_faces(float *field, const FaceJob job,
     const int c1 = job.cnt[f][1], c2 = job.cnt[f][2];
     const int sz = job.start[f][0], sy = job.start[f][1], sx = job.start[f][2];
     float *buf = job.buf[f];
+    if (job.vec[f]) {
+        const int q2 = c2 >> 2;                 // float4 chunks per row
+        const int nq = n >> 2;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += gridDim.x * blockDim.x) {
+            const int i2 = e % q2;
+            const int t = e / q2;
+            const int i1 = t % c1;
+            const int i0 = t / c1;
+            const int64_t idx =
+                offset + (int64_t)(sz + i0) * PZ + (int64_t)(sy + i1) * PY + (sx + 4 * i2);
+            float4 *fp = reinterpret_cast<float4 *>(field + idx);
+            float4 *bp = reinterpret_cast<float4 *>(buf) + e;
+            if (UNPACK) *fp = *bp;
+            else *bp = *fp;
+        }
+        return;
+    }
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int i2 = e % c2;
         const int t = e / c2;
@@ -55,7 +76,10 @@ static void face_job(const fd_grid *g, unsigned mask, bool halo_side, FaceJob &j
             job.start[f][a] = st[a];
         }
         job.elems[f] = active ? cnt[0] * cnt[1] * cnt[2] : 0;
-        if (job.elems[f] > maxe) maxe = job.elems[f];
+        // DOMAIN x = 0 sits at a multiple of 4 floats in every row
+        job.vec[f] = (cnt[2] % 4 == 0 && ((st[2] % 4) + 4) % 4 == 0) ? 1 : 0;
+        const int work = job.vec[f] ? job.elems[f] / 4 : job.elems[f];
+        if (work > maxe) maxe = work;
     }
 }
 
@@ -95,6 +119,36 @@ __global__ __launch_bounds__(256) void k_swap(float4 *a, float4 *b, int64_t n4)
         a[i] = b[i];
         b[i] = t;
     }
+}
+
+__global__ __launch_bounds__(256) void k_copy4(float4 *dst, const float4 *src, int64_t n4)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_copy1(float *dst, const float *src, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+int launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return FD_OK;
+    if (n % 4 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(src) % 16 == 0) {
+        const int64_t n4 = n / 4;
+        const int nb = (int)std::min<int64_t>((n4 + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_copy4, dim3(nb), dim3(256), 0, s, reinterpret_cast<float4 *>(dst),
+                           reinterpret_cast<const float4 *>(src), n4);
+    } else {
+        const int nb = (int)std::min<int64_t>((n + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_copy1, dim3(nb), dim3(256), 0, s, dst, src, n);
+    }
+    return check_launch("copy");
 }
 
 // n must be a multiple of 4 and both pointers 16-byte aligned (padded fields are)

@@ -21,8 +21,10 @@ struct ZTile {
 
 // One block's z-march over tile (tx, ty) and z chunk zc of a grid described
 // by p; u -> up with up possibly aliasing um (in place).  `lds` holds
-// ZTile<R,BY,RY>::LDS floats.
-template <int R, int BY, int RY>
+// ZTile<R,BY,RY>::LDS floats.  PF planes of loads are kept in flight ahead of
+// the plane being computed; NTS stores u+ with the non-temporal hint (it is
+// not read again in this step).
+template <int R, int BY, int RY, int PF, bool NTS>
 __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const float *um,
                                             float *up, const float *__restrict__ vdt2,
                                             const StepParams &p, const int tx, const int ty,
@@ -94,76 +96,85 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
             q[j][k + 1] = rl[j] ? uo[(int64_t)(z0 - R + k) * PZ + col] : 0.0f;
     }
 
-    // prefetch registers for the next plane
-    float nf[RY], nm[RY], nv[RY], nhy[HY], nhx[HX];
-    auto prefetch = [&](int z) {
+    // PF slots of prefetched loads; slot d holds plane z with z - z0 == d mod PF
+    float nf[PF][RY], nm[PF][RY], nv[PF][RY], nhy[PF][HY], nhx[PF][HX];
+    auto prefetch = [&](const int z, const int d) {
         const int64_t pz = (int64_t)z * PZ;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int64_t col = (int64_t)(yb + j) * PY + x;
-            nf[j] = rl[j] ? uo[pz + R * PZ + col] : 0.0f;
-            nm[j] = ro[j] ? umo[pz + col] : 0.0f;
-            nv[j] = ro[j] ? vo[pz + col] : 0.0f;
+            nf[d][j] = rl[j] ? uo[pz + R * PZ + col] : 0.0f;
+            nm[d][j] = ro[j] ? umo[pz + col] : 0.0f;
+            nv[d][j] = ro[j] ? vo[pz + col] : 0.0f;
         }
 #pragma unroll
-        for (int k = 0; k < HY; ++k) nhy[k] = hyk[k] ? uo[pz + hyo[k]] : 0.0f;
+        for (int k = 0; k < HY; ++k) nhy[d][k] = hyk[k] ? uo[pz + hyo[k]] : 0.0f;
 #pragma unroll
-        for (int k = 0; k < HX; ++k) nhx[k] = hxk[k] ? uo[pz + hxo[k]] : 0.0f;
+        for (int k = 0; k < HX; ++k) nhx[d][k] = hxk[k] ? uo[pz + hxo[k]] : 0.0f;
     };
-    if (z0 < z1) prefetch(z0);
+#pragma unroll
+    for (int d = 0; d < PF; ++d)
+        if (z0 + d < z1) prefetch(z0 + d, d);
 
-    for (int z = z0; z < z1; ++z) {
-        float cm[RY], cv[RY], chy[HY], chx[HX];
+    const float ax = p.nbl > 0 ? sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+    for (int zb = z0; zb < z1; zb += PF) {
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
+        for (int d = 0; d < PF; ++d) {
+            const int z = zb + d;
+            if (z < z1) {
+                float cm[RY], cv[RY], chy[HY], chx[HX];
 #pragma unroll
-            for (int k = 0; k < 2 * R; ++k) q[j][k] = q[j][k + 1];
-            q[j][2 * R] = nf[j];
-            cm[j] = nm[j];
-            cv[j] = nv[j];
-        }
+                for (int j = 0; j < RY; ++j) {
 #pragma unroll
-        for (int k = 0; k < HY; ++k) chy[k] = nhy[k];
+                    for (int k = 0; k < 2 * R; ++k) q[j][k] = q[j][k + 1];
+                    q[j][2 * R] = nf[d][j];
+                    cm[j] = nm[d][j];
+                    cv[j] = nv[d][j];
+                }
 #pragma unroll
-        for (int k = 0; k < HX; ++k) chx[k] = nhx[k];
-        if (z + 1 < z1) prefetch(z + 1);
+                for (int k = 0; k < HY; ++k) chy[k] = nhy[d][k];
+#pragma unroll
+                for (int k = 0; k < HX; ++k) chx[k] = nhx[d][k];
+                if (z + PF < z1) prefetch(z + PF, d);
 
-        float *t = lds + (z & 1) * (LY * LX);
+                float *t = lds + (z & 1) * (LY * LX);
 #pragma unroll
-        for (int j = 0; j < RY; ++j) t[(wy * RY + j + R) * LX + lane + R] = q[j][R];
+                for (int j = 0; j < RY; ++j) t[(wy * RY + j + R) * LX + lane + R] = q[j][R];
 #pragma unroll
-        for (int k = 0; k < HY; ++k)
-            if (tid + k * NT < NHY) t[hys[k]] = chy[k];
+                for (int k = 0; k < HY; ++k)
+                    if (tid + k * NT < NHY) t[hys[k]] = chy[k];
 #pragma unroll
-        for (int k = 0; k < HX; ++k)
-            if (tid + k * NT < NHX) t[hxs[k]] = chx[k];
-        __syncthreads();
+                for (int k = 0; k < HX; ++k)
+                    if (tid + k * NT < NHX) t[hxs[k]] = chx[k];
+                __syncthreads();
 
-        const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
-        const float ax = p.nbl > 0 ? sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+                const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            const float *c = t + (wy * RY + j + R) * LX + lane + R;
-            float lz = 0.0f, ly = 0.0f, lx = 0.0f;
+                for (int j = 0; j < RY; ++j) {
+                    const float *c = t + (wy * RY + j + R) * LX + lane + R;
+                    float lz = 0.0f, ly = 0.0f, lx = 0.0f;
 #pragma unroll
-            for (int k = 1; k <= R; ++k) {
-                lz += p.cz[k] * (q[j][R + k] + q[j][R - k]);
-                ly += p.cy[k] * (c[k * LX] + c[-k * LX]);
-                lx += p.cx[k] * (c[k] + c[-k]);
+                    for (int k = 1; k <= R; ++k) {
+                        lz += p.cz[k] * (q[j][R + k] + q[j][R - k]);
+                        ly += p.cy[k] * (c[k * LX] + c[-k * LX]);
+                        lx += p.cx[k] * (c[k] + c[-k]);
+                    }
+                    const float uc = q[j][R];
+                    const float lap = p.c0 * uc + lz + ly + lx;
+                    const int y = yb + j;
+                    // same summation order as damp_a(): (z + x) + y
+                    const float ay = p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
+                    const float a = p.half_dt * ((az + ax) + ay);
+                    const float val = uc + ((1.0f - a) * (uc - cm[j]) + cv[j] * lap) / (1.0f + a);
+                    if (ro[j]) {
+                        float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + x;
+                        if (NTS) __builtin_nontemporal_store(val, dst);
+                        else *dst = val;
+                    }
+                }
             }
-            const float uc = q[j][R];
-            const float lap = p.c0 * uc + lz + ly + lx;
-            const int y = yb + j;
-            // same summation order as damp_a(): (z + x) + y
-            const float ay = p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
-            const float a = p.half_dt * ((az + ax) + ay);
-            if (ro[j])
-                upo[(int64_t)z * PZ + (int64_t)y * PY + x] =
-                    uc + ((1.0f - a) * (uc - cm[j]) + cv[j] * lap) / (1.0f + a);
         }
     }
 }
-
-
 
 }  // namespace fd

@@ -72,10 +72,12 @@ def lib():
                              vp, vp]
     L.fd_gradient_to_velocity.argtypes = [vp, vp, vp, vp]
     L.fd_sample.argtypes = [vp, vp, P(SparseC), vp, vp]
+    L.fd_autotune.argtypes = [vp, ctypes.c_char_p, P(ctypes.c_int), P(ctypes.c_double), vp]
     L.fd_halo_face_elems.argtypes = [vp, i]
     L.fd_halo_face_elems.restype = i64
     L.fd_pack_halo.argtypes = [vp, vp, ctypes.c_uint, P(vp), vp]
     L.fd_unpack_halo.argtypes = [vp, vp, ctypes.c_uint, P(vp), vp]
+    L.fd_copy_floats.argtypes = [vp, vp, i64, vp]
     L.fd_profile_begin.argtypes = [vp, i]
     L.fd_profile_end.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int)]
     L.fd_last_error.restype = ctypes.c_char_p
@@ -104,6 +106,12 @@ def _ptr_array(ts):
 def _stream(device):
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def copy_floats(dst, src, n=None):
+    """Device copy of n floats with the library's copy kernel."""
+    n = dst.numel() if n is None else n
+    _check(lib().fd_copy_floats(_ptr(dst), _ptr(src), int(n), _stream(dst.device.index or 0)))
 
 
 class SparsePoints:
@@ -192,6 +200,14 @@ class Grid:
     # -- API -----------------------------------------------------------------
     def set_tile(self, by, ry=1, nzb=64, xcd=1):
         _check(lib().fd_set_tile(self.handle, by, ry, nzb, xcd))
+
+    def autotune(self, cache_path=None):
+        """Timed tile search (or cache lookup); returns ((by, ry, nzb, xcd), ms)."""
+        t = (ctypes.c_int * 4)()
+        ms = ctypes.c_double()
+        _check(lib().fd_autotune(self.handle, cache_path.encode() if cache_path else None, t,
+                                 ctypes.byref(ms), _stream(self.device)))
+        return tuple(t), ms.value
 
     def sparse(self, coords):
         return SparsePoints(self, coords)
