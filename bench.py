@@ -184,7 +184,7 @@ def bench_learned(args):
     c = synth.cfg_learned(ntrain=args.train_models, ntest=8)
     lc = LC.LearnedCorrector(c)
     models = []
-    steps = list(range(20, c.nt_coarse - 2, 20))
+    steps = [1, 2, 3, 5, 8] + list(range(12, c.nt_coarse - 2, 12))
     t0 = time.perf_counter()
     train = lc.make_samples(c.train_seeds, steps, models)
     t_data = time.perf_counter() - t0

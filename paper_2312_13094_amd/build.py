@@ -23,17 +23,38 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-ato
          "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    subprocess.check_call([HIPCC, *FLAGS, "-c", src, "-o", obj])
+PER_RADIUS = "fd-build: one object per stencil radius"
+
+
+def _jobs(src: str):
+    """(source, extra flags, object) for one file; sources marked per-radius
+    are compiled once per stencil radius 1..8."""
+    with open(src) as f:
+        head = f.read(200)
+    base = os.path.join(BUILD, os.path.basename(src))
+    if PER_RADIUS in head:
+        return [(src, ["-DFD_RADIUS=%d" % r], base + ".r%d.o" % r) for r in range(1, 9)]
+    return [(src, [], base + ".o")]
+
+
+def _compile(job) -> str:
+    src, extra, obj = job
+    subprocess.check_call([HIPCC, *FLAGS, *extra, "-c", src, "-o", obj])
     return obj
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    jobs = [j for s in srcs for j in _jobs(s)]
+    # big objects first so the pool stays busy
+    jobs.sort(key=lambda j: 0 if j[1] else 1)
+    workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, jobs))
+    for stale in glob.glob(os.path.join(BUILD, "*.o")):
+        if stale not in objs:
+            os.remove(stale)
     tmp = OUT + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp, *objs])
     os.replace(tmp, OUT)

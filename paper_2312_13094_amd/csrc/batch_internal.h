@@ -36,6 +36,11 @@ struct BatchShot {
     float *d;               // [nt][nr]
 };
 
+// batched z-marching step for stencil radius R (k_step_radius.hip)
+template <int R>
+int launch_batch_radius(const BatchShot *shots_dev, int nshots, int total_blocks,
+                        const Tuning &t, int iu, int ium, int iup, hipStream_t s);
+
 // launchers (k_batch.hip)
 int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, int r,
                       const Tuning &t, int iu, int ium, int iup, hipStream_t s);

@@ -269,11 +269,11 @@ int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int xcd)
     if (!b) return set_error(FD_EINVAL, "fd_batch_set_tile: null handle");
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
                        (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
-    if (!known || nzb < 1 || xcd < 0 || xcd > 7)
+    if (!known || nzb < 1 || xcd < 0 || xcd > 15)
         return set_error(FD_EINVAL, "unsupported tile shape");
     DeviceGuard dg(b->d.device);
     drop_graph(b);
-    b->tune = Tuning{by, ry, nzb, xcd & 7};
+    b->tune = Tuning{by, ry, nzb, xcd & 15};
     layout_blocks(b);
     return FD_OK;
 }

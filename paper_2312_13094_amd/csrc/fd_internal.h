@@ -80,9 +80,10 @@ struct Tuning {
     int ry;        // rows per thread (tile height = by * ry)
     int nzb;       // planes per block (z chunk)
     int flags;     // bit 0: XCD-aware block remap; bit 1: prefetch two planes
-                   // ahead; bit 2: non-temporal stores of u+
+                   // ahead; bit 2: non-temporal hints on the streamed fields;
+                   // bit 3: halo loads issued with the neighbours' front loads
 };
-constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4;
+constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8;
 
 // One set of sparse points bound to a step.
 struct SparseArgs {
@@ -150,6 +151,10 @@ int check_launch(const char *what);
 int launch_step(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s);
 int launch_step_simple(const fd_grid *g, const float *u, const float *um, float *up,
                        hipStream_t s);
+// z-marching step for stencil radius R (k_step_radius.hip, one object per R)
+template <int R>
+int launch_zmarch_radius(const fd_grid *g, const float *u, const float *um, float *up,
+                         hipStream_t s);
 int launch_sparse(const fd_grid *g, float *u, const SparseArgs &inj, const SparseArgs &smp,
                   hipStream_t s);
 int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *const *buf,

@@ -26,7 +26,6 @@
 // k_acoustic_simple: one thread per point, neighbours straight from global
 // memory; used for 2-D grids and as the reference GPU path.
 #include "fd_internal.h"
-#include "zmarch.h"
 
 namespace fd {
 
@@ -60,27 +59,6 @@ __global__ __launch_bounds__(256) void k_acoustic_simple(const float *__restrict
     // u+ = u + [(1-a)(u - u-) + v^2 dt^2 lap] / (1+a): algebraically the
     // leapfrog update, with one rounding at the field's magnitude per step
     up[i] = c + ((1.0f - a) * (c - um[i]) + vdt2[i] * lap) / (1.0f + a);
-}
-
-template <int R, int BY, int RY, int PF, bool NTS>
-__global__ __launch_bounds__(64 * BY) void k_acoustic_zmarch(
-    const float *__restrict__ u, const float *um, float *up, const float *__restrict__ vdt2,
-    const StepParams p, const int ntx, const int nty, const int nzb, const int remap)
-{
-    __shared__ float lds[ZTile<R, BY, RY>::LDS];
-    int b = blockIdx.x;
-    if (remap) {
-        // the dispatcher deals block b to XCD b % 8: give XCD k the
-        // contiguous logical range [k * nb/8, (k+1) * nb/8)
-        const int per = gridDim.x >> 3;
-        b = (b & 7) * per + (b >> 3);
-    }
-    const int tx = b % ntx;
-    b /= ntx;
-    const int ty = b % nty;
-    const int zc = b / nty;
-
-    zmarch_body<R, BY, RY, PF, NTS>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -120,58 +98,19 @@ int launch_step_simple(const fd_grid *g, const float *u, const float *um, float 
     return check_launch("acoustic step (simple)");
 }
 
-template <int R, int BY, int RY, int PF, bool NTS>
-static void zmarch_v(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
-{
-    const StepParams &p = g->sp;
-    constexpr int TY = BY * RY;
-    const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
-    const int ntx = (p.nx + 63) / 64, nty = (p.ny + TY - 1) / TY, nzc = (p.nz + nzb - 1) / nzb;
-    const unsigned nb = (unsigned)ntx * nty * nzc;
-    const int remap = ((g->tune.flags & kTileXcd) && nb % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS>), dim3(nb), dim3(64, BY), 0, s, u,
-                       um, up, g->vdt2, p, ntx, nty, nzb, remap);
-}
-
-template <int R, int BY, int RY>
-static void zmarch(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
-{
-    const int f = g->tune.flags;
-    const bool pf2 = f & kTilePf2, nts = f & kTileNts;
-    if (pf2 && nts) zmarch_v<R, BY, RY, 2, true>(g, u, um, up, s);
-    else if (pf2) zmarch_v<R, BY, RY, 2, false>(g, u, um, up, s);
-    else if (nts) zmarch_v<R, BY, RY, 1, true>(g, u, um, up, s);
-    else zmarch_v<R, BY, RY, 1, false>(g, u, um, up, s);
-}
-
-template <int R>
-static int zmarch_r(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
-{
-    const int by = g->tune.by, ry = g->tune.ry;
-    if (by == 4 && ry == 4) zmarch<R, 4, 4>(g, u, um, up, s);
-    else if (by == 4 && ry == 2) zmarch<R, 4, 2>(g, u, um, up, s);
-    else if (by == 4 && ry == 8) zmarch<R, 4, 8>(g, u, um, up, s);
-    else if (by == 8 && ry == 2) zmarch<R, 8, 2>(g, u, um, up, s);
-    else if (by == 8 && ry == 4) zmarch<R, 8, 4>(g, u, um, up, s);
-    else if (by == 2 && ry == 8) zmarch<R, 2, 8>(g, u, um, up, s);
-    else if (by == 4 && ry == 1) zmarch<R, 4, 1>(g, u, um, up, s);
-    else return set_error(FD_EINVAL, "unsupported tile shape");
-    return FD_OK;
-}
-
 int launch_step(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
 {
     if (g->ndim == 2 || g->tune.by == 0) return launch_step_simple(g, u, um, up, s);
     int rc;
     switch (g->r) {
-    case 1: rc = zmarch_r<1>(g, u, um, up, s); break;
-    case 2: rc = zmarch_r<2>(g, u, um, up, s); break;
-    case 3: rc = zmarch_r<3>(g, u, um, up, s); break;
-    case 4: rc = zmarch_r<4>(g, u, um, up, s); break;
-    case 5: rc = zmarch_r<5>(g, u, um, up, s); break;
-    case 6: rc = zmarch_r<6>(g, u, um, up, s); break;
-    case 7: rc = zmarch_r<7>(g, u, um, up, s); break;
-    case 8: rc = zmarch_r<8>(g, u, um, up, s); break;
+    case 1: rc = launch_zmarch_radius<1>(g, u, um, up, s); break;
+    case 2: rc = launch_zmarch_radius<2>(g, u, um, up, s); break;
+    case 3: rc = launch_zmarch_radius<3>(g, u, um, up, s); break;
+    case 4: rc = launch_zmarch_radius<4>(g, u, um, up, s); break;
+    case 5: rc = launch_zmarch_radius<5>(g, u, um, up, s); break;
+    case 6: rc = launch_zmarch_radius<6>(g, u, um, up, s); break;
+    case 7: rc = launch_zmarch_radius<7>(g, u, um, up, s); break;
+    case 8: rc = launch_zmarch_radius<8>(g, u, um, up, s); break;
     default: return set_error(FD_EINVAL, "unsupported stencil radius");
     }
     if (rc != FD_OK) return rc;

@@ -8,85 +8,22 @@
 // captured graph node serves all shots.  The remaining kernels put the
 // shot index on blockIdx.y.
 #include "batch_internal.h"
-#include "zmarch.h"
 
 namespace fd {
-
-template <int R, int BY, int RY, int PF, bool NTS>
-__global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__restrict__ shots,
-                                                          const int nshots, const int total,
-                                                          const int iu, const int ium,
-                                                          const int iup, const int nzb,
-                                                          const int remap)
-{
-    __shared__ float lds[ZTile<R, BY, RY>::LDS];
-    int b = blockIdx.x;
-    if (remap) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
-    if (b >= total) return;
-    int s = 0;
-    for (int k = 1; k < nshots; ++k)
-        if (shots[k].block0 <= b) s = k;
-    const BatchShot &S = shots[s];
-    int lb = b - S.block0;
-    const int tx = lb % S.ntx;
-    lb /= S.ntx;
-    const int ty = lb % S.nty;
-    const int zc = lb / S.nty;
-    float *base = S.base;
-    const int64_t st = S.stride;
-    zmarch_body<R, BY, RY, PF, NTS>(base + iu * st, base + ium * st, base + iup * st,
-                                    base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
-}
-
-template <int R, int BY, int RY, int PF, bool NTS>
-static void batch_step_v(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
-                         int ium, int iup, hipStream_t s)
-{
-    const int remap = (t.flags & kTileXcd) ? 1 : 0;
-    const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
-    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, PF, NTS>), dim3(nb), dim3(64, BY), 0, s, shots,
-                       nshots, total, iu, ium, iup, t.nzb, remap);
-}
-
-template <int R, int BY, int RY>
-static void batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
-                       int ium, int iup, hipStream_t s)
-{
-    const bool pf2 = t.flags & kTilePf2, nts = t.flags & kTileNts;
-    if (pf2 && nts) batch_step_v<R, BY, RY, 2, true>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (pf2) batch_step_v<R, BY, RY, 2, false>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (nts) batch_step_v<R, BY, RY, 1, true>(shots, nshots, total, t, iu, ium, iup, s);
-    else batch_step_v<R, BY, RY, 1, false>(shots, nshots, total, t, iu, ium, iup, s);
-}
-
-template <int R>
-static int batch_step_r(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
-                        int ium, int iup, hipStream_t s)
-{
-    if (t.by == 4 && t.ry == 4) batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 2) batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 8) batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 8 && t.ry == 2) batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 8 && t.ry == 4) batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 2 && t.ry == 8) batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 1) batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, s);
-    else return set_error(FD_EINVAL, "unsupported tile shape");
-    return FD_OK;
-}
 
 int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, int r,
                       const Tuning &t, int iu, int ium, int iup, hipStream_t s)
 {
     int rc;
     switch (r) {
-    case 1: rc = batch_step_r<1>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 2: rc = batch_step_r<2>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 3: rc = batch_step_r<3>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 4: rc = batch_step_r<4>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 5: rc = batch_step_r<5>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 6: rc = batch_step_r<6>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 7: rc = batch_step_r<7>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 8: rc = batch_step_r<8>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 1: rc = launch_batch_radius<1>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 2: rc = launch_batch_radius<2>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 3: rc = launch_batch_radius<3>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 4: rc = launch_batch_radius<4>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 5: rc = launch_batch_radius<5>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 6: rc = launch_batch_radius<6>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 7: rc = launch_batch_radius<7>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 8: rc = launch_batch_radius<8>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
     default: return set_error(FD_EINVAL, "unsupported stencil radius");
     }
     if (rc) return rc;

@@ -1,0 +1,152 @@
+// fd-build: one object per stencil radius (compiled with -DFD_RADIUS=1..8)
+//
+// Every variant of the z-marching 3-D step for one stencil radius: the
+// single-grid kernel and the batched multi-shot kernel, over the supported
+// tiles and flag combinations (see zmarch.h).  Compiling one radius per
+// object keeps the build parallel.
+#include "batch_internal.h"
+#include "zmarch.h"
+
+#ifndef FD_RADIUS
+#error "compile with -DFD_RADIUS=<stencil radius>"
+#endif
+
+namespace fd {
+
+template <int R, int BY, int RY, int PF, bool NTS, bool RING>
+__global__ __launch_bounds__(64 * BY) void k_acoustic_zmarch(
+    const float *__restrict__ u, const float *um, float *up, const float *__restrict__ vdt2,
+    const StepParams p, const int ntx, const int nty, const int nzb, const int remap)
+{
+    __shared__ float lds[ZTile<R, BY, RY>::LDS];
+    int b = blockIdx.x;
+    if (remap) {
+        // the dispatcher deals block b to XCD b % 8: give XCD k the
+        // contiguous logical range [k * nb/8, (k+1) * nb/8)
+        const int per = gridDim.x >> 3;
+        b = (b & 7) * per + (b >> 3);
+    }
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int zc = b / nty;
+
+    if (RING) zmarch_ring_body<R, BY, RY, NTS>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
+    else zmarch_body<R, BY, RY, PF, NTS>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
+}
+
+template <int R, int BY, int RY, int PF, bool NTS, bool RING>
+static void zmarch_v(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+{
+    const StepParams &p = g->sp;
+    constexpr int TY = BY * RY;
+    const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
+    const int ntx = (p.nx + 63) / 64, nty = (p.ny + TY - 1) / TY, nzc = (p.nz + nzb - 1) / nzb;
+    const unsigned nb = (unsigned)ntx * nty * nzc;
+    const int remap = ((g->tune.flags & kTileXcd) && nb % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS, RING>), dim3(nb), dim3(64, BY), 0, s, u,
+                       um, up, g->vdt2, p, ntx, nty, nzb, remap);
+}
+
+template <int R, int BY, int RY>
+static void zmarch(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+{
+    const int f = g->tune.flags;
+    const bool pf2 = f & kTilePf2, nts = f & kTileNts, ring = f & kTileRing;
+    if (ring && nts) zmarch_v<R, BY, RY, 1, true, true>(g, u, um, up, s);
+    else if (ring) zmarch_v<R, BY, RY, 1, false, true>(g, u, um, up, s);
+    else if (pf2 && nts) zmarch_v<R, BY, RY, 2, true, false>(g, u, um, up, s);
+    else if (pf2) zmarch_v<R, BY, RY, 2, false, false>(g, u, um, up, s);
+    else if (nts) zmarch_v<R, BY, RY, 1, true, false>(g, u, um, up, s);
+    else zmarch_v<R, BY, RY, 1, false, false>(g, u, um, up, s);
+}
+
+template <int R>
+int launch_zmarch_radius(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+{
+    const int by = g->tune.by, ry = g->tune.ry;
+    if (by == 4 && ry == 4) zmarch<R, 4, 4>(g, u, um, up, s);
+    else if (by == 4 && ry == 2) zmarch<R, 4, 2>(g, u, um, up, s);
+    else if (by == 4 && ry == 8) zmarch<R, 4, 8>(g, u, um, up, s);
+    else if (by == 8 && ry == 2) zmarch<R, 8, 2>(g, u, um, up, s);
+    else if (by == 8 && ry == 4) zmarch<R, 8, 4>(g, u, um, up, s);
+    else if (by == 2 && ry == 8) zmarch<R, 2, 8>(g, u, um, up, s);
+    else if (by == 4 && ry == 1) zmarch<R, 4, 1>(g, u, um, up, s);
+    else return set_error(FD_EINVAL, "unsupported tile shape");
+    return FD_OK;
+}
+
+template <int R, int BY, int RY, int PF, bool NTS, bool RING>
+__global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__restrict__ shots,
+                                                          const int nshots, const int total,
+                                                          const int iu, const int ium,
+                                                          const int iup, const int nzb,
+                                                          const int remap)
+{
+    __shared__ float lds[ZTile<R, BY, RY>::LDS];
+    int b = blockIdx.x;
+    if (remap) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
+    if (b >= total) return;
+    int s = 0;
+    for (int k = 1; k < nshots; ++k)
+        if (shots[k].block0 <= b) s = k;
+    const BatchShot &S = shots[s];
+    int lb = b - S.block0;
+    const int tx = lb % S.ntx;
+    lb /= S.ntx;
+    const int ty = lb % S.nty;
+    const int zc = lb / S.nty;
+    float *base = S.base;
+    const int64_t st = S.stride;
+    if (RING)
+        zmarch_ring_body<R, BY, RY, NTS>(base + iu * st, base + ium * st, base + iup * st,
+                                         base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
+    else
+        zmarch_body<R, BY, RY, PF, NTS>(base + iu * st, base + ium * st, base + iup * st,
+                                        base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
+}
+
+template <int R, int BY, int RY, int PF, bool NTS, bool RING>
+static void batch_step_v(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+                         int ium, int iup, hipStream_t s)
+{
+    const int remap = (t.flags & kTileXcd) ? 1 : 0;
+    const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
+    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, PF, NTS, RING>), dim3(nb), dim3(64, BY), 0, s, shots,
+                       nshots, total, iu, ium, iup, t.nzb, remap);
+}
+
+template <int R, int BY, int RY>
+static void batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+                       int ium, int iup, hipStream_t s)
+{
+    const bool pf2 = t.flags & kTilePf2, nts = t.flags & kTileNts, ring = t.flags & kTileRing;
+    if (ring && nts) batch_step_v<R, BY, RY, 1, true, true>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (ring) batch_step_v<R, BY, RY, 1, false, true>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (pf2 && nts) batch_step_v<R, BY, RY, 2, true, false>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (pf2) batch_step_v<R, BY, RY, 2, false, false>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (nts) batch_step_v<R, BY, RY, 1, true, false>(shots, nshots, total, t, iu, ium, iup, s);
+    else batch_step_v<R, BY, RY, 1, false, false>(shots, nshots, total, t, iu, ium, iup, s);
+}
+
+template <int R>
+int launch_batch_radius(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+                        int ium, int iup, hipStream_t s)
+{
+    if (t.by == 4 && t.ry == 4) batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 2) batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 8) batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 8 && t.ry == 2) batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 8 && t.ry == 4) batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 2 && t.ry == 8) batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 1) batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, s);
+    else return set_error(FD_EINVAL, "unsupported tile shape");
+    return FD_OK;
+}
+
+template int launch_zmarch_radius<FD_RADIUS>(const fd_grid *, const float *, const float *,
+                                             float *, hipStream_t);
+template int launch_batch_radius<FD_RADIUS>(const BatchShot *, int, int, const Tuning &, int, int,
+                                            int, hipStream_t);
+
+}  // namespace fd

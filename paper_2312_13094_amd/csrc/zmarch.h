@@ -177,4 +177,167 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
     }
 }
 
+// Variant with the halo loads moved R planes earlier.  In the plain body a
+// tile reads the x/y halo of plane z when it computes plane z, R iterations
+// after its neighbours streamed plane z in as their queue front -- by then
+// L2 has usually evicted it, so the halo costs HBM traffic.  Here the halo
+// of plane z + R + 1 is issued in the same iteration as the neighbours'
+// front loads of that plane and parked in a register ring of R + 1 planes
+// until it is written to LDS; the streamed fields (u-, v^2 dt^2, u+) carry
+// the non-temporal hint when NTS is set so they do not evict u from L2.
+template <int R, int BY, int RY, bool NTS>
+__device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, const float *um,
+                                                 float *up, const float *__restrict__ vdt2,
+                                                 const StepParams &p, const int tx, const int ty,
+                                                 const int zc, const int nzb, float *lds)
+{
+    constexpr int TX = 64, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
+    constexpr int NT = 64 * BY;
+    constexpr int NHY = 2 * R * TX;
+    constexpr int NHX = 2 * R * TY;
+    constexpr int HY = (NHY + NT - 1) / NT;
+    constexpr int HX = (NHX + NT - 1) / NT;
+    constexpr int NR = R + 1;                 // halo ring depth (planes)
+    const int lane = threadIdx.x, wy = threadIdx.y;
+    const int tid = wy * 64 + lane;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int x = x0 + lane;
+    const int yb = y0 + wy * RY;
+    const int z0 = zc * nzb;
+    const int z1 = min(z0 + nzb, p.nz);
+    const int64_t PY = p.pitch_y, PZ = p.pitch_z;
+    const float *uo = u + p.offset;
+    const float *umo = um + p.offset;
+    const float *vo = vdt2 + p.offset;
+    float *upo = up + p.offset;
+
+    const bool xl = x < p.nx + R;
+    bool rl[RY], ro[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        rl[j] = xl && (yb + j) < p.ny + R;
+        ro[j] = x < p.nx && (yb + j) < p.ny;
+    }
+    int64_t hyo[HY], hxo[HX];
+    int hys[HY], hxs[HX];
+    bool hyk[HY], hxk[HX];
+#pragma unroll
+    for (int k = 0; k < HY; ++k) {
+        const int e = tid + k * NT;
+        const int row = e / TX, col = e % TX;
+        const int yy = row < R ? y0 - R + row : y0 + TY + (row - R);
+        const int ly = row < R ? row : TY + row;
+        const int xx = x0 + col;
+        hyk[k] = e < NHY && yy < p.ny + R && xx < p.nx + R;
+        hyo[k] = (int64_t)yy * PY + xx;
+        hys[k] = ly * LX + col + R;
+    }
+#pragma unroll
+    for (int k = 0; k < HX; ++k) {
+        const int e = tid + k * NT;
+        const int row = e / (2 * R), c = e % (2 * R);
+        const int yy = y0 + row;
+        const int xx = c < R ? x0 - R + c : x0 + TX + (c - R);
+        const int lx = c < R ? c : TX + c;
+        hxk[k] = e < NHX && yy < p.ny + R && xx < p.nx + R;
+        hxo[k] = (int64_t)yy * PY + xx;
+        hxs[k] = (row + R) * LX + lx;
+    }
+
+    float q[RY][2 * R + 1];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int64_t col = (int64_t)(yb + j) * PY + x;
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k)
+            q[j][k + 1] = rl[j] ? uo[(int64_t)(z0 - R + k) * PZ + col] : 0.0f;
+    }
+    // halo ring: slot d holds the halo of plane z with (z - z0) % NR == d
+    float hy[NR][HY], hx[NR][HX];
+    auto load_halo = [&](const int z, const int d) {
+        const int64_t pz = (int64_t)z * PZ;
+#pragma unroll
+        for (int k = 0; k < HY; ++k) hy[d][k] = hyk[k] ? uo[pz + hyo[k]] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < HX; ++k) hx[d][k] = hxk[k] ? uo[pz + hxo[k]] : 0.0f;
+    };
+#pragma unroll
+    for (int d = 0; d < NR; ++d)
+        if (z0 + d < z1) load_halo(z0 + d, d);
+    float nf[RY], nm[RY], nv[RY];
+    auto prefetch = [&](const int z) {
+        const int64_t pz = (int64_t)z * PZ;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int64_t col = (int64_t)(yb + j) * PY + x;
+            nf[j] = rl[j] ? uo[pz + R * PZ + col] : 0.0f;
+            if (NTS) {
+                nm[j] = ro[j] ? __builtin_nontemporal_load(umo + pz + col) : 0.0f;
+                nv[j] = ro[j] ? __builtin_nontemporal_load(vo + pz + col) : 0.0f;
+            } else {
+                nm[j] = ro[j] ? umo[pz + col] : 0.0f;
+                nv[j] = ro[j] ? vo[pz + col] : 0.0f;
+            }
+        }
+    };
+    if (z0 < z1) prefetch(z0);
+
+    const float ax = p.nbl > 0 ? sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+    for (int zb = z0; zb < z1; zb += NR) {
+#pragma unroll
+        for (int d = 0; d < NR; ++d) {
+            const int z = zb + d;
+            if (z < z1) {
+                float cm[RY], cv[RY];
+#pragma unroll
+                for (int j = 0; j < RY; ++j) {
+#pragma unroll
+                    for (int k = 0; k < 2 * R; ++k) q[j][k] = q[j][k + 1];
+                    q[j][2 * R] = nf[j];
+                    cm[j] = nm[j];
+                    cv[j] = nv[j];
+                }
+                if (z + 1 < z1) prefetch(z + 1);
+                float *t = lds + (z & 1) * (LY * LX);
+#pragma unroll
+                for (int j = 0; j < RY; ++j) t[(wy * RY + j + R) * LX + lane + R] = q[j][R];
+#pragma unroll
+                for (int k = 0; k < HY; ++k)
+                    if (tid + k * NT < NHY) t[hys[k]] = hy[d][k];
+#pragma unroll
+                for (int k = 0; k < HX; ++k)
+                    if (tid + k * NT < NHX) t[hxs[k]] = hx[d][k];
+                // the ring slot is free again: issue the halo of plane z + NR,
+                // together with the neighbours' front loads of that plane
+                if (z + NR < z1) load_halo(z + NR, d);
+                __syncthreads();
+
+                const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
+#pragma unroll
+                for (int j = 0; j < RY; ++j) {
+                    const float *c = t + (wy * RY + j + R) * LX + lane + R;
+                    float lz = 0.0f, ly = 0.0f, lx = 0.0f;
+#pragma unroll
+                    for (int k = 1; k <= R; ++k) {
+                        lz += p.cz[k] * (q[j][R + k] + q[j][R - k]);
+                        ly += p.cy[k] * (c[k * LX] + c[-k * LX]);
+                        lx += p.cx[k] * (c[k] + c[-k]);
+                    }
+                    const float uc = q[j][R];
+                    const float lap = p.c0 * uc + lz + ly + lx;
+                    const int y = yb + j;
+                    const float ay = p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
+                    const float a = p.half_dt * ((az + ax) + ay);
+                    const float val = uc + ((1.0f - a) * (uc - cm[j]) + cv[j] * lap) / (1.0f + a);
+                    if (ro[j]) {
+                        float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + x;
+                        if (NTS) __builtin_nontemporal_store(val, dst);
+                        else *dst = val;
+                    }
+                }
+            }
+        }
+    }
+}
+
 }  // namespace fd

@@ -5,14 +5,16 @@ is corrected after every coarse step by the 3-layer BF16 network of
 ``fdnn.h`` toward the space-order-8 fine-grid solution:
 
     u~(n+1) = coarse leapfrog step of (u(n), u(n-1))            [fd_forward]
-    s       = rms(u(n))                                          [nn_rms]
+    s       = rms(u~(n+1))                                       [nn_rms]
     u(n+1)  = u~(n+1) + s * N(u~(n+1)/s, u(n)/s, (v - 3000)/1500) [nn_* kernels]
 
 Training data come from the plain solver: fine solves are restricted to the
 coarse nodes (even fine indices) at coarse times, the coarse step is taken
 from the restricted states, and the network learns the one-step residual
 (teacher forcing).  The plain fine solve is both the reference for the
-trace error and the fallback when the corrected run turns non-finite.
+trace error and the fallback when the corrected run turns non-finite or its
+amplitude grows late in the run (a learned correction can feed an unstable
+mode; the physical field only decays once the source has stopped).
 
 This module only allocates caller-side buffers and sequences library calls;
 every arithmetic step runs in libfd's kernels (restriction to the coarse
@@ -127,9 +129,9 @@ class LearnedCorrector:
         self.coarse.forward([self.ca, self.cb], self.Sc, self.qc[n:n + 1], None, None, 1)
 
     def correct(self):
-        """ca <- ca + s * N(ca/s, cb/s, vhat) with s = rms(cb)."""
+        """ca <- ca + s * N(ca/s, cb/s, vhat) with s = rms(ca)."""
         net = self.net
-        net.rms(self.cb, self.cview)
+        net.rms(self.ca, self.cview)
         net.pack_input(self.ca, self.cview, self.cb, self.cview, self.vhat, self.dview,
                        scale=net.scale)
         net.forward(keep=False, out=self.ca, base=self.ca, vbase=self.cview, vout=self.cview,
@@ -137,25 +139,32 @@ class LearnedCorrector:
 
     def learned_solve(self, guard=True):
         """Corrected coarse run; falls back to the plain fine solve if the
-        corrected wavefield turns non-finite."""
+        corrected wavefield turns non-finite or its RMS in the last quarter of
+        the run exceeds twice its peak over the first three quarters."""
         c = self.cfg
         self.ca.zero_()
         self.cb.zero_()
         self.net.flag.zero_()
         d = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32, device=self.dev)
+        hist = torch.zeros(c.nt_coarse, dtype=torch.float32, device=self.dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for n in range(c.nt_coarse):
             self.coarse_step(n)
             self.correct()
+            hist[n:n + 1].copy_(self.net.scale[:1])
             self.coarse.sample(self.ca, self.Rc, d[n])
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         tr = d.double().cpu().numpy()
-        bad = bool(self.net.flag.item()) or not np.isfinite(tr).all()
-        if guard and bad:
+        h = hist.cpu().numpy()
+        q = (3 * len(h)) // 4
+        growth = len(h) > 4 and h[q:].max() > 2.0 * h[:q].max()
+        bad = bool(self.net.flag.item()) or not np.isfinite(tr).all() or not np.isfinite(h).all()
+        if guard and (bad or growth):
             ftr, fsecs, _ = self.fine_solve()
-            return RunResult(ftr, secs + fsecs, fallback=True, info={"learned_seconds": secs})
+            return RunResult(ftr, secs + fsecs, fallback=True,
+                             info={"learned_seconds": secs, "non_finite": bad, "growth": growth})
         return RunResult(tr, secs)
 
     # -- training data and training -----------------------------------------
@@ -193,7 +202,7 @@ class LearnedCorrector:
         hist = []
         for it in range(iters):
             s = samples[int(rng.integers(len(samples)))]
-            net.rms(s.u0, self.dview)
+            net.rms(s.ut, self.dview)
             net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
                            scale=net.scale)
             net.loss.zero_()
@@ -210,7 +219,7 @@ class LearnedCorrector:
         net = self.net
         tot, base = 0.0, 0.0
         for s in samples:
-            net.rms(s.u0, self.dview)
+            net.rms(s.ut, self.dview)
             net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
                            scale=net.scale)
             net.forward(keep=True)

@@ -119,7 +119,7 @@ def test_one_step_parity(shape, so, nbl, bc, tile):
 
 def test_tiles_are_bit_identical():
     """The per-point arithmetic does not depend on the tile, the z chunk, the
-    XCD remap, the prefetch distance or the store hint."""
+    XCD remap, the prefetch distance, the halo-ring loads or the cache hints."""
     rng = np.random.default_rng(3)
     shape, so, h, vmax = (45, 38, 97), 8, 10.0, 3000.0
     v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
@@ -128,7 +128,8 @@ def test_tiles_are_bit_identical():
     base = None
     for tile in [(4, 4, 64, 1), (4, 1, 5, 0), (4, 2, 13, 1), (4, 8, 45, 1), (8, 2, 9, 1),
                  (8, 4, 64, 0), (2, 8, 3, 1), (4, 4, 64, 2), (4, 4, 7, 3), (4, 2, 13, 6),
-                 (8, 2, 9, 7), (4, 1, 5, 4)]:
+                 (8, 2, 9, 7), (4, 1, 5, 4), (4, 4, 64, 8), (8, 4, 11, 12), (4, 2, 3, 13),
+                 (2, 8, 64, 9)]:
         u, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, 5, nbl=7, u0=u0, tile=tile)
         if base is None:
             base = u

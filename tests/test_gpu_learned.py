@@ -17,11 +17,11 @@ def trained():
     cfg = synth.cfg_learned(n_fine=64, nt_fine=240, ntrain=4, ntest=2)
     lc = LC.LearnedCorrector(cfg)
     models = []
-    steps = list(range(12, 118, 8))
+    steps = [1, 2, 3, 5] + list(range(8, 118, 6))
     train = lc.make_samples(cfg.train_seeds, steps, models)
     test = lc.make_samples(cfg.test_seeds, steps, models)
     before, base = lc.sample_loss(test, models)
-    lc.train(train, models, iters=400, lr=2e-3, seed=0)
+    lc.train(train, models, iters=600, lr=2e-3, seed=0)
     after, _ = lc.sample_loss(test, models)
     return lc, cfg, models, (before, base, after)
 
