@@ -30,23 +30,29 @@ METRIC = "Gpts/s & % HBM roofline, 3D so-8 acoustic; learned vs plain time at sa
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
 STEP_BYTES_PER_POINT = 16             # read u, u-, v^2dt^2; write u+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "acoustic_step_512cube_so8_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2312_13094_amd", "csrc", "k_acoustic.hip")
+# sources that define the step kernel and its launch (tile defaults included)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2312_13094_amd", "csrc", f)
+               for f in ("zmarch.h", "k_step_radius.hip", "fd_internal.h", "fd_api.hip")]
 
 
 def _kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
-def _traffic():
+def _traffic(tile):
     """HBM bytes per step-kernel launch from the committed rocprofv3 PMC
-    summary, or None if absent or taken on a different kernel source."""
+    summary, or None if absent, taken on a different kernel source or taken
+    with another tile."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != _kernel_hash():
+    if t.get("kernel_source_sha256") != _kernel_hash() or t.get("tile") != tile:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -189,7 +195,7 @@ def bench_learned(args):
     train = lc.make_samples(c.train_seeds, steps, models)
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
-    lc.train(train, models, iters=args.train_iters, lr=1e-3)
+    lc.train(train, models, iters=args.train_iters)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     rows = []
@@ -292,7 +298,7 @@ def main():
     avg_ms = kern_ms / max(launches, 1)
     bytes_launch = STEP_BYTES_PER_POINT * c.points
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic()
+    traffic = _traffic(args.tile or "default")
     out = {
         "metric": METRIC,
         "value": round(gpts, 3),

@@ -116,7 +116,7 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * registers until used; bit 1 is then ignored).  by = 0 selects the
  * one-thread-per-point kernel.  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
- * arithmetic per point). */
+ * arithmetic per point).  A 3-D grid starts with (8, 2, 64, 12). */
 int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int flags);
 
 /* Autotuner: pick the 3-D step kernel's tile for this handle by timed

@@ -48,11 +48,20 @@ int64_t nn_wgrad_workspace_bytes(int nz, int ny, int nx);
 /* params (FP32) -> packed BF16 fragments (round to nearest even). */
 int nn_pack_weights(const float *params_dev, void *packed_dev, void *stream);
 
-/* x[p] = (a[p] * sa, b[p] * sb, c[p], 0, 0, 0, 0, 0) as BF16, with
- * sa = sb = 1 / scale_dev[0] if scale_dev is non-NULL (else 1). */
+/* Half-open index box [lo, hi) in (z, y, x) order; points inside it are
+ * excluded (see nn_conv_out, nn_mse).  An empty box excludes nothing. */
+typedef struct nn_box {
+    int lo[3];
+    int hi[3];
+} nn_box;
+
+/* x[p] = (a[p] * sa, b[p] * sa, c3, 0, 0, 0, 0, 0) as BF16, with
+ * sa = 1 / scale_dev[0] if scale_dev is non-NULL (else 1), and
+ * c3 = c[p] * a[p] * sa if c_times_a is non-zero (the third channel then
+ * vanishes wherever a does), c3 = c[p] otherwise. */
 int nn_pack_input(int nz, int ny, int nx, const float *a, nn_view va, const float *b,
-                  nn_view vb, const float *c, nn_view vc, const float *scale_dev, void *x8_dev,
-                  void *stream);
+                  nn_view vb, const float *c, nn_view vc, int c_times_a, const float *scale_dev,
+                  void *x8_dev, void *stream);
 
 /* scale_dev[0] = sqrt(mean(u^2)) + 1e-30 over the volume; flag_dev[0] (may
  * be NULL) is set to 1 if any value is not finite, left unchanged otherwise.
@@ -69,17 +78,23 @@ int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const voi
 
 /* Forward layer 3 (16 -> 1): y = conv(a16) + b3.  If y_dense_dev is
  * non-NULL it receives y (dense [nz][ny][nx]); if out_dev is non-NULL,
- * out[vout] = base[vbase] + s * y with s = scale_dev[0] (or 1 if NULL). */
+ * out[vout] = base[vbase] + gain * s * y with s = scale_dev[0] (or 1 if
+ * NULL), except inside `skip` (may be NULL) where out[vout] = base[vbase].
+ * out may alias base (same element for every point). */
 int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_dev,
                 const float *params_dev, float *y_dense_dev, const float *base_dev,
                 nn_view vbase, float *out_dev, nn_view vout, const float *scale_dev,
-                void *stream);
+                float gain, const nn_box *skip, void *stream);
 
-/* MSE over the volume against the target t / s (s = scale_dev[0], or 1 if
- * scale_dev is NULL): loss_dev[0] += mean((y - t/s)^2) (float atomics),
- * gy8[p] = (2 (y - t/s) / N, 0, ..., 0) as BF16. */
+/* MSE over the volume against the target t / (gain * s) (s = scale_dev[0],
+ * or 1 if scale_dev is NULL), with points inside `skip` (may be NULL)
+ * contributing zero: with m[p] = 0 inside skip and 1 elsewhere and N the
+ * number of points, loss_dev[0] += sum(m (y - t/(gain s))^2) / N (float
+ * atomics) and gy8[p] = (2 m (y - t/(gain s)) / N, 0, ..., 0) as BF16.
+ * gain must be positive. */
 int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,
-           const float *scale_dev, void *gy8_dev, float *loss_dev, void *stream);
+           const float *scale_dev, float gain, const nn_box *skip, void *gy8_dev,
+           float *loss_dev, void *stream);
 
 /* Data gradient through layer 3 (gin = gy8) or layer 2 (gin = gz16),
  * multiplied by GELU'(z) of the previous layer: gz_out16 = (W^T * gin) .
@@ -95,9 +110,11 @@ int nn_dgrad_gelu(int layer, int nz, int ny, int nx, const void *gin_dev,
 int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
              void *workspace_dev, float *grads_dev, void *stream);
 
-/* Adam on all parameters (t is the 1-based step). */
+/* Adam (t is the 1-based step) on every weight, and on the biases too if
+ * train_bias is non-zero; otherwise biases and their moments are left as
+ * they are (a bias-free network keeps N(0) = 0). */
 int nn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int t,
-            float lr, float beta1, float beta2, float eps, void *stream);
+            float lr, float beta1, float beta2, float eps, int train_bias, void *stream);
 
 #ifdef __cplusplus
 }

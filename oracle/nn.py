@@ -10,8 +10,11 @@ textbook definition, evaluated in float64 with numpy:
   (channels-first arrays [C][nz][ny][nx]);
 * its data gradient (the adjoint correlation) and weight/bias gradients;
 * GELU(x) = x Phi(x) with the Gaussian CDF Phi (erf form) and its derivative;
-* mean-squared error;
-* one Adam step (Kingma & Ba) with bias correction.
+* mean-squared error, optionally with points of an index box excluded;
+* the input channels (two fields scaled by 1/s and a third channel that is
+  either given or modulates the first field);
+* one Adam step (Kingma & Ba) with bias correction, optionally leaving some
+  entries (the biases of a bias-free network) untouched.
 
 Operands of the BF16 kernels are first rounded to BF16 (round to nearest
 even) with ``bf16_round`` and then computed here in float64, so a comparison
@@ -97,13 +100,39 @@ def mse(pred: np.ndarray, target: np.ndarray) -> float:
     return float(np.mean((pred - target) ** 2))
 
 
-def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update at step t (1-based).  Returns (p, m, v)."""
-    m = b1 * m + (1 - b1) * g
-    v = b2 * v + (1 - b2) * g * g
-    mh = m / (1 - b1 ** t)
-    vh = v / (1 - b2 ** t)
-    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+def box_mask(shape, lo=None, hi=None) -> np.ndarray:
+    """1 everywhere except 0 inside the half-open index box [lo, hi)."""
+    m = np.ones(shape)
+    if lo is not None:
+        m[tuple(slice(int(a), int(b)) for a, b in zip(lo, hi))] = 0.0
+    return m
+
+
+def masked_mse(pred: np.ndarray, target: np.ndarray, mask: np.ndarray) -> float:
+    """Sum of mask * squared error divided by the number of ALL points (the
+    masked points count in the denominator and contribute zero)."""
+    return float(np.sum(mask * (pred - target) ** 2) / pred.size)
+
+
+def input_channels(a, b, c, s=1.0, c_times_a=False) -> np.ndarray:
+    """Network input [3][...]: (a/s, b/s, c*a/s) or (a/s, b/s, c)."""
+    a = np.asarray(a, dtype=np.float64) / s
+    b = np.asarray(b, dtype=np.float64) / s
+    c = np.asarray(c, dtype=np.float64)
+    return np.stack([a, b, c * a if c_times_a else c])
+
+
+def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, frozen=None):
+    """One Adam update at step t (1-based).  Returns (p, m, v).  Entries
+    where the boolean array `frozen` is true keep p, m and v unchanged."""
+    m1 = b1 * m + (1 - b1) * g
+    v1 = b2 * v + (1 - b2) * g * g
+    mh = m1 / (1 - b1 ** t)
+    vh = v1 / (1 - b2 ** t)
+    p1 = p - lr * mh / (np.sqrt(vh) + eps)
+    if frozen is not None:
+        p1, m1, v1 = (np.where(frozen, a0, a1) for a0, a1 in ((p, p1), (m, m1), (v, v1)))
+    return p1, m1, v1
 
 
 class Net:
@@ -123,12 +152,14 @@ class Net:
             return y, (x, z1, a1, z2, a2)
         return y
 
-    def loss_and_grads(self, x, target):
-        """MSE over all outputs and its gradient w.r.t. every parameter."""
+    def loss_and_grads(self, x, target, mask=None):
+        """MSE over all outputs (masked_mse when a 0/1 mask of the output's
+        shape is given) and its gradient w.r.t. every parameter."""
         w1, b1, w2, b2, w3, b3 = self.p
         y, (x, z1, a1, z2, a2) = self.forward(x, keep=True)
         n = y.size
-        gy = 2.0 * (y - target) / n
+        m = np.ones_like(y) if mask is None else np.broadcast_to(mask, y.shape)
+        gy = 2.0 * m * (y - target) / n
         gw3, gb3 = conv3d_wgrad(a2, gy)
         ga2 = conv3d_dgrad(gy, w3)
         gz2 = ga2 * gelu_grad(z2)
@@ -136,4 +167,4 @@ class Net:
         ga1 = conv3d_dgrad(gz2, w2)
         gz1 = ga1 * gelu_grad(z1)
         gw1, gb1 = conv3d_wgrad(x, gz1)
-        return mse(y, target), [gw1, gb1, gw2, gb2, gw3, gb3]
+        return masked_mse(y, target, m), [gw1, gb1, gw2, gb2, gw3, gb3]

@@ -267,7 +267,7 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     make_geometry(d, g->ndim, g->n, g->h, r, g->L, g->sp);
     const fd_layout &L = g->L;
 
-    g->tune = d.ndim == 3 ? Tuning{4, 4, 64, 0} : Tuning{0, 0, 0, 0};
+    g->tune = d.ndim == 3 ? Tuning{8, 2, 64, kTileRing | kTileNts} : Tuning{0, 0, 0, 0};
 
     DeviceGuard dg(d.device);
     if (!dg.ok()) {

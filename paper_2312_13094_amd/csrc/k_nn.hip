@@ -119,7 +119,15 @@ struct ConvArgs {
     float *out;
     nn_view vout;
     const float *scale;       // EPI_OUT: s = scale[0] (NULL = 1)
+    float gain;               // EPI_OUT: out = base + gain * s * y
+    nn_box skip;              // EPI_OUT: no correction inside (empty = none)
 };
+
+__device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
+{
+    return z >= b.lo[0] && z < b.hi[0] && y >= b.lo[1] && y < b.hi[1] && x >= b.lo[2] &&
+           x < b.hi[2];
+}
 
 template <int CIN, int STEPS, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
@@ -180,10 +188,10 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                 const float yv = acc[0] + a.bias[0];
                 if (a.ydense) a.ydense[p] = yv;
                 if (a.out) {
-                    const float s = a.scale ? a.scale[0] : 1.0f;
+                    const float s = a.gain * (a.scale ? a.scale[0] : 1.0f);
                     const int64_t ib = a.vbase.offset + z * a.vbase.pitch_z + y * a.vbase.pitch_y + x;
                     const int64_t io = a.vout.offset + z * a.vout.pitch_z + y * a.vout.pitch_y + x;
-                    a.out[io] = a.base[ib] + s * yv;
+                    a.out[io] = in_box(a.skip, z, y, x) ? a.base[ib] : a.base[ib] + s * yv;
                 }
             }
         } else {
@@ -340,7 +348,8 @@ __global__ __launch_bounds__(256) void k_pack_input(const int nz, const int ny, 
                                                     const float *a, const nn_view va,
                                                     const float *b, const nn_view vb,
                                                     const float *c, const nn_view vc,
-                                                    const float *scale, uint16_t *x8)
+                                                    const int c_times_a, const float *scale,
+                                                    uint16_t *x8)
 {
     const int64_t n = (int64_t)nz * ny * nx;
     const float inv = scale ? 1.0f / scale[0] : 1.0f;
@@ -351,7 +360,8 @@ __global__ __launch_bounds__(256) void k_pack_input(const int nz, const int ny, 
         const int y = (int)(t % ny), z = (int)(t / ny);
         const float va_ = a[va.offset + z * va.pitch_z + y * va.pitch_y + x] * inv;
         const float vb_ = b[vb.offset + z * vb.pitch_z + y * vb.pitch_y + x] * inv;
-        const float vc_ = c[vc.offset + z * vc.pitch_z + y * vc.pitch_y + x];
+        const float cv = c[vc.offset + z * vc.pitch_z + y * vc.pitch_y + x];
+        const float vc_ = c_times_a ? cv * va_ : cv;
         uint4 o;
         o.x = f2bf(va_) | ((uint32_t)f2bf(vb_) << 16);
         o.y = f2bf(vc_);
@@ -402,18 +412,23 @@ __global__ __launch_bounds__(64) void k_rms_final(const double *part, const int6
     }
 }
 
-__global__ __launch_bounds__(256) void k_mse(const int64_t n, const float *__restrict__ y,
+__global__ __launch_bounds__(256) void k_mse(const int nz, const int ny, const int nx,
+                                             const float *__restrict__ y,
                                              const float *__restrict__ t,
-                                             const float *__restrict__ scale, uint16_t *gy8,
-                                             float *loss)
+                                             const float *__restrict__ scale, const float gain,
+                                             const nn_box skip, uint16_t *gy8, float *loss)
 {
     __shared__ float red[256];
     float s = 0.0f;
+    const int64_t n = (int64_t)nz * ny * nx;
     const float inv = 1.0f / (float)n;
-    const float ts = scale ? 1.0f / scale[0] : 1.0f;
+    const float ts = 1.0f / (gain * (scale ? scale[0] : 1.0f));
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float d = y[i] - t[i] * ts;
+        const int x = (int)(i % nx);
+        const int64_t r = i / nx;
+        const int yy = (int)(r % ny), z = (int)(r / ny);
+        const float d = in_box(skip, z, yy, x) ? 0.0f : y[i] - t[i] * ts;
         s += d * d;
         uint4 o = make_uint4(f2bf(2.0f * d * inv), 0u, 0u, 0u);
         reinterpret_cast<uint4 *>(gy8)[i] = o;
@@ -430,10 +445,12 @@ __global__ __launch_bounds__(256) void k_mse(const int64_t n, const float *__res
 __global__ __launch_bounds__(256) void k_adam(float *p, const float *__restrict__ g, float *m,
                                               float *v, const float c1, const float c2,
                                               const float lr, const float b1, const float b2,
-                                              const float eps)
+                                              const float eps, const int train_bias)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kNP) return;
+    const bool bias = (i >= kB1 && i < kB1 + 16) || (i >= kB2 && i < kB2 + 16) || i == kB3;
+    if (bias && !train_bias) return;
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -472,14 +489,15 @@ int nn_pack_weights(const float *params_dev, void *packed_dev, void *stream)
 static bool bad_shape(int nz, int ny, int nx) { return nz < 1 || ny < 1 || nx < 1; }
 
 int nn_pack_input(int nz, int ny, int nx, const float *a, nn_view va, const float *b, nn_view vb,
-                  const float *c, nn_view vc, const float *scale_dev, void *x8_dev, void *stream)
+                  const float *c, nn_view vc, int c_times_a, const float *scale_dev, void *x8_dev,
+                  void *stream)
 {
     if (bad_shape(nz, ny, nx) || !a || !b || !c || !x8_dev)
         return set_error(FD_EINVAL, "nn_pack_input: bad argument");
     const int64_t n = (int64_t)nz * ny * nx;
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(k_pack_input, dim3(nb), dim3(256), 0, (hipStream_t)stream, nz, ny, nx, a,
-                       va, b, vb, c, vc, scale_dev, (uint16_t *)x8_dev);
+                       va, b, vb, c, vc, c_times_a, scale_dev, (uint16_t *)x8_dev);
     return check_launch("nn pack input");
 }
 
@@ -527,10 +545,11 @@ int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const voi
 
 int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_dev,
                 const float *params_dev, float *y_dense_dev, const float *base_dev, nn_view vbase,
-                float *out_dev, nn_view vout, const float *scale_dev, void *stream)
+                float *out_dev, nn_view vout, const float *scale_dev, float gain,
+                const nn_box *skip, void *stream)
 {
     if (bad_shape(nz, ny, nx) || !a16_dev || !packed_dev || !params_dev ||
-        (out_dev && !base_dev) || (!out_dev && !y_dense_dev))
+        (out_dev && !base_dev) || (!out_dev && !y_dense_dev) || !std::isfinite(gain))
         return set_error(FD_EINVAL, "nn_conv_out: bad argument");
     ConvArgs a{};
     a.nz = nz;
@@ -545,18 +564,23 @@ int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_
     a.out = out_dev;
     a.vout = vout;
     a.scale = scale_dev;
+    a.gain = gain;
+    a.skip = skip ? *skip : nn_box{{0, 0, 0}, {0, 0, 0}};
     return conv<16, 14, EPI_OUT>(a, (hipStream_t)stream);
 }
 
 int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,
-           const float *scale_dev, void *gy8_dev, float *loss_dev, void *stream)
+           const float *scale_dev, float gain, const nn_box *skip, void *gy8_dev,
+           float *loss_dev, void *stream)
 {
-    if (bad_shape(nz, ny, nx) || !y_dev || !t_dev || !gy8_dev || !loss_dev)
+    if (bad_shape(nz, ny, nx) || !y_dev || !t_dev || !gy8_dev || !loss_dev || !(gain > 0.0f) ||
+        !std::isfinite(gain))
         return set_error(FD_EINVAL, "nn_mse: bad argument");
     const int64_t n = (int64_t)nz * ny * nx;
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, (hipStream_t)stream, n, y_dev, t_dev,
-                       scale_dev, (uint16_t *)gy8_dev, loss_dev);
+    const nn_box sk = skip ? *skip : nn_box{{0, 0, 0}, {0, 0, 0}};
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, (hipStream_t)stream, nz, ny, nx, y_dev,
+                       t_dev, scale_dev, gain, sk, (uint16_t *)gy8_dev, loss_dev);
     return check_launch("nn mse");
 }
 
@@ -614,14 +638,15 @@ int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g
 }
 
 int nn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int t, float lr,
-            float beta1, float beta2, float eps, void *stream)
+            float beta1, float beta2, float eps, int train_bias, void *stream)
 {
     if (!params_dev || !grads_dev || !m_dev || !v_dev || t < 1)
         return set_error(FD_EINVAL, "nn_adam: bad argument");
     const float c1 = 1.0f - (float)std::pow((double)beta1, t);
     const float c2 = 1.0f - (float)std::pow((double)beta2, t);
     hipLaunchKernelGGL(k_adam, dim3((kNP + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                       params_dev, grads_dev, m_dev, v_dev, c1, c2, lr, beta1, beta2, eps);
+                       params_dev, grads_dev, m_dev, v_dev, c1, c2, lr, beta1, beta2, eps,
+                       train_bias);
     return check_launch("nn adam");
 }
 

@@ -4,17 +4,28 @@ A space-order-4 propagation on a 2x coarser grid with a 2x larger time step
 is corrected after every coarse step by the 3-layer BF16 network of
 ``fdnn.h`` toward the space-order-8 fine-grid solution:
 
-    u~(n+1) = coarse leapfrog step of (u(n), u(n-1))            [fd_forward]
-    s       = rms(u~(n+1))                                       [nn_rms]
-    u(n+1)  = u~(n+1) + s * N(u~(n+1)/s, u(n)/s, (v - 3000)/1500) [nn_* kernels]
+    u~(n+1) = coarse leapfrog step of (u(n), u(n-1))             [fd_forward]
+    s       = rms(u~(n+1))                                        [nn_rms]
+    u(n+1)  = u~(n+1) + k s N(u~/s, u(n)/s, v^ u~/s)  outside B   [nn_* kernels]
+            = u~(n+1)                                 inside B
+
+with v^ = (v - 3000)/1500, a fixed output gain k = 1e-3 (the one-step
+residual is about that fraction of the field, so the network's output is
+O(1)) and B a 5^3 box of coarse nodes around the source.  The network has no
+biases and its velocity channel multiplies the field, so N(0) = 0: it cannot
+create a wavefield where there is none.  Inside B the residual is the
+mismatch of the two grids' discrete point sources, which depends on the
+source wavelet the network does not see; B is excluded from the correction
+and from the loss.
 
 Training data come from the plain solver: fine solves are restricted to the
 coarse nodes (even fine indices) at coarse times, the coarse step is taken
 from the restricted states, and the network learns the one-step residual
-(teacher forcing).  The plain fine solve is both the reference for the
-trace error and the fallback when the corrected run turns non-finite or its
-amplitude grows late in the run (a learned correction can feed an unstable
-mode; the physical field only decays once the source has stopped).
+(teacher forcing), with a cosine-decayed Adam step.  The plain fine solve
+is both the reference for the trace error and the fallback when the
+corrected run turns non-finite or its amplitude grows late in the run (a
+learned correction can feed an unstable mode; the physical field only decays
+once the source has stopped).
 
 This module only allocates caller-side buffers and sequences library calls;
 every arithmetic step runs in libfd's kernels (restriction to the coarse
@@ -55,6 +66,9 @@ class RunResult:
 
 
 class LearnedCorrector:
+    GAIN = 1e-3          # output gain k
+    SKIP_HALF = 2        # half-width of the source box B, coarse nodes
+
     def __init__(self, cfg: Learned, params=None, device: int = 0):
         self.cfg = c = cfg
         self.dev = torch.device("cuda", device)
@@ -63,7 +77,11 @@ class LearnedCorrector:
                             nbl=c.nbl_fine, device=device)
         self.coarse = FD.Grid((nc,) * 3, (c.h_coarse,) * 3, c.so_coarse, c.dt_coarse, c.vmax,
                               nbl=c.nbl_coarse, device=device)
-        self.net = NN.Net((nc,) * 3, params, device)
+        self.net = NN.Net((nc,) * 3, params, device, bias=False)
+        sc = [i // 2 for i in c.src_idx]
+        w = self.SKIP_HALF
+        self.skip = NN.box([max(0, i - w) for i in sc], [min(nc, i + w + 1) for i in sc])
+        self._zero = torch.zeros(nc ** 3, dtype=torch.float32, device=self.dev)
         src, rec = c.src_fine(), c.rec_fine()          # physical coordinates, shared
         self.Sf, self.Rf = self.fine.sparse(src), self.fine.sparse(rec)
         self.Sc, self.Rc = self.coarse.sparse(src), self.coarse.sparse(rec)
@@ -129,13 +147,13 @@ class LearnedCorrector:
         self.coarse.forward([self.ca, self.cb], self.Sc, self.qc[n:n + 1], None, None, 1)
 
     def correct(self):
-        """ca <- ca + s * N(ca/s, cb/s, vhat) with s = rms(ca)."""
+        """ca <- ca + k s N(ca/s, cb/s, vhat ca/s) outside B, s = rms(ca)."""
         net = self.net
         net.rms(self.ca, self.cview)
         net.pack_input(self.ca, self.cview, self.cb, self.cview, self.vhat, self.dview,
-                       scale=net.scale)
+                       scale=net.scale, c_times_a=True)
         net.forward(keep=False, out=self.ca, base=self.ca, vbase=self.cview, vout=self.cview,
-                    scale=net.scale, ydense=False)
+                    scale=net.scale, ydense=False, gain=self.GAIN, skip=self.skip)
 
     def learned_solve(self, guard=True):
         """Corrected coarse run; falls back to the plain fine solve if the
@@ -195,39 +213,48 @@ class LearnedCorrector:
                 samples.append(Sample(ut, u0.clone(), (up - ut).contiguous(), mi))
         return samples
 
-    def train(self, samples, models, iters, lr=1e-3, seed=0, log_every=0):
-        """Adam on the one-step MSE of the scaled residual; returns the loss history."""
+    def _load(self, s, models):
+        net = self.net
+        net.rms(s.ut, self.dview)
+        net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
+                       scale=net.scale, c_times_a=True)
+
+    def train(self, samples, models, iters, lr=2e-3, seed=0, log_every=0):
+        """Adam on the one-step MSE of the scaled residual r / (k s) outside B,
+        one random sample per step, step size lr (1 + cos(pi i / iters)) / 2;
+        returns the loss history."""
         rng = np.random.default_rng(seed)
         net = self.net
         hist = []
         for it in range(iters):
             s = samples[int(rng.integers(len(samples)))]
-            net.rms(s.ut, self.dview)
-            net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
-                           scale=net.scale)
+            self._load(s, models)
             net.loss.zero_()
             net.forward(keep=True)
-            net.backward(s.target, scale=net.scale)
-            net.adam(lr=lr)
+            net.backward(s.target, scale=net.scale, gain=self.GAIN, skip=self.skip)
+            net.adam(lr=lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)))
             if log_every and (it % log_every == 0 or it == iters - 1):
                 hist.append((it, net.loss.item()))
         return hist
 
     def sample_loss(self, samples, models):
-        """Mean one-step loss of the current network over `samples` (and of the
-        uncorrected coarse step, i.e. the target's own scaled energy)."""
+        """Mean one-step loss of the current network over `samples`, and that
+        of the uncorrected coarse step (a zero prediction)."""
         net = self.net
+        nz, ny, nx = net.shape
+        L = NN.lib()
         tot, base = 0.0, 0.0
         for s in samples:
-            net.rms(s.ut, self.dview)
-            net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
-                           scale=net.scale)
+            self._load(s, models)
             net.forward(keep=True)
             net.loss.zero_()
-            net.backward(s.target, scale=net.scale)
+            net.backward(s.target, scale=net.scale, gain=self.GAIN, skip=self.skip)
             tot += net.loss.item()
-            sc = net.scale[0].item()
-            base += float(torch.mean((s.target / sc) ** 2).item())
+            net.loss.zero_()
+            NN._chk(L.nn_mse(nz, ny, nx, NN._p(self._zero), NN._p(s.target), NN._p(net.scale),
+                             self.GAIN, NN._bp(self.skip), NN._p(net.g8), NN._p(net.loss),
+                             NN._s()))
+            base += net.loss.item()
         return tot / len(samples), base / len(samples)
 
 

@@ -20,6 +20,19 @@ class View(ctypes.Structure):
                 ("pitch_z", ctypes.c_int64)]
 
 
+class Box(ctypes.Structure):
+    """Half-open (z, y, x) index box [lo, hi)."""
+    _fields_ = [("lo", ctypes.c_int * 3), ("hi", ctypes.c_int * 3)]
+
+
+def box(lo, hi):
+    return Box((ctypes.c_int * 3)(*[int(v) for v in lo]), (ctypes.c_int * 3)(*[int(v) for v in hi]))
+
+
+def _bp(b):
+    return None if b is None else ctypes.byref(b)
+
+
 def dense_view(shape):
     nz, ny, nx = shape
     return View(0, nx, ny * nx)
@@ -44,14 +57,15 @@ def lib():
         L.nn_wgrad_workspace_bytes.restype = ctypes.c_int64
         L.nn_wgrad_workspace_bytes.argtypes = [i, i, i]
         L.nn_pack_weights.argtypes = [vp, vp, vp]
-        L.nn_pack_input.argtypes = [i, i, i, vp, View, vp, View, vp, View, vp, vp, vp]
+        L.nn_pack_input.argtypes = [i, i, i, vp, View, vp, View, vp, View, i, vp, vp, vp]
         L.nn_rms.argtypes = [i, i, i, vp, View, vp, vp, vp]
         L.nn_conv_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp]
-        L.nn_conv_out.argtypes = [i, i, i, vp, vp, vp, vp, vp, View, vp, View, vp, vp]
-        L.nn_mse.argtypes = [i, i, i, vp, vp, vp, vp, vp, vp]
+        bp = ctypes.POINTER(Box)
+        L.nn_conv_out.argtypes = [i, i, i, vp, vp, vp, vp, vp, View, vp, View, vp, f, bp, vp]
+        L.nn_mse.argtypes = [i, i, i, vp, vp, vp, f, bp, vp, vp, vp]
         L.nn_dgrad_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
         L.nn_wgrad.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
-        L.nn_adam.argtypes = [vp, vp, vp, vp, i, f, f, f, f, vp]
+        L.nn_adam.argtypes = [vp, vp, vp, vp, i, f, f, f, f, i, vp]
         _bound = True
     return L
 
@@ -104,8 +118,11 @@ def split_params(flat):
 class Net:
     """Device state of the 3-layer correction network for volumes of `shape`."""
 
-    def __init__(self, shape, params=None, device=0):
+    def __init__(self, shape, params=None, device=0, bias=True):
+        """bias=False: biases stay at their initial values (zero from
+        init_params) during training."""
         self.shape = tuple(int(v) for v in shape)
+        self.train_bias = bool(bias)
         self.dev = torch.device("cuda", device)
         L = lib()
         n = int(np.prod(self.shape))
@@ -143,17 +160,17 @@ class Net:
         self.pack()
 
     # -- building blocks -----------------------------------------------------
-    def pack_input(self, a, va, b, vb, c, vc, scale=None):
+    def pack_input(self, a, va, b, vb, c, vc, scale=None, c_times_a=False):
         nz, ny, nx = self.shape
-        _chk(lib().nn_pack_input(nz, ny, nx, _p(a), va, _p(b), vb, _p(c), vc, _p(scale),
-                                 _p(self.x8), _s()))
+        _chk(lib().nn_pack_input(nz, ny, nx, _p(a), va, _p(b), vb, _p(c), vc, int(c_times_a),
+                                 _p(scale), _p(self.x8), _s()))
 
     def rms(self, u, vu):
         nz, ny, nx = self.shape
         _chk(lib().nn_rms(nz, ny, nx, _p(u), vu, _p(self.scale), _p(self.flag), _s()))
 
     def forward(self, keep=True, out=None, base=None, vbase=None, vout=None, scale=None,
-                ydense=True):
+                ydense=True, gain=1.0, skip=None):
         """Layers 1-3 on self.x8.  keep: store pre-activations (training)."""
         nz, ny, nx = self.shape
         L = lib()
@@ -164,14 +181,15 @@ class Net:
         dv = dense_view(self.shape)
         _chk(L.nn_conv_out(nz, ny, nx, _p(self.a2), _p(self.packed), _p(self.params),
                            _p(self.y) if ydense else None, _p(base), vbase or dv, _p(out),
-                           vout or dv, _p(scale), _s()))
+                           vout or dv, _p(scale), float(gain), _bp(skip), _s()))
 
-    def backward(self, target, scale=None):
-        """MSE against target / scale[0] (dense FP32) and all parameter gradients."""
+    def backward(self, target, scale=None, gain=1.0, skip=None):
+        """MSE against target / (gain * scale[0]) (dense FP32, zero weight
+        inside `skip`) and all parameter gradients."""
         nz, ny, nx = self.shape
         L = lib()
-        _chk(L.nn_mse(nz, ny, nx, _p(self.y), _p(target), _p(scale), _p(self.g8), _p(self.loss),
-                      _s()))
+        _chk(L.nn_mse(nz, ny, nx, _p(self.y), _p(target), _p(scale), float(gain), _bp(skip),
+                      _p(self.g8), _p(self.loss), _s()))
         _chk(L.nn_wgrad(3, nz, ny, nx, _p(self.a2), _p(self.g8), _p(self.ws), _p(self.grads), _s()))
         _chk(L.nn_dgrad_gelu(3, nz, ny, nx, _p(self.g8), _p(self.packed), _p(self.z2),
                              _p(self.g16a), _s()))
@@ -185,5 +203,5 @@ class Net:
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.t += 1
         _chk(lib().nn_adam(_p(self.params), _p(self.grads), _p(self.m), _p(self.v), self.t,
-                           lr, b1, b2, eps, _s()))
+                           lr, b1, b2, eps, int(self.train_bias), _s()))
         self.pack()

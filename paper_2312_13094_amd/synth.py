@@ -302,6 +302,7 @@ class Learned:
     vmax: float
     src_idx: tuple          # fine-grid index of the source (even)
     rec_z: int              # fine-grid depth index of the receiver line (even)
+    rec_y: int              # fine-grid crossline index of the receiver line (even)
     f0: float
     train_seeds: list
     test_seeds: list
@@ -349,7 +350,7 @@ class Learned:
 
     def rec_fine(self):
         n = self.n_fine
-        return np.array([[self.rec_z * self.h_fine, (n // 2) * self.h_fine, 2 * i * self.h_fine]
+        return np.array([[self.rec_z * self.h_fine, self.rec_y * self.h_fine, 2 * i * self.h_fine]
                          for i in range(n // 2)])
 
     def q_fine(self):
@@ -363,12 +364,15 @@ def cfg_learned(n_fine: int = 256, nt_fine: int = 1000, ntrain: int = 64, ntest:
     """Fine 256^3 (h = 10 m, so 8, 40-point layer, dt at 0.5 CFL) and coarse
     128^3 (h = 20 m, so 4, 20-point layer, 2 dt); 1000 fine / 500 coarse
     steps; 15 Hz Ricker near the top centre; 128 receivers on coarse nodes
-    near the top; training seeds 5000.., held-out seeds 5100.."""
+    near the top, on an inline offset n/4 crossline from the source (the
+    nearest receiver is 640 m away at n = 256, beyond the source's near
+    field); training seeds 5000.., held-out seeds 5100.."""
     h = 10.0
     vmax = 4500.0
     dt = stable_dt(8, 3, h, vmax)
     s = n_fine / 256.0
     src = (2 * round(24 * s), n_fine // 2, n_fine // 2)
     return Learned("learned_%dfine_%dcoarse" % (n_fine, n_fine // 2), n_fine, h, 8, 4,
-                   2 * round(20 * s), dt, nt_fine, vmax, src, 2 * round(26 * s), 15.0,
+                   2 * round(20 * s), dt, nt_fine, vmax, src, 2 * round(26 * s),
+                   n_fine // 2 + 2 * round(n_fine / 8), 15.0,
                    list(range(5000, 5000 + ntrain)), list(range(5100, 5100 + ntest)))

@@ -1,8 +1,9 @@
 """Learned coarse-grid correction end to end at a small scale (fine 64^3 so 8,
-coarse 32^3 so 4): training on solver-generated data lowers the one-step
-error, the corrected coarse run beats the plain coarse run against the plain
-fine solve on held-out models, and non-finite weights fall back to the fine
-solve."""
+coarse 32^3 so 4, 4 training and 2 held-out models): training on
+solver-generated data lowers the one-step error, the corrected coarse run
+beats the plain coarse run against the plain fine solve on held-out models,
+the correction leaves the source box and zero fields untouched, and
+non-finite weights fall back to the fine solve."""
 import numpy as np
 import pytest
 
@@ -21,7 +22,7 @@ def trained():
     train = lc.make_samples(cfg.train_seeds, steps, models)
     test = lc.make_samples(cfg.test_seeds, steps, models)
     before, base = lc.sample_loss(test, models)
-    lc.train(train, models, iters=600, lr=2e-3, seed=0)
+    lc.train(train, models, iters=2000, lr=2e-3, seed=0)
     after, _ = lc.sample_loss(test, models)
     return lc, cfg, models, (before, base, after)
 
@@ -49,6 +50,32 @@ def test_correction_beats_plain_coarse_on_held_out_models(trained):
     assert gains, "every held-out run fell back to the fine solve"
     for e_plain, e_learned in gains:
         assert e_learned < e_plain, (gains, fell_back)
+
+
+def test_correction_is_zero_on_zero_field_and_inside_source_box(trained):
+    """N(0) = 0 (bias-free, velocity channel modulated by the field), and the
+    source box keeps the plain coarse values."""
+    import torch
+    lc, cfg, _, _ = trained
+    lc.set_model(cfg.velocity(cfg.test_seeds[0]))
+    lc.ca.zero_()
+    lc.cb.zero_()
+    lc.correct()
+    torch.cuda.synchronize()
+    assert float(lc.coarse.domain(lc.ca).abs().max()) == 0.0
+    # a field with energy everywhere: only the box stays bit-identical
+    rng = np.random.default_rng(3)
+    nc = cfg.n_coarse
+    f = torch.from_numpy(rng.standard_normal((nc,) * 3).astype(np.float32)).cuda()
+    lc.coarse.domain(lc.ca).copy_(f)
+    lc.coarse.domain(lc.cb).copy_(f * 0.9)
+    lc.correct()
+    torch.cuda.synchronize()
+    out = lc.coarse.domain(lc.ca).cpu().numpy()
+    lo, hi = list(lc.skip.lo), list(lc.skip.hi)
+    inside = tuple(slice(a, b) for a, b in zip(lo, hi))
+    np.testing.assert_array_equal(out[inside], f.cpu().numpy()[inside])
+    assert np.abs(out - f.cpu().numpy()).max() > 0.0
 
 
 def test_non_finite_network_falls_back_to_fine_solve(trained):

@@ -108,7 +108,8 @@ def test_output_layer_fp32_and_residual():
     scale[0] = 2.5
     vb = nn.View(off, py, pz)
     nn._chk(L.nn_conv_out(nz, ny, nx, nn._p(net.a2), nn._p(net.packed), nn._p(net.params),
-                          nn._p(net.y), nn._p(base), vb, nn._p(out), vb, nn._p(scale), nn._s()))
+                          nn._p(net.y), nn._p(base), vb, nn._p(out), vb, nn._p(scale), 1.0, None,
+                          nn._s()))
     torch.cuda.synchronize()
     w3, b3 = _oracle_params(p)[4:]
     y = N.conv3d(N.bf16_round(a2), w3, b3)[0]
@@ -122,6 +123,44 @@ def test_output_layer_fp32_and_residual():
     mask = np.ones(o.size, bool)
     mask[idx.ravel()] = False
     assert np.all(o[mask] == 7.0)
+    # gain and an excluded box, updated in place (out aliases base)
+    lo, hi = (2, 3, 10), (7, 9, 30)
+    bx = nn.box(lo, hi)
+    before = base.clone()
+    nn._chk(L.nn_conv_out(nz, ny, nx, nn._p(net.a2), nn._p(net.packed), nn._p(net.params),
+                          None, nn._p(base), vb, nn._p(base), vb, nn._p(scale), 1e-3,
+                          nn._bp(bx), nn._s()))
+    torch.cuda.synchronize()
+    m = N.box_mask(SHAPE, lo, hi)
+    b0 = before.cpu().numpy()[idx]
+    np.testing.assert_allclose(base.cpu().numpy()[idx], b0 + 2.5e-3 * m * got, rtol=1e-6,
+                               atol=1e-7)
+    np.testing.assert_array_equal(base.cpu().numpy()[idx][m == 0], b0[m == 0])
+    np.testing.assert_array_equal(base.cpu().numpy()[mask], before.cpu().numpy()[mask])
+
+
+def test_pack_input_modulated_channel():
+    """Third channel c * a / s when requested; BF16 rounding of the FP32 product."""
+    import torch
+    from paper_2312_13094_amd import nn
+    net = _net(_params())
+    a, b, c = _input(11)
+    a[3] = 0.0
+    dv = nn.dense_view(SHAPE)
+    scale = torch.zeros(int(nn.lib().nn_rms_scratch_floats()), device="cuda")
+    scale[0] = 4.0
+    ta, tb, tc = (torch.from_numpy(v).cuda() for v in (a, b, c))
+    net.pack_input(ta, dv, tb, dv, tc, dv, scale=scale, c_times_a=True)
+    torch.cuda.synchronize()
+    x = _from_bits(net.x8, 8)
+    ref = N.input_channels(a, b, c, 4.0, c_times_a=True)
+    # a/4, b/4 are exact in FP32; the product c * (a/4) rounds once to FP32, then to BF16
+    np.testing.assert_array_equal(x[0], N.bf16_round((a / np.float32(4.0)).astype(np.float32)))
+    np.testing.assert_array_equal(x[1], N.bf16_round((b / np.float32(4.0)).astype(np.float32)))
+    np.testing.assert_array_equal(
+        x[2], N.bf16_round((c * (a / np.float32(4.0))).astype(np.float32)))
+    assert rel_l2(x[2], ref[2]) <= 5e-3
+    assert np.all(x[2][3] == 0.0) and np.all(x[3:] == 0.0)
 
 
 @pytest.mark.parametrize("layer", [1, 2, 3])
@@ -184,13 +223,28 @@ def test_mse_and_adam():
     net.loss.zero_()
     nz, ny, nx = SHAPE
     tt = torch.from_numpy(t.ravel()).cuda()
-    nn._chk(nn.lib().nn_mse(nz, ny, nx, nn._p(net.y), nn._p(tt), None, nn._p(net.g8),
-                            nn._p(net.loss), nn._s()))
+    nn._chk(nn.lib().nn_mse(nz, ny, nx, nn._p(net.y), nn._p(tt), None, 1.0, None,
+                            nn._p(net.g8), nn._p(net.loss), nn._s()))
     torch.cuda.synchronize()
     assert abs(net.loss.item() - N.mse(y.astype(np.float64), t)) <= 1e-5 * N.mse(y, t)
     g = _from_bits(net.g8, 8)
     ref = 2 * (y.astype(np.float64) - t) / y.size
     assert rel_l2(g[0], ref) <= 5e-3 and np.all(g[1:] == 0)
+    # target scaled by 1 / (gain * s), points of a box excluded
+    lo, hi = (0, 4, 5), (6, 13, 20)
+    m = N.box_mask(SHAPE, lo, hi)
+    scale = torch.zeros(int(nn.lib().nn_rms_scratch_floats()), device="cuda")
+    scale[0] = 3.0
+    net.loss.zero_()
+    nn._chk(nn.lib().nn_mse(nz, ny, nx, nn._p(net.y), nn._p(tt), nn._p(scale), 0.25,
+                            nn._bp(nn.box(lo, hi)), nn._p(net.g8), nn._p(net.loss), nn._s()))
+    torch.cuda.synchronize()
+    tsc = t.astype(np.float64) / 0.75
+    want = N.masked_mse(y.astype(np.float64), tsc, m)
+    assert abs(net.loss.item() - want) <= 1e-5 * want
+    g = _from_bits(net.g8, 8)
+    ref = 2 * m * (y.astype(np.float64) - tsc) / y.size
+    assert rel_l2(g[0], ref) <= 5e-3 and np.all(g[0][m == 0] == 0)
     # Adam: three steps against the textbook update
     p0 = net.params.cpu().numpy().astype(np.float64)
     m = np.zeros_like(p0)
@@ -203,6 +257,22 @@ def test_mse_and_adam():
         p, m, v = N.adam_step(p, gr.astype(np.float32).astype(np.float64), m, v, step, lr=1e-2)
     torch.cuda.synchronize()
     assert np.abs(net.params.cpu().numpy() - p).max() <= 1e-5
+    # bias-free training: biases and their moments stay as they are
+    bias = np.zeros(p0.size, bool)
+    bias[1296:1312] = bias[8224:8240] = bias[8672] = True
+    net.train_bias = False
+    mdev = net.m.cpu().numpy().astype(np.float64)
+    vdev = net.v.cpu().numpy().astype(np.float64)
+    p = net.params.cpu().numpy().astype(np.float64)
+    gr = rng.standard_normal(p0.size)
+    net.grads.copy_(torch.from_numpy(gr.astype(np.float32)))
+    net.adam(lr=1e-2)
+    p, m2, v2 = N.adam_step(p, gr.astype(np.float32).astype(np.float64), mdev, vdev, 4, lr=1e-2,
+                            frozen=bias)
+    torch.cuda.synchronize()
+    got = net.params.cpu().numpy()
+    assert np.abs(got - p).max() <= 1e-5
+    np.testing.assert_array_equal(net.m.cpu().numpy()[bias], mdev[bias].astype(np.float32))
 
 
 def test_end_to_end_gradient_and_training():

@@ -95,3 +95,69 @@ def test_bf16_rounding():
     assert r[4] == 65536.0
     # representable bf16 values are fixed points
     np.testing.assert_array_equal(N.bf16_round(r.astype(np.float32)), r)
+
+
+def test_masked_mse_is_subset_sum_over_all_points():
+    """Masked points drop out of the sum but stay in the denominator; an empty
+    box is the plain MSE, a box over everything gives zero."""
+    rng = np.random.default_rng(5)
+    y, t = rng.standard_normal((2, 5, 6, 7))
+    m = N.box_mask(y.shape, (1, 2, 3), (3, 5, 6))
+    keep = np.ones(y.shape, bool)
+    keep[1:3, 2:5, 3:6] = False
+    assert keep.sum() == y.size - 2 * 3 * 3
+    ref = sum(float(d) ** 2 for d in (y - t)[keep]) / y.size
+    assert abs(N.masked_mse(y, t, m) - ref) <= 1e-14 * ref
+    assert N.masked_mse(y, t, N.box_mask(y.shape)) == N.mse(y, t)
+    assert N.masked_mse(y, t, N.box_mask(y.shape, (0, 0, 0), y.shape)) == 0.0
+
+
+def test_masked_network_gradients_finite_differences():
+    """Gradients of the masked loss match central differences, and a parameter
+    that only reaches masked outputs gets none of their error."""
+    rng = np.random.default_rng(6)
+    shapes = [(16, 3, 3, 3, 3), (16,), (16, 16, 3, 3, 3), (16,), (1, 16, 3, 3, 3), (1,)]
+    p = [rng.standard_normal(s) * 0.2 for s in shapes]
+    x = rng.standard_normal((3, 5, 4, 4))
+    t = rng.standard_normal((1, 5, 4, 4))
+    mask = N.box_mask((5, 4, 4), (1, 0, 1), (4, 3, 3))[None]
+    loss, grads = N.Net(*p).loss_and_grads(x, t, mask)
+    eps = 1e-6
+    for k, idx in [(0, (2, 2, 1, 0, 2)), (2, (4, 11, 2, 1, 1)), (4, (0, 9, 0, 2, 1)), (5, (0,))]:
+        pp = [a.copy() for a in p]
+        pm = [a.copy() for a in p]
+        pp[k][idx] += eps
+        pm[k][idx] -= eps
+        fd = (N.Net(*pp).loss_and_grads(x, t, mask)[0] -
+              N.Net(*pm).loss_and_grads(x, t, mask)[0]) / (2 * eps)
+        assert abs(fd - grads[k][idx]) <= 1e-6 * max(1e-3, abs(fd)), (k, fd, grads[k][idx])
+    # the output bias gradient is 2 * sum over unmasked points of (y - t) / N
+    y = N.Net(*p).forward(x)
+    ref = 2.0 * float(np.sum(mask * (y - t))) / y.size
+    assert abs(grads[5][0] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_input_channels_modulated_channel_vanishes_with_field():
+    rng = np.random.default_rng(7)
+    a, b, c = rng.standard_normal((3, 4, 3, 5))
+    a[1] = 0.0
+    x = N.input_channels(a, b, c, 2.0, c_times_a=True)
+    assert np.all(x[2][1] == 0.0)
+    # homogeneous of degree zero in (a, b, s)
+    np.testing.assert_allclose(N.input_channels(3 * a, 3 * b, c, 6.0, True), x, rtol=1e-15)
+    np.testing.assert_array_equal(N.input_channels(a, b, c, 2.0)[2], c)
+
+
+def test_adam_frozen_entries_are_untouched():
+    g = np.array([0.3, -2.0, 1e-3, 4.0])
+    p0 = np.array([1.0, 2.0, 3.0, 4.0])
+    m0 = np.array([0.1, 0.0, -0.2, 0.0])
+    v0 = np.array([0.01, 0.0, 0.04, 0.0])
+    fz = np.array([False, True, False, True])
+    p, m, v = N.adam_step(p0, g, m0, v0, 3, lr=0.01, frozen=fz)
+    pf, mf, vf = N.adam_step(p0, g, m0, v0, 3, lr=0.01)
+    np.testing.assert_array_equal(p[fz], p0[fz])
+    np.testing.assert_array_equal(m[fz], m0[fz])
+    np.testing.assert_array_equal(v[fz], v0[fz])
+    np.testing.assert_array_equal(p[~fz], pf[~fz])
+    np.testing.assert_array_equal(m[~fz], mf[~fz])
