@@ -66,10 +66,16 @@ def cpu_baseline(c, budget_s):
     og = O.Grid(c.shape, c.spacing, so=c.so, dt=c.dt, nbl=c.nbl, vmax=c.vmax, bc=c.boundary)
     v = c.velocity().astype(np.float64)
     q = c.q.astype(np.float64)
+    # per-step cost from a 1-step and a 3-step run (the difference drops the
+    # fixed set-up cost of a call)
     t0 = time.perf_counter()
     O.forward(og, v, c.src, q[:1], c.rec, 1)
     t1 = time.perf_counter() - t0
-    nt = int(max(1, min(c.nt, round(budget_s / max(t1, 1e-3)))))
+    t0 = time.perf_counter()
+    O.forward(og, v, c.src, q[:3], c.rec, 3)
+    t3 = time.perf_counter() - t0
+    per = max((t3 - t1) / 2.0, t3 / 6.0, 1e-3)
+    nt = int(max(1, min(c.nt, round(budget_s / per))))
     t0 = time.perf_counter()
     O.forward(og, v, c.src, q[:nt], c.rec, nt)
     dt = time.perf_counter() - t0

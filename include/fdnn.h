@@ -103,12 +103,14 @@ int nn_dgrad_gelu(int layer, int nz, int ny, int nx, const void *gin_dev,
                   const void *packed_dev, const void *z16_prev_dev, void *gz_out16_dev,
                   void *stream);
 
-/* Weight and bias gradient of layer 1, 2 or 3 (overwrites the layer's
- * slice of grads_dev, same layout as params): x = act8 (layer 1) or act16,
- * g = gz16 (layers 1, 2) or gy8 (layer 3).  Per-block partial sums in
- * workspace, then an ordered reduction (deterministic). */
+/* Weight and bias gradient of layer 1, 2 or 3 into the layer's slice of
+ * grads_dev (same layout as params): overwritten, or added to the slice's
+ * current values if accumulate is non-zero (a mini-batch summed one sample
+ * at a time).  x = act8 (layer 1) or act16, g = gz16 (layers 1, 2) or gy8
+ * (layer 3).  Per-block partial sums in workspace, then an ordered reduction
+ * (deterministic). */
 int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
-             void *workspace_dev, float *grads_dev, void *stream);
+             void *workspace_dev, float *grads_dev, int accumulate, void *stream);
 
 /* Adam (t is the 1-based step) on every weight, and on the biases too if
  * train_bias is non-zero; otherwise biases and their moments are left as

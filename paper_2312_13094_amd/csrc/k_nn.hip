@@ -320,11 +320,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const int nz, const int ny, const
     if (wave == 0 && lane < 16) pb[27 * 256 + lane] = dbacc;
 }
 
-// grads[layer slice] = sum over blocks (in block order)
+// grads[layer slice] (+)= sum over blocks (in block order)
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part,
                                                       const int nparts, const int cin_real,
                                                       const int cout_real, float *wout,
-                                                      float *bout)
+                                                      float *bout, const int accumulate)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;   // co * cin_real * 27 + ci * 27 + tap
     const int nw = cout_real * cin_real * 27;
@@ -332,12 +332,12 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ 
         const int tap = e % 27, ci = (e / 27) % cin_real, co = e / (27 * cin_real);
         float s = 0.0f;
         for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * WG_PART + tap * 256 + co * 16 + ci];
-        wout[e] = s;
+        wout[e] = accumulate ? wout[e] + s : s;
     } else if (e < nw + cout_real) {
         const int co = e - nw;
         float s = 0.0f;
         for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * WG_PART + 27 * 256 + co];
-        bout[co] = s;
+        bout[co] = accumulate ? bout[co] + s : s;
     }
 }
 
@@ -608,7 +608,7 @@ int nn_dgrad_gelu(int layer, int nz, int ny, int nx, const void *gin_dev, const 
 }
 
 int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
-             void *workspace_dev, float *grads_dev, void *stream)
+             void *workspace_dev, float *grads_dev, int accumulate, void *stream)
 {
     if (bad_shape(nz, ny, nx) || !x_dev || !g_dev || !workspace_dev || !grads_dev ||
         layer < 1 || layer > 3)
@@ -633,7 +633,7 @@ int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g
     if (rc) return rc;
     const int nout = cout_real * cin_real * 27 + cout_real;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 255) / 256), dim3(256), 0, s, part, nbk,
-                       cin_real, cout_real, grads_dev + woff, grads_dev + boff);
+                       cin_real, cout_real, grads_dev + woff, grads_dev + boff, accumulate);
     return check_launch("nn wgrad reduce");
 }
 

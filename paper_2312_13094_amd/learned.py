@@ -219,19 +219,21 @@ class LearnedCorrector:
         net.pack_input(s.ut, self.dview, s.u0, self.dview, models[s.model], self.dview,
                        scale=net.scale, c_times_a=True)
 
-    def train(self, samples, models, iters, lr=2e-3, seed=0, log_every=0):
+    def train(self, samples, models, iters, lr=2e-3, seed=0, batch=4, log_every=0):
         """Adam on the one-step MSE of the scaled residual r / (k s) outside B,
-        one random sample per step, step size lr (1 + cos(pi i / iters)) / 2;
-        returns the loss history."""
+        gradients summed over `batch` random samples per step, step size
+        lr (1 + cos(pi i / iters)) / 2; returns the loss history."""
         rng = np.random.default_rng(seed)
         net = self.net
         hist = []
         for it in range(iters):
-            s = samples[int(rng.integers(len(samples)))]
-            self._load(s, models)
             net.loss.zero_()
-            net.forward(keep=True)
-            net.backward(s.target, scale=net.scale, gain=self.GAIN, skip=self.skip)
+            for b in range(batch):
+                s = samples[int(rng.integers(len(samples)))]
+                self._load(s, models)
+                net.forward(keep=True)
+                net.backward(s.target, scale=net.scale, gain=self.GAIN, skip=self.skip,
+                             accumulate=b > 0)
             net.adam(lr=lr * 0.5 * (1.0 + np.cos(np.pi * it / iters)))
             if log_every and (it % log_every == 0 or it == iters - 1):
                 hist.append((it, net.loss.item()))

@@ -64,7 +64,7 @@ def lib():
         L.nn_conv_out.argtypes = [i, i, i, vp, vp, vp, vp, vp, View, vp, View, vp, f, bp, vp]
         L.nn_mse.argtypes = [i, i, i, vp, vp, vp, f, bp, vp, vp, vp]
         L.nn_dgrad_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
-        L.nn_wgrad.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
+        L.nn_wgrad.argtypes = [i, i, i, i, vp, vp, vp, vp, i, vp]
         L.nn_adam.argtypes = [vp, vp, vp, vp, i, f, f, f, f, i, vp]
         _bound = True
     return L
@@ -183,22 +183,25 @@ class Net:
                            _p(self.y) if ydense else None, _p(base), vbase or dv, _p(out),
                            vout or dv, _p(scale), float(gain), _bp(skip), _s()))
 
-    def backward(self, target, scale=None, gain=1.0, skip=None):
+    def backward(self, target, scale=None, gain=1.0, skip=None, accumulate=False):
         """MSE against target / (gain * scale[0]) (dense FP32, zero weight
-        inside `skip`) and all parameter gradients."""
+        inside `skip`) and all parameter gradients (added to self.grads if
+        accumulate)."""
+        acc = int(accumulate)
         nz, ny, nx = self.shape
         L = lib()
         _chk(L.nn_mse(nz, ny, nx, _p(self.y), _p(target), _p(scale), float(gain), _bp(skip),
                       _p(self.g8), _p(self.loss), _s()))
-        _chk(L.nn_wgrad(3, nz, ny, nx, _p(self.a2), _p(self.g8), _p(self.ws), _p(self.grads), _s()))
+        _chk(L.nn_wgrad(3, nz, ny, nx, _p(self.a2), _p(self.g8), _p(self.ws), _p(self.grads), acc,
+                        _s()))
         _chk(L.nn_dgrad_gelu(3, nz, ny, nx, _p(self.g8), _p(self.packed), _p(self.z2),
                              _p(self.g16a), _s()))
         _chk(L.nn_wgrad(2, nz, ny, nx, _p(self.a1), _p(self.g16a), _p(self.ws), _p(self.grads),
-                        _s()))
+                        acc, _s()))
         _chk(L.nn_dgrad_gelu(2, nz, ny, nx, _p(self.g16a), _p(self.packed), _p(self.z1),
                              _p(self.g16b), _s()))
         _chk(L.nn_wgrad(1, nz, ny, nx, _p(self.x8), _p(self.g16b), _p(self.ws), _p(self.grads),
-                        _s()))
+                        acc, _s()))
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.t += 1

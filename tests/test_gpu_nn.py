@@ -180,13 +180,27 @@ def test_weight_gradients_match_oracle(layer):
     net.grads.zero_()
     nz, ny, nx = SHAPE
     nn._chk(nn.lib().nn_wgrad(layer, nz, ny, nx, nn._p(xt), nn._p(gt), nn._p(net.ws),
-                              nn._p(net.grads), nn._s()))
+                              nn._p(net.grads), 0, nn._s()))
     torch.cuda.synchronize()
     gw, gb = N.conv3d_wgrad(N.bf16_round(x[:cin_real]), N.bf16_round(g[:co_real]))
-    parts = nn.split_params(net.grads.cpu().numpy())
+    first = net.grads.cpu().numpy()
+    parts = nn.split_params(first)
     w_got, b_got = parts[2 * layer - 2], parts[2 * layer - 1]
     assert rel_l2(w_got, gw) <= 1e-4
     assert rel_l2(b_got, gb) <= 1e-4
+    # accumulate: a second sample's gradient is added with one FP32 rounding
+    g2 = np.zeros_like(g)
+    g2[:co_real] = rng.standard_normal((co_real,) + SHAPE)
+    gt.copy_(torch.from_numpy(_bits(_cl(g2))))
+    net.grads.zero_()
+    nn._chk(nn.lib().nn_wgrad(layer, nz, ny, nx, nn._p(xt), nn._p(gt), nn._p(net.ws),
+                              nn._p(net.grads), 0, nn._s()))
+    second = net.grads.cpu().numpy()
+    net.grads.copy_(torch.from_numpy(first))
+    nn._chk(nn.lib().nn_wgrad(layer, nz, ny, nx, nn._p(xt), nn._p(gt), nn._p(net.ws),
+                              nn._p(net.grads), 1, nn._s()))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(net.grads.cpu().numpy(), first + second)
 
 
 @pytest.mark.parametrize("layer", [2, 3])
