@@ -30,9 +30,9 @@ METRIC = "Gpts/s & % HBM roofline, 3D so-8 acoustic; learned vs plain time at sa
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
 STEP_BYTES_PER_POINT = 16             # read u, u-, v^2dt^2; write u+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "acoustic_step_512cube_so8_traffic.json")
-# sources that define the step kernel and its launch (tile defaults included)
+# sources that define the step kernel and its launch (the default tile included)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2312_13094_amd", "csrc", f)
-               for f in ("zmarch.h", "k_step_radius.hip", "fd_internal.h", "fd_api.hip")]
+               for f in ("zmarch.h", "k_step_radius.hip", "fd_internal.h")]
 
 
 def _kernel_hash():
@@ -193,7 +193,7 @@ def bench_learned(args):
 
     from paper_2312_13094_amd import learned as LC
     from paper_2312_13094_amd import synth
-    c = synth.cfg_learned(ntrain=args.train_models, ntest=8)
+    c = synth.cfg_learned(ntrain=args.train_models, ntest=args.test_models)
     lc = LC.LearnedCorrector(c)
     models = []
     steps = [1, 2, 3, 5, 8] + list(range(12, c.nt_coarse - 2, 12))
@@ -204,15 +204,17 @@ def bench_learned(args):
     lc.train(train, models, iters=args.train_iters)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    after, base = lc.sample_loss(train[::max(1, len(train) // 64)], models)
     rows = []
     for seed in c.test_seeds:
         lc.set_model(c.velocity(seed))
         ref, t_fine, _ = lc.fine_solve()
         plain, t_plain = lc.coarse_solve()
-        res = lc.learned_solve()
+        eager = lc.learned_solve()
+        res = lc.learned_solve(graph=True)      # captured on the first model, replayed after
         rows.append((LC.trace_error(plain, ref), LC.trace_error(res.traces, ref), t_fine,
-                     res.seconds, t_plain, res.fallback))
-    r = np.array([x[:5] for x in rows])
+                     res.seconds, t_plain, eager.seconds, res.fallback))
+    r = np.array([x[:6] for x in rows])
     return {"metric": "learned vs plain time at same err (wall ms, held-out mean)",
             "value": round(float(r[:, 3].mean() * 1e3), 3), "unit": "ms",
             "n_gpus": 1, "steps": len(rows), "warmup": 0,
@@ -220,9 +222,14 @@ def bench_learned(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
             "config": {"workload": c.name, "fine_ms": round(float(r[:, 2].mean() * 1e3), 3),
                        "plain_coarse_ms": round(float(r[:, 4].mean() * 1e3), 3),
+                       "learned_eager_ms": round(float(r[:, 5].mean() * 1e3), 3),
+                       "learned_timing": "HIP-graph replay of the whole corrected run "
+                                         "(captured once on the first held-out model)",
+                       "one_step_loss_vs_uncorrected": [round(after, 5), round(base, 5)],
                        "trace_err_learned": [round(float(x), 4) for x in r[:, 1]],
                        "trace_err_plain_coarse": [round(float(x), 4) for x in r[:, 0]],
-                       "fallbacks": int(sum(x[5] for x in rows)),
+                       "fallbacks": int(sum(x[6] for x in rows)),
+                       "tiles": {k: list(v[0]) for k, v in lc.tiles.items()},
                        "train_models": args.train_models, "train_iters": args.train_iters,
                        "samples": len(train), "data_s": round(t_data, 1),
                        "train_s": round(t_train, 1)}}
@@ -245,6 +252,7 @@ def main():
                     help="acoustic = the headline line; the others print their own line")
     ap.add_argument("--train-models", type=int, default=64)
     ap.add_argument("--train-iters", type=int, default=3000)
+    ap.add_argument("--test-models", type=int, default=8)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -262,12 +270,22 @@ def main():
     from paper_2312_13094_amd import fd, synth
 
     dev = torch.device("cuda", 0)
+    copy_gbs = None
     if args.calibrate_copy:
-        # the library's plain copy kernel over 2 GiB: reference for HBM counters
+        # the library's plain copy kernel over 2 GiB: reference for HBM
+        # counters, and the copy bandwidth this device sustains (best of 5)
         src = torch.ones(1 << 29, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         fd.copy_floats(dst, src)
-        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fd.copy_floats(dst, src)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        copy_gbs = round(2 * src.numel() * 4 / (best * 1e-3) / 1e9, 1)
         del src, dst
     c = synth.cfg_3d_layered(n=args.n, nt=args.nt)
     g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, boundary=c.boundary)
@@ -327,7 +345,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_acoustic_zmarch (stencil + leapfrog + damping)",
                      "avg_launch_ms": round(avg_ms, 5), "launches_timed": launches,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "copy_kernel_gbs": copy_gbs},
         "cpu_baseline": None,
     }
     g.close()

@@ -116,7 +116,9 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * registers until used; bit 1 is then ignored).  by = 0 selects the
  * one-thread-per-point kernel.  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
- * arithmetic per point).  A 3-D grid starts with (8, 2, 64, 12). */
+ * arithmetic per point).  A 3-D grid starts with flags 12 and the first of
+ * (by, ry) = (8, 2), (4, 2), (4, 1) whose launch reaches 1024 blocks with
+ * nzb = 64, 32, 16 or 8 (else (4, 1, 8)): (8, 2, 64, 12) at 512^3. */
 int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int flags);
 
 /* Autotuner: pick the 3-D step kernel's tile for this handle by timed
@@ -163,6 +165,17 @@ int fd_forward(fd_grid *g, float *const *state_dev,
                const fd_sparse *src, const float *q_dev,
                const fd_sparse *rec, float *d_dev, int nt,
                float *const *ckpt_dev, int ckpt_every, void *stream);
+
+/* One update of fd_forward in place, for callers that keep their own time
+ * loop (acoustic only): um_up_dev holds u^(n-1) on entry and u^(n+1) on
+ * return, u_dev holds u^n (for FD_BC_LOOPBACK its halo is refreshed first,
+ * so it is written too).  Then src injects q_dev[ns] (this update's values;
+ * src may be NULL) and rec samples u^(n+1) into d_dev[nr] (rec may be
+ * NULL).  Bit-identical to the same update inside fd_forward; unlike
+ * fd_forward with nt = 1 it moves no field between the two buffers, so the
+ * caller alternates their roles.  Allocates nothing; enqueues on `stream`. */
+int fd_step(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src,
+            const float *q_dev, const fd_sparse *rec, float *d_dev, void *stream);
 
 /* Adjoint (exact transpose of fd_forward, acoustic): the same recurrence
  * run backwards in time, receivers injecting the residual resid[nt][nr]

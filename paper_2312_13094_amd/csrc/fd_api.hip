@@ -267,7 +267,7 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     make_geometry(d, g->ndim, g->n, g->h, r, g->L, g->sp);
     const fd_layout &L = g->L;
 
-    g->tune = d.ndim == 3 ? Tuning{8, 2, 64, kTileRing | kTileNts} : Tuning{0, 0, 0, 0};
+    g->tune = d.ndim == 3 ? default_tuning(g->n) : Tuning{0, 0, 0, 0};
 
     DeviceGuard dg(d.device);
     if (!dg.ok()) {
@@ -519,6 +519,27 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
     return FD_OK;
 }
 
+int fd_step(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src, const float *q_dev,
+            const fd_sparse *rec, float *d_dev, void *stream)
+{
+    if (!g || !u_dev || !um_up_dev || u_dev == um_up_dev)
+        return set_error(FD_EINVAL, "fd_step: bad argument");
+    if (g->d.physics != FD_ACOUSTIC) return set_error(FD_ENOTSUP, "fd_step: acoustic physics only");
+    if (!g->model_loaded) return set_error(FD_EINVAL, "fd_step: no model loaded");
+    int rc = validate_sparse(g, src, q_dev, "sources");
+    if (rc) return rc;
+    if ((rc = validate_sparse(g, rec, d_dev, "receivers"))) return rc;
+    DeviceGuard dg(g->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    SparseArgs inj{src ? src->n : 0, src ? src->base_dev : nullptr, src ? src->frac_dev : nullptr,
+                   src && src->n ? q_dev : nullptr, nullptr, (float)(1.0 / cell_volume(g))};
+    SparseArgs smp{rec ? rec->n : 0, rec ? rec->base_dev : nullptr, rec ? rec->frac_dev : nullptr,
+                   nullptr, rec && rec->n ? d_dev : nullptr, 1.0f};
+    if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, u_dev, s))) return rc;
+    if ((rc = timed_step(g, u_dev, um_up_dev, um_up_dev, s))) return rc;
+    return launch_sparse(g, um_up_dev, inj, smp, s);
+}
+
 int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const float *resid_dev,
                const fd_sparse *src, const float *q_dev, float *qadj_dev, int nt,
                float *const *ckpt_dev, int ckpt_every, float *const *slot_dev, float *grad_m_dev,
@@ -707,7 +728,7 @@ int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, v
     (void)hipEventCreate(&e1);
     const Tuning saved = g->tune;
     const int cand[7][2] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {2, 8}};
-    const int nzbs[3] = {32, 64, 128};
+    const int nzbs[5] = {8, 16, 32, 64, 128};
     double best_ms = 1e30;
     int rc = FD_OK;
     for (const auto &c : cand)

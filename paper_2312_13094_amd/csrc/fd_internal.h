@@ -85,6 +85,23 @@ struct Tuning {
 };
 constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8;
 
+// Default 3-D tile: halo ring and non-temporal hints; the first of
+// 64 x 16 (8 waves of 2 rows), 64 x 8 (4 x 2) and 64 x 4 (4 x 1) columns
+// whose launch reaches 1024 blocks with z chunks of 64 planes halved down to
+// 8 (the smallest tile with 8-plane chunks otherwise), so that small grids
+// still fill 256 CUs.
+inline Tuning default_tuning(const int n[3])
+{
+    const int shapes[3][2] = {{8, 2}, {4, 2}, {4, 1}};
+    for (const auto &sh : shapes) {
+        const int64_t tiles = (int64_t)((n[2] + 63) / 64) * ((n[1] + sh[0] * sh[1] - 1) / (sh[0] * sh[1]));
+        for (int nzb = 64; nzb >= 8; nzb /= 2)
+            if (tiles * ((n[0] + nzb - 1) / nzb) >= 1024)
+                return Tuning{sh[0], sh[1], nzb, kTileRing | kTileNts};
+    }
+    return Tuning{4, 1, 8, kTileRing | kTileNts};
+}
+
 // One set of sparse points bound to a step.
 struct SparseArgs {
     int n;

@@ -129,59 +129,18 @@ __device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
            x < b.hi[2];
 }
 
-template <int CIN, int STEPS, int EPI>
-__global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
+// Per-row epilogue of k_conv: bias, activation and stores for the 16 points
+// of row `row` of the tile (lane n holds point n; lane group g holds output
+// channels 4g..4g+3).
+template <int EPI>
+__device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, const int x0,
+                                         const int y0, const int z0, const int row, const int n,
+                                         const int g)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t tile[HZC * HYC * HXC * CIN];
-    const int ntx = (a.nx + TXC - 1) / TXC, nty = (a.ny + TYC - 1) / TYC;
-    int b = blockIdx.x;
-    const int tx = b % ntx;
-    b /= ntx;
-    const int ty = b % nty;
-    const int tz = b / nty;
-    const int x0 = tx * TXC, y0 = ty * TYC, z0 = tz * TZC;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    // weights: all K steps resident in registers
-    bf16x8 af[STEPS];
-    const bf16x8 *fr = reinterpret_cast<const bf16x8 *>(a.frag);
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) af[s] = fr[s * 64 + lane];
-
-    // halo tile, 16-byte chunks (8 channels)
-    constexpr int CH = CIN / 8;
-    constexpr int NCHUNK = HZC * HYC * HXC * CH;
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
-    uint4 *dst = reinterpret_cast<uint4 *>(tile);
-    for (int c = tid; c < NCHUNK; c += 256) {
-        const int pt = c / CH, ch = c % CH;
-        const int hx = pt % HXC, hy = (pt / HXC) % HYC, hz = pt / (HXC * HYC);
-        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
-            v = src[(((int64_t)gz * a.ny + gy) * a.nx + gx) * CH + ch];
-        dst[c] = v;
-    }
-    __syncthreads();
-
-    const int n = lane & 15, g = lane >> 4;
-    // 64 rows of 16 points; wave w takes rows w, w+4, ...
-    for (int row = wave; row < TZC * TYC; row += 4) {
+    {
         const int zl = row / TYC, yl = row % TYC;
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            const int kb = 32 * s + 8 * g;
-            int tap = kb / CIN;
-            const int c0 = kb % CIN;
-            tap = tap > 26 ? 26 : tap;              // padding steps: zero weights
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-            const int off = (((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx)) * CIN + c0;
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(tile + off);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bv, acc, 0, 0, 0);
-        }
         const int x = x0 + n, y = y0 + yl, z = z0 + zl;
-        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) return;
         const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
         if (EPI == EPI_OUT) {
             if (g == 0) {
@@ -222,6 +181,79 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                         make_uint2(zo[0] | ((uint32_t)zo[1] << 16), zo[2] | ((uint32_t)zo[3] << 16));
             }
         }
+    }
+}
+
+template <int CIN, int STEPS, int EPI>
+__global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t tile[HZC * HYC * HXC * CIN];
+    const int ntx = (a.nx + TXC - 1) / TXC, nty = (a.ny + TYC - 1) / TYC;
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int tz = b / nty;
+    const int x0 = tx * TXC, y0 = ty * TYC, z0 = tz * TZC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // weights: all K steps resident in registers
+    bf16x8 af[STEPS];
+    const bf16x8 *fr = reinterpret_cast<const bf16x8 *>(a.frag);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) af[s] = fr[s * 64 + lane];
+
+    // halo tile, 16-byte chunks (8 channels): every load of the tile is in
+    // flight before the first LDS store
+    constexpr int CH = CIN / 8;
+    constexpr int NCHUNK = HZC * HYC * HXC * CH;
+    constexpr int NIT = (NCHUNK + 255) / 256;
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
+    uint4 *dst = reinterpret_cast<uint4 *>(tile);
+    uint4 stage[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int c = tid + it * 256;
+        const int pt = c / CH, ch = c % CH;
+        const int hx = pt % HXC, hy = (pt / HXC) % HYC, hz = pt / (HXC * HYC);
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        stage[it] = make_uint4(0u, 0u, 0u, 0u);
+        if (c < NCHUNK && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+            stage[it] = src[(((int64_t)gz * a.ny + gy) * a.nx + gx) * CH + ch];
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it)
+        if (tid + it * 256 < NCHUNK) dst[tid + it * 256] = stage[it];
+    __syncthreads();
+
+    const int n = lane & 15, g = lane >> 4;
+    // 64 rows of 16 points; wave w takes rows w + 4 i, four rows at a time
+    // with independent accumulators so consecutive MFMAs do not wait on
+    // each other
+    constexpr int NR = 4;
+    for (int r0 = wave; r0 < TZC * TYC; r0 += 4 * NR) {
+        floatx4 acc[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            const int kb = 32 * s + 8 * g;
+            int tap = kb / CIN;
+            const int c0 = kb % CIN;
+            tap = tap > 26 ? 26 : tap;              // padding steps: zero weights
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const int row = r0 + 4 * j;
+                const int zl = row / TYC, yl = row % TYC;
+                const int off = (((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx)) * CIN + c0;
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(tile + off);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bv, acc[j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            epilogue<EPI>(a, acc[j], x0, y0, z0, r0 + 4 * j, n, g);
     }
 }
 
@@ -349,15 +381,16 @@ __global__ __launch_bounds__(256) void k_pack_input(const int nz, const int ny, 
                                                     const float *b, const nn_view vb,
                                                     const float *c, const nn_view vc,
                                                     const int c_times_a, const float *scale,
-                                                    uint16_t *x8)
+                                                    uint16_t *x8, const int seg)
 {
-    const int64_t n = (int64_t)nz * ny * nx;
     const float inv = scale ? 1.0f / scale[0] : 1.0f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int64_t t = i / nx;
-        const int y = (int)(t % ny), z = (int)(t / ny);
+    // seg threads per x row, blockDim / seg rows per block iteration (no
+    // 64-bit index division)
+    const int rpi = blockDim.x / seg, sub = threadIdx.x / seg, xl = threadIdx.x % seg;
+    for (int row = blockIdx.x * rpi + sub; row < nz * ny; row += gridDim.x * rpi)
+    for (int x = xl; x < nx; x += seg) {
+        const int y = row % ny, z = row / ny;
+        const int64_t i = (int64_t)row * nx + x;
         const float va_ = a[va.offset + z * va.pitch_z + y * va.pitch_y + x] * inv;
         const float vb_ = b[vb.offset + z * vb.pitch_z + y * vb.pitch_y + x] * inv;
         const float cv = c[vc.offset + z * vc.pitch_z + y * vc.pitch_y + x];
@@ -376,20 +409,24 @@ constexpr int kRmsBlocks = 256;
 // stage 1: per-block sums of squares (double) and non-finite flags
 __global__ __launch_bounds__(256) void k_rms_part(const int nz, const int ny, const int nx,
                                                   const float *u, const nn_view vu, double *part,
-                                                  unsigned *flag)
+                                                  unsigned *flag, const int seg)
 {
     __shared__ double red[256];
-    const int64_t n = (int64_t)nz * ny * nx;
     double s = 0.0;
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int64_t t = i / nx;
-        const int y = (int)(t % ny), z = (int)(t / ny);
-        const float v = u[vu.offset + z * vu.pitch_z + y * vu.pitch_y + x];
-        if (!isfinite(v)) bad = true;
-        s += (double)v * v;
+    // x rows dealt to blocks in a fixed order; FP32 partial sums per row
+    // segment, accumulated in FP64 per thread
+    const int rpi = blockDim.x / seg, sub = threadIdx.x / seg, xl = threadIdx.x % seg;
+    for (int row = blockIdx.x * rpi + sub; row < nz * ny; row += gridDim.x * rpi) {
+        const int y = row % ny, z = row / ny;
+        const float *r = u + vu.offset + z * vu.pitch_z + y * vu.pitch_y;
+        float rs = 0.0f;
+        for (int x = xl; x < nx; x += seg) {
+            const float v = r[x];
+            if (!isfinite(v)) bad = true;
+            rs = fmaf(v, v, rs);
+        }
+        s += (double)rs;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -416,18 +453,19 @@ __global__ __launch_bounds__(256) void k_mse(const int nz, const int ny, const i
                                              const float *__restrict__ y,
                                              const float *__restrict__ t,
                                              const float *__restrict__ scale, const float gain,
-                                             const nn_box skip, uint16_t *gy8, float *loss)
+                                             const nn_box skip, uint16_t *gy8, float *loss,
+                                             const int seg)
 {
     __shared__ float red[256];
     float s = 0.0f;
     const int64_t n = (int64_t)nz * ny * nx;
     const float inv = 1.0f / (float)n;
     const float ts = 1.0f / (gain * (scale ? scale[0] : 1.0f));
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int64_t r = i / nx;
-        const int yy = (int)(r % ny), z = (int)(r / ny);
+    const int rpi = blockDim.x / seg, sub = threadIdx.x / seg, xl = threadIdx.x % seg;
+    for (int row = blockIdx.x * rpi + sub; row < nz * ny; row += gridDim.x * rpi)
+    for (int x = xl; x < nx; x += seg) {
+        const int yy = row % ny, z = row / ny;
+        const int64_t i = (int64_t)row * nx + x;
         const float d = in_box(skip, z, yy, x) ? 0.0f : y[i] - t[i] * ts;
         s += d * d;
         uint4 o = make_uint4(f2bf(2.0f * d * inv), 0u, 0u, 0u);
@@ -488,16 +526,30 @@ int nn_pack_weights(const float *params_dev, void *packed_dev, void *stream)
 
 static bool bad_shape(int nz, int ny, int nx) { return nz < 1 || ny < 1 || nx < 1; }
 
+// threads per x row for the row-wise elementwise kernels (a power of two
+// dividing 256, at least min(nx, 256))
+static int row_seg(int nx)
+{
+    int s = 32;
+    while (s < 256 && s < nx) s *= 2;
+    return s;
+}
+
+static int row_blocks(int nz, int ny, int nx, int cap)
+{
+    const int64_t rows = (int64_t)nz * ny, rpi = 256 / row_seg(nx);
+    return (int)std::min<int64_t>((rows + rpi - 1) / rpi, cap);
+}
+
 int nn_pack_input(int nz, int ny, int nx, const float *a, nn_view va, const float *b, nn_view vb,
                   const float *c, nn_view vc, int c_times_a, const float *scale_dev, void *x8_dev,
                   void *stream)
 {
     if (bad_shape(nz, ny, nx) || !a || !b || !c || !x8_dev)
         return set_error(FD_EINVAL, "nn_pack_input: bad argument");
-    const int64_t n = (int64_t)nz * ny * nx;
-    const int nb = (int)std::min<int64_t>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_pack_input, dim3(nb), dim3(256), 0, (hipStream_t)stream, nz, ny, nx, a,
-                       va, b, vb, c, vc, c_times_a, scale_dev, (uint16_t *)x8_dev);
+    hipLaunchKernelGGL(k_pack_input, dim3(row_blocks(nz, ny, nx, 8192)), dim3(256), 0,
+                       (hipStream_t)stream, nz, ny, nx, a, va, b, vb, c, vc, c_times_a, scale_dev,
+                       (uint16_t *)x8_dev, row_seg(nx));
     return check_launch("nn pack input");
 }
 
@@ -510,7 +562,7 @@ int nn_rms(int nz, int ny, int nx, const float *u, nn_view vu, float *scale_dev,
     double *part = reinterpret_cast<double *>(scale_dev + 2);
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_rms_part, dim3(kRmsBlocks), dim3(256), 0, s, nz, ny, nx, u, vu, part,
-                       flag_dev);
+                       flag_dev, row_seg(nx));
     hipLaunchKernelGGL(k_rms_final, dim3(1), dim3(64), 0, s, part, (int64_t)nz * ny * nx,
                        scale_dev);
     return check_launch("nn rms");
@@ -576,11 +628,10 @@ int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,
     if (bad_shape(nz, ny, nx) || !y_dev || !t_dev || !gy8_dev || !loss_dev || !(gain > 0.0f) ||
         !std::isfinite(gain))
         return set_error(FD_EINVAL, "nn_mse: bad argument");
-    const int64_t n = (int64_t)nz * ny * nx;
-    const int nb = (int)std::min<int64_t>((n + 255) / 256, 2048);
     const nn_box sk = skip ? *skip : nn_box{{0, 0, 0}, {0, 0, 0}};
-    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, (hipStream_t)stream, nz, ny, nx, y_dev,
-                       t_dev, scale_dev, gain, sk, (uint16_t *)gy8_dev, loss_dev);
+    hipLaunchKernelGGL(k_mse, dim3(row_blocks(nz, ny, nx, 2048)), dim3(256), 0,
+                       (hipStream_t)stream, nz, ny, nx, y_dev, t_dev, scale_dev, gain, sk,
+                       (uint16_t *)gy8_dev, loss_dev, row_seg(nx));
     return check_launch("nn mse");
 }
 

@@ -70,6 +70,7 @@ def lib():
     L.fd_forward.argtypes = [vp, P(vp), P(SparseC), vp, P(SparseC), vp, i, P(vp), i, vp]
     L.fd_adjoint.argtypes = [vp, P(vp), P(SparseC), vp, P(SparseC), vp, vp, i, P(vp), i, P(vp),
                              vp, vp]
+    L.fd_step.argtypes = [vp, vp, vp, P(SparseC), vp, P(SparseC), vp, vp]
     L.fd_gradient_to_velocity.argtypes = [vp, vp, vp, vp]
     L.fd_sample.argtypes = [vp, vp, P(SparseC), vp, vp]
     L.fd_autotune.argtypes = [vp, ctypes.c_char_p, P(ctypes.c_int), P(ctypes.c_double), vp]
@@ -230,6 +231,13 @@ class Grid:
             ctypes.byref(src.c) if src else None, _ptr(q), _ptr(qadj), int(nt),
             _ptr_array(ckpt), int(ckpt_every), _ptr_array(slots), _ptr(grad_m),
             _stream(self.device)))
+
+    def step(self, u, um_up, src=None, q=None, rec=None, d=None):
+        """One update in place: um_up (u^(n-1)) becomes u^(n+1); q, d are this
+        update's source values and receiver outputs."""
+        _check(lib().fd_step(
+            self.handle, _ptr(u), _ptr(um_up), ctypes.byref(src.c) if src else None, _ptr(q),
+            ctypes.byref(rec.c) if rec else None, _ptr(d), _stream(self.device)))
 
     def sample(self, field, rec, out):
         _check(lib().fd_sample(self.handle, _ptr(field), ctypes.byref(rec.c), _ptr(out),

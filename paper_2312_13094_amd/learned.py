@@ -99,6 +99,11 @@ class LearnedCorrector:
         self.fine.set_model(vf)
         vc = vf[::2, ::2, ::2].contiguous()
         self.coarse.set_model(vc)
+        if not getattr(self, "_tuned", False):
+            # the library's autotuner picks both grids' step tiles once (the
+            # plain fine solve, the reference, is tuned too)
+            self.tiles = {"fine": self.fine.autotune(), "coarse": self.coarse.autotune()}
+            self._tuned = True
         # network input channel: (v - 3000) / 1500
         self.vhat.copy_(vc).sub_(3000.0).div_(1500.0)
 
@@ -142,36 +147,67 @@ class LearnedCorrector:
         return d.double().cpu().numpy(), time.perf_counter() - t0
 
     # -- learned run ---------------------------------------------------------
-    def coarse_step(self, n):
-        """ca, cb = (u(n), u(n-1)) -> (u~(n+1), u(n))."""
-        self.coarse.forward([self.ca, self.cb], self.Sc, self.qc[n:n + 1], None, None, 1)
+    def coarse_step(self, n, u, um_up):
+        """Plain coarse update n in place: um_up (u(n-1)) becomes u~(n+1)."""
+        self.coarse.step(u, um_up, self.Sc, self.qc[n])
 
-    def correct(self):
-        """ca <- ca + k s N(ca/s, cb/s, vhat ca/s) outside B, s = rms(ca)."""
+    def correct(self, new, old):
+        """new <- new + k s N(new/s, old/s, vhat new/s) outside B, s = rms(new)."""
         net = self.net
-        net.rms(self.ca, self.cview)
-        net.pack_input(self.ca, self.cview, self.cb, self.cview, self.vhat, self.dview,
+        net.rms(new, self.cview)
+        net.pack_input(new, self.cview, old, self.cview, self.vhat, self.dview,
                        scale=net.scale, c_times_a=True)
-        net.forward(keep=False, out=self.ca, base=self.ca, vbase=self.cview, vout=self.cview,
+        net.forward(keep=False, out=new, base=new, vbase=self.cview, vout=self.cview,
                     scale=net.scale, ydense=False, gain=self.GAIN, skip=self.skip)
 
-    def learned_solve(self, guard=True):
-        """Corrected coarse run; falls back to the plain fine solve if the
-        corrected wavefield turns non-finite or its RMS in the last quarter of
-        the run exceeds twice its peak over the first three quarters."""
+    def _corrected_run(self, d, hist):
+        """The whole corrected coarse run from rest: traces into d, the RMS of
+        every coarse prediction into hist, non-finite values flagged in
+        net.flag.  Enqueues only (no host synchronisation), so it can be
+        captured into a graph."""
         c = self.cfg
         self.ca.zero_()
         self.cb.zero_()
         self.net.flag.zero_()
-        d = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32, device=self.dev)
-        hist = torch.zeros(c.nt_coarse, dtype=torch.float32, device=self.dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        u, um = self.ca, self.cb
         for n in range(c.nt_coarse):
-            self.coarse_step(n)
-            self.correct()
+            self.coarse_step(n, u, um)
+            self.correct(um, u)
             hist[n:n + 1].copy_(self.net.scale[:1])
-            self.coarse.sample(self.ca, self.Rc, d[n])
+            self.coarse.sample(um, self.Rc, d[n])
+            u, um = um, u
+
+    def learned_solve(self, guard=True, graph=False):
+        """Corrected coarse run; falls back to the plain fine solve if the
+        corrected wavefield turns non-finite or its RMS in the last quarter of
+        the run exceeds twice its peak over the first three quarters.
+
+        graph=True records the run into a HIP graph on first use (the
+        coarse model and network weights are read from the same buffers on
+        every replay, so later models and weights need no new capture) and
+        replays it; the time reported is the replay's."""
+        c = self.cfg
+        if graph:
+            if getattr(self, "_graph", None) is None:
+                self._gd = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32,
+                                       device=self.dev)
+                self._gh = torch.zeros(c.nt_coarse, dtype=torch.float32, device=self.dev)
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    self._corrected_run(self._gd, self._gh)
+                torch.cuda.synchronize()
+                self._graph = g
+            d, hist = self._gd, self._gh
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self._graph.replay()
+        else:
+            d = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32, device=self.dev)
+            hist = torch.zeros(c.nt_coarse, dtype=torch.float32, device=self.dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self._corrected_run(d, hist)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         tr = d.double().cpu().numpy()
@@ -208,8 +244,8 @@ class LearnedCorrector:
                 self.cb.zero_()
                 self.coarse.domain(self.ca).copy_(u0)
                 self.coarse.domain(self.cb).copy_(um)
-                self.coarse_step(n)
-                ut = self.coarse.domain(self.ca).contiguous()
+                self.coarse_step(n, self.ca, self.cb)
+                ut = self.coarse.domain(self.cb).contiguous()
                 samples.append(Sample(ut, u0.clone(), (up - ut).contiguous(), mi))
         return samples
 

@@ -268,6 +268,42 @@ def test_headline_512_plane_wave_500_steps():
 # multi-subdomain emulation on the device (external halos, pack/unpack)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("boundary", [0, 1])
+def test_step_loop_equals_forward(boundary):
+    """fd_step with alternating buffer roles reproduces fd_forward bit for
+    bit: states, and traces sampled after every update."""
+    import torch
+    FD = _fd()
+    rng = np.random.default_rng(12)
+    shape, so, h, vmax, nt = (24, 21, 70), 8, 10.0, 3000.0, 9
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, 3, h, vmax)
+    src = np.array([[11.3 * h, 9.7 * h, 33.2 * h]])
+    rec = np.array([[5 * h, 10.5 * h, (3 + 2 * i) * h] for i in range(30)])
+    q = synth.ricker(nt, dt, 25.0)[:, None].astype(np.float32)
+    u0 = synth.smooth_state(shape, 6, 3.0)
+    g = FD.Grid(shape, (h,) * 3, so, dt, vmax, nbl=5, boundary=boundary)
+    g.set_model(to_dev(v))
+    S, R = g.sparse(src), g.sparse(rec)
+    qd = to_dev(q)
+    a, b = g.field(), g.field()
+    g.domain(a).copy_(to_dev(u0))
+    d_ref = torch.zeros((nt, R.n), device="cuda")
+    g.forward([a, b], S, qd, R, d_ref, nt)
+    c, e = g.field(), g.field()
+    g.domain(c).copy_(to_dev(u0))
+    d = torch.zeros_like(d_ref)
+    cur, prev = c, e
+    for n in range(nt):
+        g.step(cur, prev, S, qd[n], R, d[n])
+        cur, prev = prev, cur
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(g.domain(cur).cpu().numpy(), g.domain(a).cpu().numpy())
+    np.testing.assert_array_equal(g.domain(prev).cpu().numpy(), g.domain(b).cpu().numpy())
+    np.testing.assert_array_equal(d.cpu().numpy(), d_ref.cpu().numpy())
+    g.close()
+
+
 def test_multidomain_emulation_bitwise():
     import torch
     FD = _fd()

@@ -60,7 +60,7 @@ def test_correction_is_zero_on_zero_field_and_inside_source_box(trained):
     lc.set_model(cfg.velocity(cfg.test_seeds[0]))
     lc.ca.zero_()
     lc.cb.zero_()
-    lc.correct()
+    lc.correct(lc.ca, lc.cb)
     torch.cuda.synchronize()
     assert float(lc.coarse.domain(lc.ca).abs().max()) == 0.0
     # a field with energy everywhere: only the box stays bit-identical
@@ -69,13 +69,31 @@ def test_correction_is_zero_on_zero_field_and_inside_source_box(trained):
     f = torch.from_numpy(rng.standard_normal((nc,) * 3).astype(np.float32)).cuda()
     lc.coarse.domain(lc.ca).copy_(f)
     lc.coarse.domain(lc.cb).copy_(f * 0.9)
-    lc.correct()
+    lc.correct(lc.ca, lc.cb)
     torch.cuda.synchronize()
     out = lc.coarse.domain(lc.ca).cpu().numpy()
     lo, hi = list(lc.skip.lo), list(lc.skip.hi)
     inside = tuple(slice(a, b) for a, b in zip(lo, hi))
     np.testing.assert_array_equal(out[inside], f.cpu().numpy()[inside])
     assert np.abs(out - f.cpu().numpy()).max() > 0.0
+
+
+def test_graph_replay_equals_eager_run(trained):
+    """The captured corrected run replays bit-identically to the eager one,
+    for a second model loaded into the same buffers and with eager work
+    between the replays."""
+    lc, cfg, _, _ = trained
+    out = []
+    for seed in cfg.test_seeds[:2]:
+        lc.set_model(cfg.velocity(seed))
+        eager = lc.learned_solve(guard=False)
+        g1 = lc.learned_solve(guard=False, graph=True)
+        plain, _ = lc.coarse_solve()
+        g2 = lc.learned_solve(guard=False, graph=True)
+        np.testing.assert_array_equal(g1.traces, eager.traces)
+        np.testing.assert_array_equal(g2.traces, eager.traces)
+        out.append(eager.traces)
+    assert not np.array_equal(out[0], out[1])
 
 
 def test_non_finite_network_falls_back_to_fine_solve(trained):
