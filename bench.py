@@ -96,6 +96,10 @@ def bench_tti(args):
     c = synth.cfg_tti(n=n, nt=args.nt)
     g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, physics=fd.FD_TTI,
                 eps_max=c.eps_max)
+    tile = [int(t) for t in args.tile.split(",")] if args.tile else None
+    if tile:
+        g.set_tile(*tile)
+    zm = not tile or tile[0] > 0
     f = {k: torch.from_numpy(v).cuda() for k, v in c.fields.items()}
     g.set_model(f["v"], [f["eps"], f["delta"], f["theta"], f["phi"]])
     del f
@@ -121,11 +125,14 @@ def bench_tti(args):
             "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": c.name + "_%dsteps" % c.nt, "shape": list(c.shape),
-                       "space_order": c.so, "time_steps": c.nt},
+                       "space_order": c.so, "time_steps": c.nt, "tile": args.tile or "default"},
             "roofline": {"bound": "hbm", "achieved": round(alg / (avg * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": None, "kernel": "k_tti_pass1 + k_tti_pass2 (one step)",
+                         "traffic": None,
+                         "kernel": ("k_tti_grad_zm + k_tti_div_zm" if zm else
+                                    "k_tti_pass1 + k_tti_pass2") + " (one step, two passes "
+                                   "moving 100 B/pt: 24 B of intermediates written and read)",
                          "avg_launch_ms": round(avg, 5), "launches_timed": nl,
                          "algorithmic_bytes_per_launch": alg}}
 

@@ -114,7 +114,9 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * v^2 dt^2 loads with bit 3, u+ stores), bit 3 issues each plane's x/y halo
  * loads together with the neighbouring tiles' loads of that plane (kept in
  * registers until used; bit 1 is then ignored).  by = 0 selects the
- * one-thread-per-point kernel.  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
+ * one-thread-per-point kernel.  FD_TTI grids use only by = 0 (the
+ * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 8
+ * tile with nzb planes per block).  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
  * arithmetic per point).  A 3-D grid starts with flags 12 and the first of
  * (by, ry) = (8, 2), (4, 2), (4, 1) whose launch reaches 1024 blocks with

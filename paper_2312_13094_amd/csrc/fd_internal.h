@@ -189,5 +189,9 @@ int launch_tti_model(const fd_grid *g, const float *vel, const float *const *tti
                      hipStream_t s);
 int launch_tti_step(const fd_grid *g, const float *p, const float *pm, float *pp, const float *r,
                     const float *rm, float *rp, hipStream_t s);
+// z-marching TTI passes (k_tti_zmarch.hip), used by launch_tti_step for 3-D
+// grids whose tile is not the one-thread-per-point kernel
+int launch_tti_step_zm(const fd_grid *g, const float *p, const float *pm, float *pp,
+                       const float *r, const float *rm, float *rp, hipStream_t s);
 
 }  // namespace fd

@@ -221,9 +221,14 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
         if (c < NCHUNK && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
             stage[it] = src[(((int64_t)gz * a.ny + gy) * a.nx + gx) * CH + ch];
     }
+    // with two 16-byte chunks per point, the chunks of points whose index has
+    // bit 2 set are stored swapped: the 8 lanes served together by a 128-bit
+    // LDS read (8 consecutive points, 32 bytes apart) then hit distinct banks
 #pragma unroll
-    for (int it = 0; it < NIT; ++it)
-        if (tid + it * 256 < NCHUNK) dst[tid + it * 256] = stage[it];
+    for (int it = 0; it < NIT; ++it) {
+        const int c = tid + it * 256;
+        if (c < NCHUNK) dst[CH == 2 ? (c ^ ((c >> 3) & 1)) : c] = stage[it];
+    }
     __syncthreads();
 
     const int n = lane & 15, g = lane >> 4;
@@ -246,8 +251,9 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
             for (int j = 0; j < NR; ++j) {
                 const int row = r0 + 4 * j;
                 const int zl = row / TYC, yl = row % TYC;
-                const int off = (((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx)) * CIN + c0;
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(tile + off);
+                const int pt = ((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx);
+                const int cs = CIN == 16 ? (c0 ^ (((pt >> 2) & 1) << 3)) : c0;
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(tile + pt * CIN + cs);
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bv, acc[j], 0, 0, 0);
             }
         }
@@ -404,7 +410,8 @@ __global__ __launch_bounds__(256) void k_pack_input(const int nz, const int ny, 
     }
 }
 
-constexpr int kRmsBlocks = 256;
+constexpr int kRmsBlocks = 1024;
+static_assert(kRmsBlocks % 256 == 0, "k_rms_final splits the partials over 256 threads");
 
 // stage 1: per-block sums of squares (double) and non-finite flags
 __global__ __launch_bounds__(256) void k_rms_part(const int nz, const int ny, const int nx,
@@ -439,14 +446,23 @@ __global__ __launch_bounds__(256) void k_rms_part(const int nz, const int ny, co
 }
 
 // stage 2: ordered sum of the block sums -> sqrt(mean) (deterministic)
-__global__ __launch_bounds__(64) void k_rms_final(const double *part, const int64_t n,
-                                                  float *scale)
+__global__ __launch_bounds__(256) void k_rms_final(const double *part, const int64_t n,
+                                                   float *scale)
 {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < kRmsBlocks; ++b) s += part[b];
-        scale[0] = (float)sqrt(s / (double)n) + 1e-30f;
+    // each thread sums kRmsBlocks / 256 consecutive partials, then a fixed
+    // tree: the same order on every call
+    __shared__ double red[256];
+    double s = 0.0;
+    constexpr int per = kRmsBlocks / 256;
+#pragma unroll
+    for (int b = 0; b < per; ++b) s += part[threadIdx.x * per + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) scale[0] = (float)sqrt(red[0] / (double)n) + 1e-30f;
 }
 
 __global__ __launch_bounds__(256) void k_mse(const int nz, const int ny, const int nx,
@@ -563,7 +579,7 @@ int nn_rms(int nz, int ny, int nx, const float *u, nn_view vu, float *scale_dev,
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_rms_part, dim3(kRmsBlocks), dim3(256), 0, s, nz, ny, nx, u, vu, part,
                        flag_dev, row_seg(nx));
-    hipLaunchKernelGGL(k_rms_final, dim3(1), dim3(64), 0, s, part, (int64_t)nz * ny * nx,
+    hipLaunchKernelGGL(k_rms_final, dim3(1), dim3(256), 0, s, part, (int64_t)nz * ny * nx,
                        scale_dev);
     return check_launch("nn rms");
 }

@@ -165,6 +165,7 @@ static void tti_r(const fd_grid *g, const float *p, const float *pm, float *pp, 
 int launch_tti_step(const fd_grid *g, const float *p, const float *pm, float *pp, const float *r,
                     const float *rm, float *rp, hipStream_t s)
 {
+    if (g->ndim == 3 && g->tune.by > 0) return launch_tti_step_zm(g, p, pm, pp, r, rm, rp, s);
     switch (g->r) {
     case 2: tti_r<2>(g, p, pm, pp, r, rm, rp, s); break;
     case 3: tti_r<3>(g, p, pm, pp, r, rm, rp, s); break;

@@ -324,3 +324,35 @@ def test_end_to_end_gradient_and_training():
         net.adam(lr=3e-3)
         losses.append(net.loss.item())
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_rms_and_non_finite_flag():
+    """nn_rms over a padded view: sqrt(mean(u^2)) within FP32 summation
+    error, the same value on every call, and the flag raised by one NaN."""
+    import torch
+    from paper_2312_13094_amd import nn
+    rng = np.random.default_rng(13)
+    nz, ny, nx = SHAPE
+    pz, py = (ny + 3) * 40, 40
+    off = 1 * pz + 2 * py + 1
+    u = torch.from_numpy(rng.standard_normal((nz + 2) * pz).astype(np.float32)).cuda()
+    idx = off + np.arange(nz)[:, None, None] * pz + np.arange(ny)[None, :, None] * py + \
+        np.arange(nx)[None, None, :]
+    vals = u.cpu().numpy()[idx].astype(np.float64)
+    net = _net(_params())
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L = nn.lib()
+    got = []
+    for _ in range(2):
+        nn._chk(L.nn_rms(nz, ny, nx, nn._p(u), nn.View(off, py, pz), nn._p(net.scale),
+                         nn._p(flag), nn._s()))
+        torch.cuda.synchronize()
+        got.append(net.scale[0].item())
+    assert got[0] == got[1]
+    assert abs(got[0] - np.sqrt(np.mean(vals ** 2))) <= 1e-6 * got[0]
+    assert flag.item() == 0
+    u[int(idx[3, 5, 7])] = float("nan")
+    nn._chk(L.nn_rms(nz, ny, nx, nn._p(u), nn.View(off, py, pz), nn._p(net.scale),
+                     nn._p(flag), nn._s()))
+    torch.cuda.synchronize()
+    assert flag.item() == 1
