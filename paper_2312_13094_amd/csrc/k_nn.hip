@@ -240,8 +240,9 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
         floatx4 acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
+        // B fragments of step s+1 are read from LDS while the MFMAs of step s
+        // run (two register sets)
+        auto fetch = [&](const int s, bf16x8 *bv) {
             const int kb = 32 * s + 8 * g;
             int tap = kb / CIN;
             const int c0 = kb % CIN;
@@ -253,9 +254,18 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                 const int zl = row / TYC, yl = row % TYC;
                 const int pt = ((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx);
                 const int cs = CIN == 16 ? (c0 ^ (((pt >> 2) & 1) << 3)) : c0;
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(tile + pt * CIN + cs);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bv, acc[j], 0, 0, 0);
+                bv[j] = *reinterpret_cast<const bf16x8 *>(tile + pt * CIN + cs);
             }
+        };
+        bf16x8 bq[2][NR];
+        fetch(0, bq[0]);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            if (s + 1 < STEPS) fetch(s + 1, bq[(s + 1) & 1]);
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[s], bq[s & 1][j], acc[j], 0,
+                                                                  0, 0);
         }
 #pragma unroll
         for (int j = 0; j < NR; ++j)
