@@ -192,13 +192,13 @@ static void prof_release(fd_grid *g)
     g->prof_used = 0;
 }
 
+// Pack every face into the handle's buffers and unpack each into the
+// opposite halo (periodic self-neighbour), fused into one pass: same
+// buffers and halo values as launch_pack followed by launch_unpack with
+// recv[f] = buf[f ^ 1].
 static int halo_exchange_loopback(fd_grid *g, float *field, hipStream_t s)
 {
-    int rc = launch_pack(g, field, 0x3fu, g->facebuf, s);
-    if (rc) return rc;
-    const float *recv[6];
-    for (int f = 0; f < 6; ++f) recv[f] = g->facebuf[f ^ 1];
-    return launch_unpack(g, field, 0x3fu, recv, s);
+    return launch_loopback(g, field, g->facebuf, s);
 }
 
 }  // namespace fd

@@ -178,6 +178,7 @@ int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *cons
                 hipStream_t s);
 int launch_unpack(const fd_grid *g, float *field, unsigned mask, const float *const *buf,
                   hipStream_t s);
+int launch_loopback(const fd_grid *g, float *field, float *const *buf, hipStream_t s);
 int launch_swap(float *a, float *b, int64_t n, hipStream_t s);
 int launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
 int launch_build_vdt2(const fd_grid *g, const float *vel, float *vdt2, unsigned *vmax_bits,

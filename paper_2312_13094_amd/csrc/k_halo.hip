@@ -61,6 +61,54 @@ __global__ __launch_bounds__(256) void k_faces(float *field, const FaceJob job,
     }
 }
 
+// Loopback exchange in one pass: face f's OWNED slab is packed into buf[f]
+// and, in the same pass, written into the HALO slab beyond face f^1 -- what
+// unpack of the buffer received across face f^1 (buf[f] itself on a
+// periodic self-neighbour) would write.  Owned slabs lie inside DOMAIN and
+// halo slabs outside it, so no element is both read and written.
+struct LoopJob {
+    FaceJob own;          // owned slabs and their buffers
+    int hstart[6][3];     // origin of the halo slab that face f's slab fills
+};
+
+__global__ __launch_bounds__(256) void k_faces_loopback(float *field, const LoopJob job,
+                                                        const int64_t offset, const int64_t PY,
+                                                        const int64_t PZ)
+{
+    const int f = blockIdx.y;
+    const int n = job.own.elems[f];
+    if (n == 0) return;
+    const int c1 = job.own.cnt[f][1], c2 = job.own.cnt[f][2];
+    const int sz = job.own.start[f][0], sy = job.own.start[f][1], sx = job.own.start[f][2];
+    const int hz = job.hstart[f][0], hy = job.hstart[f][1], hx = job.hstart[f][2];
+    float *buf = job.own.buf[f];
+    if (job.own.vec[f]) {
+        const int q2 = c2 >> 2;
+        const int nq = n >> 2;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nq; e += gridDim.x * blockDim.x) {
+            const int i2 = e % q2;
+            const int t = e / q2;
+            const int i1 = t % c1;
+            const int i0 = t / c1;
+            const float4 v = *reinterpret_cast<const float4 *>(
+                field + offset + (int64_t)(sz + i0) * PZ + (int64_t)(sy + i1) * PY + (sx + 4 * i2));
+            reinterpret_cast<float4 *>(buf)[e] = v;
+            *reinterpret_cast<float4 *>(field + offset + (int64_t)(hz + i0) * PZ +
+                                        (int64_t)(hy + i1) * PY + (hx + 4 * i2)) = v;
+        }
+        return;
+    }
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int i2 = e % c2;
+        const int t = e / c2;
+        const int i1 = t % c1;
+        const int i0 = t / c1;
+        const float v = field[offset + (int64_t)(sz + i0) * PZ + (int64_t)(sy + i1) * PY + (sx + i2)];
+        buf[e] = v;
+        field[offset + (int64_t)(hz + i0) * PZ + (int64_t)(hy + i1) * PY + (hx + i2)] = v;
+    }
+}
+
 static void face_job(const fd_grid *g, unsigned mask, bool halo_side, FaceJob &job, int &maxe)
 {
     maxe = 0;
@@ -109,6 +157,27 @@ int launch_unpack(const fd_grid *g, float *field, unsigned mask, const float *co
     hipLaunchKernelGGL(k_faces<true>, dim3(nbx, 6), dim3(256), 0, s, field, job, g->L.offset,
                        g->L.pitch_y, g->L.pitch_z);
     return check_launch("halo unpack");
+}
+
+int launch_loopback(const fd_grid *g, float *field, float *const *buf, hipStream_t s)
+{
+    LoopJob job;
+    FaceJob halo;
+    int maxe, maxh;
+    face_job(g, 0x3fu, false, job.own, maxe);
+    face_job(g, 0x3fu, true, halo, maxh);
+    for (int f = 0; f < 6; ++f) {
+        job.own.buf[f] = job.own.elems[f] ? buf[f] : nullptr;
+        // face f's slab fills the halo beyond face f^1; both slabs have the
+        // same extents, and the vector path needs both origins 4-aligned
+        for (int a = 0; a < 3; ++a) job.hstart[f][a] = halo.start[f ^ 1][a];
+        job.own.vec[f] = job.own.vec[f] && halo.vec[f ^ 1];
+    }
+    if (maxe == 0) return FD_OK;
+    const int nbx = std::min((maxe + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_faces_loopback, dim3(nbx, 6), dim3(256), 0, s, field, job, g->L.offset,
+                       g->L.pitch_y, g->L.pitch_z);
+    return check_launch("halo loopback exchange");
 }
 
 __global__ __launch_bounds__(256) void k_swap(float4 *a, float4 *b, int64_t n4)

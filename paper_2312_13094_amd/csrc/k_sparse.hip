@@ -14,7 +14,7 @@
 
 namespace fd {
 
-__global__ __launch_bounds__(256) void k_sparse(float *u, const float *__restrict__ vdt2,
+__global__ __launch_bounds__(1024) void k_sparse(float *u, const float *__restrict__ vdt2,
                                                 const StepParams p, const int ndim,
                                                 const SparseArgs inj, const SparseArgs smp)
 {
@@ -47,7 +47,10 @@ int launch_sparse(const fd_grid *g, float *u, const SparseArgs &inj, const Spars
                   hipStream_t s)
 {
     if (inj.n == 0 && smp.n == 0) return FD_OK;
-    hipLaunchKernelGGL(k_sparse, dim3(1), dim3(256), 0, s, u, g->vdt2, g->sp, g->ndim, inj, smp);
+    // one block (injection before sampling needs a block-wide barrier); 1024
+    // threads so that up to 1024 receivers sample with their corner loads
+    // in flight together
+    hipLaunchKernelGGL(k_sparse, dim3(1), dim3(1024), 0, s, u, g->vdt2, g->sp, g->ndim, inj, smp);
     return check_launch("sparse inject/sample");
 }
 

@@ -64,6 +64,32 @@ def test_pack_unpack_bit_exact(shape, so):
     del r
 
 
+@pytest.mark.parametrize("shape,so", [((12, 10, 40), 8), ((9, 11, 13), 6), ((14, 37), 4)])
+def test_loopback_exchange_equals_pack_then_unpack(shape, so):
+    """The fused loopback exchange inside a loopback update leaves the
+    current field exactly as the oracle's face pack followed by unpack of
+    the opposite face's buffer (periodic self-neighbour) would."""
+    import torch
+    FD = _fd()
+    rng = np.random.default_rng(5)
+    h = (10.0,) * len(shape)
+    dt = synth.stable_dt(so, len(shape), 10.0, 3000.0)
+    g = FD.Grid(shape, h, so, dt, 3000.0, boundary=FD.FD_BC_LOOPBACK)
+    g.set_model(to_dev(np.full(shape, 2000.0, np.float32)))
+    og = O.Grid(shape, h, so=so, dt=dt)
+    a, b = g.field(), g.field()
+    a.copy_(torch.from_numpy(rng.standard_normal(g.field_elems).astype(np.float32)))
+    ref = og.zeros()
+    ref[...] = g.with_halo(a).double().cpu().numpy()
+    packed = [O.pack_face(og, ref, k) if O.face_elems(og, k) else None for k in range(6)]
+    for k in range(6):
+        if packed[k ^ 1] is not None:
+            O.unpack_face(og, ref, k, packed[k ^ 1])
+    g.step(a, b)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(g.with_halo(a).double().cpu().numpy(), ref)
+
+
 def test_pack_rejects_bad_face_mask():
     import torch
     FD = _fd()
