@@ -108,12 +108,14 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
 
 /* Select the 3-D step kernel's tile: blocks of 64 x by threads, each thread
  * computing ry consecutive rows (tile 64 x by*ry points), nzb planes per
- * block.  flags (0..15): bit 0 remaps blocks so each XCD sweeps a
+ * block.  flags (0..31): bit 0 remaps blocks so each XCD sweeps a
  * contiguous tile range, bit 1 keeps two planes of loads in flight instead
  * of one, bit 2 puts the non-temporal hint on the streamed fields (u-,
  * v^2 dt^2 loads with bit 3, u+ stores), bit 3 issues each plane's x/y halo
  * loads together with the neighbouring tiles' loads of that plane (kept in
- * registers until used; bit 1 is then ignored).  by = 0 selects the
+ * registers until used; bit 1 is then ignored), bit 4 makes the tile 128
+ * columns wide with two columns per lane (with bit 3 behaviour; only for
+ * (by, ry) = (8,2) (4,2) (4,4)).  by = 0 selects the
  * one-thread-per-point kernel.  FD_TTI grids use only by = 0 (the
  * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 8
  * tile with nzb planes per block).  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)

@@ -334,7 +334,8 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
     if (g->ndim != 3) return set_error(FD_EINVAL, "tiles apply to 3-D grids");
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
                        (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
-    if (!known || nzb < 1 || xcd < 0 || xcd > 15)
+    const bool wide_ok = (by == 8 && ry == 2) || (by == 4 && (ry == 2 || ry == 4));
+    if (!known || nzb < 1 || xcd < 0 || xcd > 31 || ((xcd & kTileWide) && !wide_ok))
         return set_error(FD_EINVAL, "unsupported tile shape");
     g->tune = Tuning{by, ry, nzb, xcd};
     return FD_OK;
@@ -733,7 +734,10 @@ int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, v
     int rc = FD_OK;
     for (const auto &c : cand)
         for (int nzb : nzbs)
-            for (int xcd = 0; xcd < 16; ++xcd) {
+            for (int xcd = 0; xcd < 32; ++xcd) {
+                const bool wide_ok = (c[0] == 8 && c[1] == 2) ||
+                                     (c[0] == 4 && (c[1] == 2 || c[1] == 4));
+                if ((xcd & kTileWide) && !wide_ok) continue;
                 g->tune = Tuning{c[0], c[1], nzb, xcd};
                 if ((rc = launch_step(g, a, b, b, s))) break;   // warm-up
                 (void)hipEventRecord(e0, s);

@@ -81,9 +81,10 @@ struct Tuning {
     int nzb;       // planes per block (z chunk)
     int flags;     // bit 0: XCD-aware block remap; bit 1: prefetch two planes
                    // ahead; bit 2: non-temporal hints on the streamed fields;
-                   // bit 3: halo loads issued with the neighbours' front loads
+                   // bit 3: halo loads issued with the neighbours' front loads;
+                   // bit 4: 128-wide tiles, two columns per lane (implies bit 3)
 };
-constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8;
+constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8, kTileWide = 16;
 
 // Default 3-D tile: halo ring and non-temporal hints; the first of
 // 64 x 16 (8 waves of 2 rows), 64 x 8 (4 x 2) and 64 x 4 (4 x 1) columns

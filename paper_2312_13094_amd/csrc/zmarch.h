@@ -13,9 +13,9 @@
 
 namespace fd {
 
-template <int R, int BY, int RY>
+template <int R, int BY, int RY, int CX = 1>
 struct ZTile {
-    static constexpr int TX = 64, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
+    static constexpr int TX = 64 * CX, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
     static constexpr int LDS = 2 * LY * LX;   // floats, double buffered
 };
 
@@ -185,13 +185,15 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
 // front loads of that plane and parked in a register ring of R + 1 planes
 // until it is written to LDS; the streamed fields (u-, v^2 dt^2, u+) carry
 // the non-temporal hint when NTS is set so they do not evict u from L2.
-template <int R, int BY, int RY, bool NTS>
+// With CX = 2 every lane owns two columns 64 apart (a 128-wide tile), which
+// halves the share of x-halo cache lines per tile row.
+template <int R, int BY, int RY, bool NTS, int CX = 1>
 __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, const float *um,
                                                  float *up, const float *__restrict__ vdt2,
                                                  const StepParams &p, const int tx, const int ty,
                                                  const int zc, const int nzb, float *lds)
 {
-    constexpr int TX = 64, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
+    constexpr int TX = 64 * CX, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
     constexpr int NT = 64 * BY;
     constexpr int NHY = 2 * R * TX;
     constexpr int NHX = 2 * R * TY;
@@ -201,7 +203,6 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
     const int lane = threadIdx.x, wy = threadIdx.y;
     const int tid = wy * 64 + lane;
     const int x0 = tx * TX, y0 = ty * TY;
-    const int x = x0 + lane;
     const int yb = y0 + wy * RY;
     const int z0 = zc * nzb;
     const int z1 = min(z0 + nzb, p.nz);
@@ -211,12 +212,16 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
     const float *vo = vdt2 + p.offset;
     float *upo = up + p.offset;
 
-    const bool xl = x < p.nx + R;
-    bool rl[RY], ro[RY];
+    int xs[CX];
+    bool rl[CX][RY], ro[CX][RY];
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        rl[j] = xl && (yb + j) < p.ny + R;
-        ro[j] = x < p.nx && (yb + j) < p.ny;
+    for (int c = 0; c < CX; ++c) {
+        xs[c] = x0 + lane + 64 * c;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            rl[c][j] = xs[c] < p.nx + R && (yb + j) < p.ny + R;
+            ro[c][j] = xs[c] < p.nx && (yb + j) < p.ny;
+        }
     }
     int64_t hyo[HY], hxo[HX];
     int hys[HY], hxs[HX];
@@ -244,14 +249,16 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
         hxs[k] = (row + R) * LX + lx;
     }
 
-    float q[RY][2 * R + 1];
+    float q[CX][RY][2 * R + 1];
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int64_t col = (int64_t)(yb + j) * PY + x;
+    for (int c = 0; c < CX; ++c)
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k)
-            q[j][k + 1] = rl[j] ? uo[(int64_t)(z0 - R + k) * PZ + col] : 0.0f;
-    }
+        for (int j = 0; j < RY; ++j) {
+            const int64_t col = (int64_t)(yb + j) * PY + xs[c];
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k)
+                q[c][j][k + 1] = rl[c][j] ? uo[(int64_t)(z0 - R + k) * PZ + col] : 0.0f;
+        }
     // halo ring: slot d holds the halo of plane z with (z - z0) % NR == d
     float hy[NR][HY], hx[NR][HX];
     auto load_halo = [&](const int z, const int d) {
@@ -264,43 +271,53 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
 #pragma unroll
     for (int d = 0; d < NR; ++d)
         if (z0 + d < z1) load_halo(z0 + d, d);
-    float nf[RY], nm[RY], nv[RY];
+    float nf[CX][RY], nm[CX][RY], nv[CX][RY];
     auto prefetch = [&](const int z) {
         const int64_t pz = (int64_t)z * PZ;
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            const int64_t col = (int64_t)(yb + j) * PY + x;
-            nf[j] = rl[j] ? uo[pz + R * PZ + col] : 0.0f;
-            if (NTS) {
-                nm[j] = ro[j] ? __builtin_nontemporal_load(umo + pz + col) : 0.0f;
-                nv[j] = ro[j] ? __builtin_nontemporal_load(vo + pz + col) : 0.0f;
-            } else {
-                nm[j] = ro[j] ? umo[pz + col] : 0.0f;
-                nv[j] = ro[j] ? vo[pz + col] : 0.0f;
+        for (int c = 0; c < CX; ++c)
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                const int64_t col = (int64_t)(yb + j) * PY + xs[c];
+                nf[c][j] = rl[c][j] ? uo[pz + R * PZ + col] : 0.0f;
+                if (NTS) {
+                    nm[c][j] = ro[c][j] ? __builtin_nontemporal_load(umo + pz + col) : 0.0f;
+                    nv[c][j] = ro[c][j] ? __builtin_nontemporal_load(vo + pz + col) : 0.0f;
+                } else {
+                    nm[c][j] = ro[c][j] ? umo[pz + col] : 0.0f;
+                    nv[c][j] = ro[c][j] ? vo[pz + col] : 0.0f;
+                }
             }
-        }
     };
     if (z0 < z1) prefetch(z0);
 
-    const float ax = p.nbl > 0 ? sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+    float ax[CX];
+#pragma unroll
+    for (int c = 0; c < CX; ++c)
+        ax[c] = p.nbl > 0 ? sponge1(xs[c], p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
     for (int zb = z0; zb < z1; zb += NR) {
 #pragma unroll
         for (int d = 0; d < NR; ++d) {
             const int z = zb + d;
             if (z < z1) {
-                float cm[RY], cv[RY];
+                float cm[CX][RY], cv[CX][RY];
 #pragma unroll
-                for (int j = 0; j < RY; ++j) {
+                for (int c = 0; c < CX; ++c)
 #pragma unroll
-                    for (int k = 0; k < 2 * R; ++k) q[j][k] = q[j][k + 1];
-                    q[j][2 * R] = nf[j];
-                    cm[j] = nm[j];
-                    cv[j] = nv[j];
-                }
+                    for (int j = 0; j < RY; ++j) {
+#pragma unroll
+                        for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + 1];
+                        q[c][j][2 * R] = nf[c][j];
+                        cm[c][j] = nm[c][j];
+                        cv[c][j] = nv[c][j];
+                    }
                 if (z + 1 < z1) prefetch(z + 1);
                 float *t = lds + (z & 1) * (LY * LX);
 #pragma unroll
-                for (int j = 0; j < RY; ++j) t[(wy * RY + j + R) * LX + lane + R] = q[j][R];
+                for (int c = 0; c < CX; ++c)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j)
+                        t[(wy * RY + j + R) * LX + lane + 64 * c + R] = q[c][j][R];
 #pragma unroll
                 for (int k = 0; k < HY; ++k)
                     if (tid + k * NT < NHY) t[hys[k]] = hy[d][k];
@@ -314,27 +331,31 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
 
                 const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
 #pragma unroll
-                for (int j = 0; j < RY; ++j) {
-                    const float *c = t + (wy * RY + j + R) * LX + lane + R;
-                    float lz = 0.0f, ly = 0.0f, lx = 0.0f;
+                for (int c = 0; c < CX; ++c)
 #pragma unroll
-                    for (int k = 1; k <= R; ++k) {
-                        lz += p.cz[k] * (q[j][R + k] + q[j][R - k]);
-                        ly += p.cy[k] * (c[k * LX] + c[-k * LX]);
-                        lx += p.cx[k] * (c[k] + c[-k]);
+                    for (int j = 0; j < RY; ++j) {
+                        const float *cc = t + (wy * RY + j + R) * LX + lane + 64 * c + R;
+                        float lz = 0.0f, ly = 0.0f, lx = 0.0f;
+#pragma unroll
+                        for (int k = 1; k <= R; ++k) {
+                            lz += p.cz[k] * (q[c][j][R + k] + q[c][j][R - k]);
+                            ly += p.cy[k] * (cc[k * LX] + cc[-k * LX]);
+                            lx += p.cx[k] * (cc[k] + cc[-k]);
+                        }
+                        const float uc = q[c][j][R];
+                        const float lap = p.c0 * uc + lz + ly + lx;
+                        const int y = yb + j;
+                        const float ay =
+                            p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
+                        const float a = p.half_dt * ((az + ax[c]) + ay);
+                        const float val =
+                            uc + ((1.0f - a) * (uc - cm[c][j]) + cv[c][j] * lap) / (1.0f + a);
+                        if (ro[c][j]) {
+                            float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + xs[c];
+                            if (NTS) __builtin_nontemporal_store(val, dst);
+                            else *dst = val;
+                        }
                     }
-                    const float uc = q[j][R];
-                    const float lap = p.c0 * uc + lz + ly + lx;
-                    const int y = yb + j;
-                    const float ay = p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
-                    const float a = p.half_dt * ((az + ax) + ay);
-                    const float val = uc + ((1.0f - a) * (uc - cm[j]) + cv[j] * lap) / (1.0f + a);
-                    if (ro[j]) {
-                        float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + x;
-                        if (NTS) __builtin_nontemporal_store(val, dst);
-                        else *dst = val;
-                    }
-                }
             }
         }
     }

@@ -73,7 +73,7 @@ def test_loopback_exchange_equals_pack_then_unpack(shape, so):
     FD = _fd()
     rng = np.random.default_rng(5)
     h = (10.0,) * len(shape)
-    dt = synth.stable_dt(so, len(shape), 10.0, 3000.0)
+    dt = 1e-4                     # far inside the stability limit of every order
     g = FD.Grid(shape, h, so, dt, 3000.0, boundary=FD.FD_BC_LOOPBACK)
     g.set_model(to_dev(np.full(shape, 2000.0, np.float32)))
     og = O.Grid(shape, h, so=so, dt=dt)
@@ -155,7 +155,8 @@ def test_tiles_are_bit_identical():
     for tile in [(4, 4, 64, 1), (4, 1, 5, 0), (4, 2, 13, 1), (4, 8, 45, 1), (8, 2, 9, 1),
                  (8, 4, 64, 0), (2, 8, 3, 1), (4, 4, 64, 2), (4, 4, 7, 3), (4, 2, 13, 6),
                  (8, 2, 9, 7), (4, 1, 5, 4), (4, 4, 64, 8), (8, 4, 11, 12), (4, 2, 3, 13),
-                 (2, 8, 64, 9), (8, 2, 64, 12), (8, 4, 128, 12)]:
+                 (2, 8, 64, 9), (8, 2, 64, 12), (8, 4, 128, 12), (8, 2, 64, 28),
+                 (4, 4, 7, 20), (4, 4, 11, 16), (4, 2, 13, 29)]:
         u, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, 5, nbl=7, u0=u0, tile=tile)
         if base is None:
             base = u
