@@ -120,9 +120,11 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 8
  * tile with nzb planes per block).  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
- * arithmetic per point).  A 3-D grid starts with flags 12 and the first of
- * (by, ry) = (8, 2), (4, 2), (4, 1) whose launch reaches 1024 blocks with
- * nzb = 64, 32, 16 or 8 (else (4, 1, 8)): (8, 2, 64, 12) at 512^3. */
+ * arithmetic per point).  A 3-D grid starts with (8, 2, nzb, 28), nzb the
+ * largest of 128, 64, 32 giving 512 blocks ((8, 2, 128, 28) at 512^3);
+ * failing that, flags 12 and the first of (by, ry) = (8, 2), (4, 2), (4, 1)
+ * whose launch reaches 1024 blocks with nzb = 64, 32, 16 or 8 (else
+ * (4, 1, 8, 12)). */
 int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int flags);
 
 /* Autotuner: pick the 3-D step kernel's tile for this handle by timed

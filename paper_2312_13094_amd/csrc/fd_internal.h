@@ -86,13 +86,19 @@ struct Tuning {
 };
 constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8, kTileWide = 16;
 
-// Default 3-D tile: halo ring and non-temporal hints; the first of
-// 64 x 16 (8 waves of 2 rows), 64 x 8 (4 x 2) and 64 x 4 (4 x 1) columns
-// whose launch reaches 1024 blocks with z chunks of 64 planes halved down to
-// 8 (the smallest tile with 8-plane chunks otherwise), so that small grids
-// still fill 256 CUs.
+// Default 3-D tile, with the halo ring and non-temporal hints.  Large grids
+// take 128 x 16 tiles (8 waves of 2 rows, two columns per lane) with the
+// deepest z chunk (128 down to 32 planes) that still gives 512 blocks;
+// otherwise the first of 64 x 16 (8 x 2), 64 x 8 (4 x 2) and 64 x 4 (4 x 1)
+// columns whose launch reaches 1024 blocks with chunks of 64 planes halved
+// down to 8 (the smallest tile with 8-plane chunks if none does), so that
+// small grids still fill 256 CUs.
 inline Tuning default_tuning(const int n[3])
 {
+    const int64_t wide = (int64_t)((n[2] + 127) / 128) * ((n[1] + 15) / 16);
+    for (int nzb = 128; nzb >= 32; nzb /= 2)
+        if (wide * ((n[0] + nzb - 1) / nzb) >= 512)
+            return Tuning{8, 2, nzb, kTileRing | kTileNts | kTileWide};
     const int shapes[3][2] = {{8, 2}, {4, 2}, {4, 1}};
     for (const auto &sh : shapes) {
         const int64_t tiles = (int64_t)((n[2] + 63) / 64) * ((n[1] + sh[0] * sh[1] - 1) / (sh[0] * sh[1]));

@@ -403,3 +403,70 @@ def test_receiver_outside_grid_is_rejected():
     with pytest.raises(FD.FdError) as e:
         g.sparse(np.array([[10.0, 10.0, 150.5]]))
     assert e.value.code == FD.FD_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,so,tile", [((4, 5, 7), 8, None), ((6, 9, 70), 12, (8, 2, 1, 12)),
+                                           ((4, 4), 8, None), ((4, 7, 130), 8, (4, 4, 3, 28))])
+def test_grid_as_thin_as_the_stencil(shape, so, tile):
+    """Axes as short as the stencil radius (the smallest the library
+    accepts): neighbour reads reach across the whole axis into the zero
+    halo, and sources/receivers on the first and last nodes (the clamped
+    cell of the interpolation) behave as in the oracle."""
+    rng = np.random.default_rng(21)
+    h = (10.0,) * len(shape)
+    vmax = 3000.0
+    dt = synth.stable_dt(so, len(shape), 10.0, vmax)
+    v = rng.uniform(1500.0, vmax, shape).astype(np.float32)
+    last = [(s - 1) * 10.0 for s in shape]
+    src = np.array([[0.0] * len(shape), last])
+    rec = np.array([last, [0.0] * len(shape), [0.5 * x for x in last]])
+    nt = 6
+    q = (rng.standard_normal((nt, 2)) * 1e3).astype(np.float32)
+    u0 = rng.standard_normal(shape).astype(np.float32)
+    args = dict(shape=shape, spacing=h, so=so, dt=dt, vmax=vmax, v=v, nt=nt, src=src, q=q,
+                rec=rec, u0=u0)
+    gu, gum, gd = run_gpu_forward(tile=tile, **args)
+    ou, oum, od = run_oracle_forward(**args)
+    assert rel_l2(gu, ou) <= 1e-5
+    assert rel_l2(gum, oum) <= 1e-5
+    assert rel_l2(gd, od) <= 1e-5
+
+
+def test_axis_shorter_than_the_stencil_radius_is_rejected():
+    FD = _fd()
+    with pytest.raises(FD.FdError):
+        FD.Grid((3, 5, 7), (10.0,) * 3, 8, 1e-4, 3000.0)
+
+
+def test_zero_steps_and_empty_sparse_sets():
+    """nt = 0 leaves both states untouched; empty source and receiver sets
+    are accepted and change nothing."""
+    import torch
+    FD = _fd()
+    shape, so = (10, 12, 40), 8
+    dt = synth.stable_dt(so, 3, 10.0, 3000.0)
+    g = FD.Grid(shape, (10.0,) * 3, so, dt, 3000.0, nbl=3)
+    g.set_model(to_dev(np.full(shape, 2000.0, np.float32)))
+    rng = np.random.default_rng(22)
+    a, b = g.field(), g.field()
+    a.copy_(torch.from_numpy(rng.standard_normal(g.field_elems).astype(np.float32)))
+    b.copy_(torch.from_numpy(rng.standard_normal(g.field_elems).astype(np.float32)))
+    a0, b0 = a.clone(), b.clone()
+    S = g.sparse(np.zeros((0, 3)))
+    R = g.sparse(np.zeros((0, 3)))
+    g.forward([a, b], S, torch.zeros((0, 0), device="cuda"), R,
+              torch.zeros((0, 0), device="cuda"), 0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a0) and torch.equal(b, b0)
+    # one update with empty sets equals one update without any
+    c, e = a0.clone(), b0.clone()
+    g.forward([a, b], S, torch.zeros((1, 0), device="cuda"), R,
+              torch.zeros((1, 0), device="cuda"), 1)
+    g.forward([c, e], nt=1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c) and torch.equal(b, e)
+    g.close()
