@@ -227,9 +227,14 @@ def bench_learned(args):
         plain, t_plain = lc.coarse_solve()
         eager = lc.learned_solve()
         res = lc.learned_solve(graph=True)      # captured on the first model, replayed after
+        # equal-error baselines: plain higher-order runs on the same coarse grid
+        vel = c.velocity(seed)
+        p8, t8 = lc.plain_coarse_solve(8, vel)
+        p12, t12 = lc.plain_coarse_solve(12, vel)
         rows.append((LC.trace_error(plain, ref), LC.trace_error(res.traces, ref), t_fine,
-                     res.seconds, t_plain, eager.seconds, res.fallback))
-    r = np.array([x[:6] for x in rows])
+                     res.seconds, t_plain, eager.seconds, LC.trace_error(p8, ref), t8,
+                     LC.trace_error(p12, ref), t12, res.fallback))
+    r = np.array([x[:10] for x in rows])
     return {"metric": "learned vs plain time at same err (wall ms, held-out mean)",
             "value": round(float(r[:, 3].mean() * 1e3), 3), "unit": "ms",
             "n_gpus": 1, "steps": len(rows), "warmup": 0,
@@ -243,7 +248,11 @@ def bench_learned(args):
                        "one_step_loss_vs_uncorrected": [round(after, 5), round(base, 5)],
                        "trace_err_learned": [round(float(x), 4) for x in r[:, 1]],
                        "trace_err_plain_coarse": [round(float(x), 4) for x in r[:, 0]],
-                       "fallbacks": int(sum(x[6] for x in rows)),
+                       "plain_coarse_so8": {"ms": round(float(r[:, 7].mean() * 1e3), 3),
+                                            "trace_err": [round(float(x), 4) for x in r[:, 6]]},
+                       "plain_coarse_so12": {"ms": round(float(r[:, 9].mean() * 1e3), 3),
+                                             "trace_err": [round(float(x), 4) for x in r[:, 8]]},
+                       "fallbacks": int(sum(x[10] for x in rows)),
                        "tiles": {k: list(v[0]) for k, v in lc.tiles.items()},
                        "train_models": args.train_models, "train_iters": args.train_iters,
                        "samples": len(train), "data_s": round(t_data, 1),

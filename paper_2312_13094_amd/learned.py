@@ -146,6 +146,33 @@ class LearnedCorrector:
         torch.cuda.synchronize()
         return d.double().cpu().numpy(), time.perf_counter() - t0
 
+    def plain_coarse_solve(self, so, vel_fine):
+        """Equal-error baseline: a plain run on the coarse grid and time step
+        with space order `so` (its own handle, tile picked by the autotuner).
+        Returns (traces [nt_coarse][nr], seconds)."""
+        c = self.cfg
+        if not hasattr(self, "_plain"):
+            self._plain = {}
+        if so not in self._plain:
+            g = FD.Grid((c.n_coarse,) * 3, (c.h_coarse,) * 3, so, c.dt_coarse, c.vmax,
+                        nbl=c.nbl_coarse, device=self.dev.index or 0)
+            S, R = g.sparse(c.src_fine()), g.sparse(c.rec_fine())
+            self._plain[so] = (g, S, R, g.field(), g.field(), False)
+        g, S, R, a, b, tuned = self._plain[so]
+        vf = torch.from_numpy(np.ascontiguousarray(vel_fine, dtype=np.float32)).to(self.dev)
+        g.set_model(vf[::2, ::2, ::2].contiguous())
+        if not tuned:
+            g.autotune()
+            self._plain[so] = (g, S, R, a, b, True)
+        a.zero_()
+        b.zero_()
+        d = torch.zeros((c.nt_coarse, R.n), dtype=torch.float32, device=self.dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.forward([a, b], S, self.qc, R, d, c.nt_coarse)
+        torch.cuda.synchronize()
+        return d.double().cpu().numpy(), time.perf_counter() - t0
+
     # -- learned run ---------------------------------------------------------
     def coarse_step(self, n, u, um_up):
         """Plain coarse update n in place: um_up (u(n-1)) becomes u~(n+1)."""
