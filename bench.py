@@ -170,6 +170,8 @@ def bench_fwi(args):
     t_setup = time.perf_counter()
     b = fd.Batch(c.spacing, c.so, c.dt, c.vmax, c.nbl, c.shapes, c.origins, c.full_shape, c.nt,
                  c.ckpt_every)
+    if args.tile:
+        b.set_tile(*[int(t) for t in args.tile.split(",")])
     for s in range(ns):
         b.set_geometry(s, c.src[s], c.rec[s])
     vstart = torch.from_numpy(c.start_velocity()).cuda()
@@ -196,7 +198,7 @@ def bench_fwi(args):
             "config": {"workload": c.name, "shots": ns, "aperture_sides": [s[0] for s in c.shapes],
                        "time_steps": c.nt, "ckpt_every": c.ckpt_every,
                        "device_gib": round(b.device_bytes / 2 ** 30, 1),
-                       "setup_s": round(setup, 2),
+                       "setup_s": round(setup, 2), "tile": args.tile or "default",
                        "gradient_sum_over_anomaly": anomaly}}
 
 

@@ -72,8 +72,9 @@ int fd_batch_set_model(fd_batch *b, const float *vel_full_dev, void *stream);
 int fd_batch_gradient(fd_batch *b, const float *const *q_dev, const float *const *dobs_dev,
                       float *const *d_dev, float *grad_v_dev, void *stream);
 
-/* Apply a tile and flags (see fd_set_tile) to the batched step kernel;
- * invalidates the captured graph. */
+/* Apply a tile and flags (see fd_set_tile, 128-wide tiles included) to the
+ * batched step kernel; invalidates the captured graph.  The default is
+ * (8, 2, 64) with flags 28 (128-wide, halo ring, non-temporal hints). */
 int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int flags);
 
 #ifdef __cplusplus

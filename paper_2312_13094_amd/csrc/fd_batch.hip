@@ -32,7 +32,7 @@ struct fd_batch {
     int64_t full[3] = {0, 0, 0};
     std::vector<ShotHost> sh;
     fd::BatchShot *table = nullptr;
-    fd::Tuning tune{8, 2, 64, fd::kTileRing | fd::kTileNts};
+    fd::Tuning tune{8, 2, 64, fd::kTileRing | fd::kTileNts | fd::kTileWide};
     int total_blocks = 0;
     const float *vel_full = nullptr;
     unsigned *scratch = nullptr;
@@ -60,9 +60,10 @@ void drop_graph(fd_batch *b)
 void layout_blocks(fd_batch *b)
 {
     const int ty = b->tune.by * b->tune.ry;
+    const int tx = (b->tune.flags & fd::kTileWide) ? 128 : 64;
     int acc = 0;
     for (ShotHost &s : b->sh) {
-        s.ntx = (s.n[2] + 63) / 64;
+        s.ntx = (s.n[2] + tx - 1) / tx;
         s.nty = (s.n[1] + ty - 1) / ty;
         s.nzc = (s.n[0] + b->tune.nzb - 1) / b->tune.nzb;
         s.block0 = acc;
@@ -269,11 +270,12 @@ int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int xcd)
     if (!b) return set_error(FD_EINVAL, "fd_batch_set_tile: null handle");
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
                        (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
-    if (!known || nzb < 1 || xcd < 0 || xcd > 15)
+    const bool wide_ok = (by == 8 && ry == 2) || (by == 4 && (ry == 2 || ry == 4));
+    if (!known || nzb < 1 || xcd < 0 || xcd > 31 || ((xcd & kTileWide) && !wide_ok))
         return set_error(FD_EINVAL, "unsupported tile shape");
     DeviceGuard dg(b->d.device);
     drop_graph(b);
-    b->tune = Tuning{by, ry, nzb, xcd & 15};
+    b->tune = Tuning{by, ry, nzb, xcd};
     layout_blocks(b);
     return FD_OK;
 }

@@ -93,14 +93,14 @@ int launch_zmarch_radius(const fd_grid *g, const float *u, const float *um, floa
     return FD_OK;
 }
 
-template <int R, int BY, int RY, int PF, bool NTS, bool RING>
+template <int R, int BY, int RY, int PF, bool NTS, bool RING, int CX = 1>
 __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__restrict__ shots,
                                                           const int nshots, const int total,
                                                           const int iu, const int ium,
                                                           const int iup, const int nzb,
                                                           const int remap)
 {
-    __shared__ float lds[ZTile<R, BY, RY>::LDS];
+    __shared__ float lds[ZTile<R, BY, RY, CX>::LDS];
     int b = blockIdx.x;
     if (remap) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
     if (b >= total) return;
@@ -116,48 +116,59 @@ __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__res
     float *base = S.base;
     const int64_t st = S.stride;
     if (RING)
-        zmarch_ring_body<R, BY, RY, NTS>(base + iu * st, base + ium * st, base + iup * st,
-                                         base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
+        zmarch_ring_body<R, BY, RY, NTS, CX>(base + iu * st, base + ium * st, base + iup * st,
+                                             base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
     else
         zmarch_body<R, BY, RY, PF, NTS>(base + iu * st, base + ium * st, base + iup * st,
                                         base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
 }
 
-template <int R, int BY, int RY, int PF, bool NTS, bool RING>
+template <int R, int BY, int RY, int PF, bool NTS, bool RING, int CX = 1>
 static void batch_step_v(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
                          int ium, int iup, hipStream_t s)
 {
     const int remap = (t.flags & kTileXcd) ? 1 : 0;
     const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
-    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, PF, NTS, RING>), dim3(nb), dim3(64, BY), 0, s, shots,
-                       nshots, total, iu, ium, iup, t.nzb, remap);
+    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, PF, NTS, RING, CX>), dim3(nb), dim3(64, BY), 0, s,
+                       shots, nshots, total, iu, ium, iup, t.nzb, remap);
 }
 
 template <int R, int BY, int RY>
-static void batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
+static bool batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
                        int ium, int iup, hipStream_t s)
 {
     const bool pf2 = t.flags & kTilePf2, nts = t.flags & kTileNts, ring = t.flags & kTileRing;
+    if (t.flags & kTileWide) {
+        // 128-wide tiles (fd_batch_set_tile admits only these shapes)
+        if constexpr ((BY == 8 && RY == 2) || (BY == 4 && (RY == 2 || RY == 4))) {
+            if (nts) batch_step_v<R, BY, RY, 1, true, true, 2>(shots, nshots, total, t, iu, ium, iup, s);
+            else batch_step_v<R, BY, RY, 1, false, true, 2>(shots, nshots, total, t, iu, ium, iup, s);
+            return true;
+        }
+        return false;
+    }
     if (ring && nts) batch_step_v<R, BY, RY, 1, true, true>(shots, nshots, total, t, iu, ium, iup, s);
     else if (ring) batch_step_v<R, BY, RY, 1, false, true>(shots, nshots, total, t, iu, ium, iup, s);
     else if (pf2 && nts) batch_step_v<R, BY, RY, 2, true, false>(shots, nshots, total, t, iu, ium, iup, s);
     else if (pf2) batch_step_v<R, BY, RY, 2, false, false>(shots, nshots, total, t, iu, ium, iup, s);
     else if (nts) batch_step_v<R, BY, RY, 1, true, false>(shots, nshots, total, t, iu, ium, iup, s);
     else batch_step_v<R, BY, RY, 1, false, false>(shots, nshots, total, t, iu, ium, iup, s);
+    return true;
 }
 
 template <int R>
 int launch_batch_radius(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
                         int ium, int iup, hipStream_t s)
 {
-    if (t.by == 4 && t.ry == 4) batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 2) batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 8) batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 8 && t.ry == 2) batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 8 && t.ry == 4) batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 2 && t.ry == 8) batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 1) batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, s);
-    else return set_error(FD_EINVAL, "unsupported tile shape");
+    bool ok = false;
+    if (t.by == 4 && t.ry == 4) ok = batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 2) ok = batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 8) ok = batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 8 && t.ry == 2) ok = batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 8 && t.ry == 4) ok = batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 2 && t.ry == 8) ok = batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, s);
+    else if (t.by == 4 && t.ry == 1) ok = batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, s);
+    if (!ok) return set_error(FD_EINVAL, "unsupported tile shape");
     return FD_OK;
 }
 

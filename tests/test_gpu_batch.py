@@ -73,7 +73,8 @@ def test_batch_tiles_agree():
     c = _small_problem()
     vstart = c.start_velocity()
     out = []
-    for tile in [(4, 4, 64, 1), (4, 2, 7, 0), (8, 2, 16, 1), (8, 2, 64, 12), (4, 4, 5, 8)]:
+    for tile in [(4, 4, 64, 1), (4, 2, 7, 0), (8, 2, 16, 1), (8, 2, 64, 12), (4, 4, 5, 8),
+                 (8, 2, 64, 28), (4, 2, 9, 29)]:
         b = fd.Batch(c.spacing, c.so, c.dt, c.vmax, c.nbl, c.shapes, c.origins, c.full_shape,
                      c.nt, c.ckpt_every)
         b.set_tile(*tile)
