@@ -138,3 +138,46 @@ def test_tti_zmarch_matches_point_kernels():
         got, _ = _run(shape, so, nbl, nt, fields, dt, init=init, tile=tile)
         for a, b in zip(got, ref):
             assert rel_l2(a, b) <= 1e-6, tile
+
+
+@pytest.mark.slow
+def test_tti_headline_size_one_step_on_sampled_points():
+    """The 384^3 so-12 workload in the launch configuration the benchmark
+    times (default tile), one step from smooth random states, checked at 48
+    sampled points outside the damping layer.  Each sample's oracle value is
+    computed on a 25^3 window around it: the rotated divergence at the centre
+    reads intermediates within 6 cells, and those read p, r within 6 more, so
+    the window's own zero boundary never reaches the centre."""
+    import torch
+    FD = _fd()
+    c = synth.cfg_tti()
+    n, so, R = c.shape[0], c.so, c.so // 2
+    g = FD.Grid(c.shape, c.spacing, so, c.dt, c.vmax, nbl=c.nbl, physics=FD.FD_TTI,
+                eps_max=c.eps_max)
+    f = {k: to_dev(v) for k, v in c.fields.items()}
+    g.set_model(f["v"], [f["eps"], f["delta"], f["theta"], f["phi"]])
+    del f
+    init = [synth.smooth_state(c.shape, s, 4.0) for s in (41, 42, 43, 44)]
+    st = [g.field() for _ in range(4)]
+    for t, a in zip(st, init):
+        g.domain(t).copy_(to_dev(a))
+    g.forward(st, nt=1)
+    torch.cuda.synchronize()
+    got_p = g.domain(st[0]).cpu().numpy()
+    got_r = g.domain(st[2]).cpu().numpy()
+    g.close()
+    rng = np.random.default_rng(7)
+    lo, hi = c.nbl + 2 * R, n - c.nbl - 2 * R
+    pts = rng.integers(lo, hi, size=(48, 3))
+    w = 2 * R
+    og = O.Grid((2 * w + 1,) * 3, c.spacing, so=so, dt=c.dt, nbl=0, vmax=c.vmax, bc=0)
+    want, have = [], []
+    for z, y, x in pts:
+        win = tuple(slice(k - w, k + w + 1) for k in (z, y, x))
+        F = {k: v[win].astype(np.float64) for k, v in c.fields.items()}
+        p0, pm, r0, rm = (og.pad(a[win].astype(np.float64)) for a in init)
+        p, _, r, _, _ = T.forward(og, F["v"], F["eps"], F["delta"], F["theta"], F["phi"], nt=1,
+                                  p0=p0, pm=pm, r0=r0, rm=rm)
+        want += [og.interior(p)[w, w, w], og.interior(r)[w, w, w]]
+        have += [got_p[z, y, x], got_r[z, y, x]]
+    assert rel_l2(np.array(have), np.array(want)) <= 1e-5
