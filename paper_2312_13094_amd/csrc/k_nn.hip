@@ -103,8 +103,6 @@ __global__ __launch_bounds__(256) void k_pack_weights(const float *__restrict__ 
 // ---------------------------------------------------------------------------
 enum Epi { EPI_GELU = 0, EPI_GELU_Z = 1, EPI_OUT = 2, EPI_DGRAD = 3 };
 
-constexpr int TXC = 16, TYC = 8, TZC = 8;                   // output tile
-constexpr int HXC = TXC + 2, HYC = TYC + 2, HZC = TZC + 2;  // halo tile
 
 struct ConvArgs {
     int nz, ny, nx;
@@ -129,17 +127,13 @@ __device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
            x < b.hi[2];
 }
 
-// Per-row epilogue of k_conv: bias, activation and stores for the 16 points
-// of row `row` of the tile (lane n holds point n; lane group g holds output
-// channels 4g..4g+3).
+// Epilogue of one MFMA row: bias, activation and stores for point (x, y, z)
+// of this lane (lane group g holds output channels 4g..4g+3).
 template <int EPI>
-__device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, const int x0,
-                                         const int y0, const int z0, const int row, const int n,
-                                         const int g)
+__device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, const int x,
+                                         const int y, const int z, const int g)
 {
     {
-        const int zl = row / TYC, yl = row % TYC;
-        const int x = x0 + n, y = y0 + yl, z = z0 + zl;
         if (x >= a.nx || y >= a.ny || z >= a.nz) return;
         const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
         if (EPI == EPI_OUT) {
@@ -184,18 +178,35 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
     }
 }
 
+// z-marching implicit-GEMM 3x3x3 convolution.  A block owns a 32 x 8 column
+// tile and marches over ZNB output planes.  Input planes (tile plus a 1-point
+// ring, channels-last BF16) live in a 4-slot LDS ring: planes z-1, z, z+1
+// feed output plane z while plane z+2 is loaded into registers under the
+// MFMAs and stored into the free slot afterwards (one barrier per plane).
+// Every input plane is fetched once per column tile instead of with a full
+// 3-D halo per block.  Per plane: 16 rows of 16 points (two per tile row),
+// each row an STEPS-deep chain of v_mfma_f32_16x16x32_bf16 with A = the
+// weights (registers, M = 16 output channels) and B = 8 consecutive K values
+// of the row's 16 points (LDS).
+constexpr int ZX = 32, ZY = 8, ZHX = ZX + 2, ZHY = ZY + 2, ZNB = 16;
+
 template <int CIN, int STEPS, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t tile[HZC * HYC * HXC * CIN];
-    const int ntx = (a.nx + TXC - 1) / TXC, nty = (a.ny + TYC - 1) / TYC;
+    constexpr int CH = CIN / 8;                 // 16-byte chunks per point
+    constexpr int PLANE = ZHY * ZHX * CIN;      // BF16 per staged plane
+    constexpr int NCH = ZHY * ZHX * CH;         // chunks per staged plane
+    constexpr int NIT = (NCH + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
+    const int ntx = (a.nx + ZX - 1) / ZX, nty = (a.ny + ZY - 1) / ZY;
     int b = blockIdx.x;
     const int tx = b % ntx;
     b /= ntx;
     const int ty = b % nty;
-    const int tz = b / nty;
-    const int x0 = tx * TXC, y0 = ty * TYC, z0 = tz * TZC;
+    const int zc = b / nty;
+    const int x0 = tx * ZX, y0 = ty * ZY, z0 = zc * ZNB, z1 = min(z0 + ZNB, a.nz);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
 
     // weights: all K steps resident in registers
     bf16x8 af[STEPS];
@@ -203,40 +214,46 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) af[s] = fr[s * 64 + lane];
 
-    // halo tile, 16-byte chunks (8 channels): every load of the tile is in
-    // flight before the first LDS store
-    constexpr int CH = CIN / 8;
-    constexpr int NCHUNK = HZC * HYC * HXC * CH;
-    constexpr int NIT = (NCHUNK + 255) / 256;
     const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
-    uint4 *dst = reinterpret_cast<uint4 *>(tile);
     uint4 stage[NIT];
+    // plane zz of the tile + ring into registers (zero outside the volume)
+    auto load_plane = [&](const int zz) {
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int c = tid + it * 256;
-        const int pt = c / CH, ch = c % CH;
-        const int hx = pt % HXC, hy = (pt / HXC) % HYC, hz = pt / (HXC * HYC);
-        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-        stage[it] = make_uint4(0u, 0u, 0u, 0u);
-        if (c < NCHUNK && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
-            stage[it] = src[(((int64_t)gz * a.ny + gy) * a.nx + gx) * CH + ch];
-    }
-    // with two 16-byte chunks per point, the chunks of points whose index has
-    // bit 2 set are stored swapped: the 8 lanes served together by a 128-bit
-    // LDS read (8 consecutive points, 32 bytes apart) then hit distinct banks
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * 256;
+            const int pt = c / CH, ch = c % CH;
+            const int gx = x0 - 1 + pt % ZHX, gy = y0 - 1 + pt / ZHX;
+            stage[it] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < NCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny)
+                stage[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * CH + ch];
+        }
+    };
+    // with two chunks per point, the chunks of points whose index has bit 2
+    // set are stored swapped, so the 8 lanes served together by a 128-bit
+    // LDS read (8 consecutive points, 32 bytes apart) hit distinct banks
+    auto store_plane = [&](const int zz) {
+        uint4 *dst = reinterpret_cast<uint4 *>(ring + (zz & 3) * PLANE);
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int c = tid + it * 256;
-        if (c < NCHUNK) dst[CH == 2 ? (c ^ ((c >> 3) & 1)) : c] = stage[it];
-    }
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * 256;
+            if (c < NCH) dst[CH == 2 ? (c ^ ((c >> 3) & 1)) : c] = stage[it];
+        }
+    };
+
+    load_plane(z0 - 1);
+    store_plane(z0 - 1);
+    load_plane(z0);
+    store_plane(z0);
+    load_plane(z0 + 1);
+    store_plane(z0 + 1);
     __syncthreads();
 
-    const int n = lane & 15, g = lane >> 4;
-    // 64 rows of 16 points; wave w takes rows w + 4 i, four rows at a time
-    // with independent accumulators so consecutive MFMAs do not wait on
-    // each other
-    constexpr int NR = 4;
-    for (int r0 = wave; r0 < TZC * TYC; r0 += 4 * NR) {
+    constexpr int NR = 2;                       // rows per wave and pass, two passes per plane
+    for (int z = z0; z < z1; ++z) {
+        const bool more = z + 1 < z1;
+        if (more) load_plane(z + 2);            // in flight under the MFMAs
+#pragma unroll 1
+        for (int rp = 0; rp < 2; ++rp) {
         floatx4 acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -246,15 +263,15 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
             const int kb = 32 * s + 8 * g;
             int tap = kb / CIN;
             const int c0 = kb % CIN;
-            tap = tap > 26 ? 26 : tap;              // padding steps: zero weights
+            tap = tap > 26 ? 26 : tap;          // padding steps: zero weights
             const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+            const uint16_t *pl = ring + ((z + dz - 1) & 3) * PLANE;
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
-                const int row = r0 + 4 * j;
-                const int zl = row / TYC, yl = row % TYC;
-                const int pt = ((zl + dz) * HYC + (yl + dy)) * HXC + (n + dx);
+                const int row = wave + 4 * (2 * rp + j);   // tile row row/2, half row%2
+                const int pt = (row / 2 + dy) * ZHX + (row % 2) * 16 + n + dx;
                 const int cs = CIN == 16 ? (c0 ^ (((pt >> 2) & 1) << 3)) : c0;
-                bv[j] = *reinterpret_cast<const bf16x8 *>(tile + pt * CIN + cs);
+                bv[j] = *reinterpret_cast<const bf16x8 *>(pl + pt * CIN + cs);
             }
         };
         bf16x8 bq[2][NR];
@@ -268,15 +285,20 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                                                                   0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-            epilogue<EPI>(a, acc[j], x0, y0, z0, r0 + 4 * j, n, g);
+        for (int j = 0; j < NR; ++j) {
+            const int row = wave + 4 * (2 * rp + j);
+            epilogue<EPI>(a, acc[j], x0 + (row % 2) * 16 + n, y0 + row / 2, z, g);
+        }
+        }
+        if (more) store_plane(z + 2);           // slot of plane z-2, read by nobody now
+        __syncthreads();
     }
 }
 
 template <int CIN, int STEPS, int EPI>
 static int conv(const ConvArgs &a, hipStream_t s)
 {
-    const int nb = ((a.nx + TXC - 1) / TXC) * ((a.ny + TYC - 1) / TYC) * ((a.nz + TZC - 1) / TZC);
+    const int nb = ((a.nx + ZX - 1) / ZX) * ((a.ny + ZY - 1) / ZY) * ((a.nz + ZNB - 1) / ZNB);
     hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI>), dim3(nb), dim3(256), 0, s, a);
     return check_launch("nn conv");
 }
