@@ -35,21 +35,46 @@ constexpr int kF1 = 0, kF2 = 7, kF3 = 21, kD3 = 35, kD2 = 42, kSteps = 56;
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    // round to nearest even; NaN stays a (quiet) NaN.  Branch-free: the
+    // epilogues convert many values per lane.
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t q = (u >> 16) | 0x40u;
+    return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? q : r);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// erf(a) for a >= 0 by Abramowitz & Stegun, Handbook of Mathematical
+// Functions, formula 7.1.26 (absolute error <= 1.5e-7): with t = 1/(1 + p a),
+// erf(a) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-a^2).  The
+// caller passes e = exp(-a^2), which GELU's derivative reuses.  About a
+// dozen VALU operations instead of a general-purpose erf, which dominated
+// the convolution epilogues.
+__device__ __forceinline__ float erf_as(float a, float e)
+{
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    return 1.0f - q * t * e;
+}
+
+// GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2
 __device__ __forceinline__ float gelu(float x)
 {
-    return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+    const float a = fabsf(x) * 0.70710678118654752f;
+    const float e = __expf(-a * a);
+    const float r = erf_as(a, e);
+    return 0.5f * x * (1.0f + copysignf(r, x));
 }
+// GELU'(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float gelu_grad(float x)
 {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-           x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    const float a = fabsf(x) * 0.70710678118654752f;
+    const float e = __expf(-a * a);
+    const float r = erf_as(a, e);
+    return 0.5f * (1.0f + copysignf(r, x)) + x * e * 0.39894228040143268f;
 }
 
 // ---------------------------------------------------------------------------
@@ -131,14 +156,15 @@ __device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
 // of this lane (lane group g holds output channels 4g..4g+3).
 template <int EPI>
 __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, const int x,
-                                         const int y, const int z, const int g)
+                                         const int y, const int z, const int g,
+                                         const float *bias4)
 {
     {
         if (x >= a.nx || y >= a.ny || z >= a.nz) return;
         const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
         if (EPI == EPI_OUT) {
             if (g == 0) {
-                const float yv = acc[0] + a.bias[0];
+                const float yv = acc[0] + bias4[0];
                 if (a.ydense) a.ydense[p] = yv;
                 if (a.out) {
                     const float s = a.gain * (a.scale ? a.scale[0] : 1.0f);
@@ -161,7 +187,7 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
                 uint16_t zo[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float zv = acc[j] + a.bias[4 * g + j];
+                    const float zv = acc[j] + bias4[j];
                     const uint16_t zb = f2bf(zv);
                     zo[j] = zb;
                     // GELU of the stored (BF16) pre-activation, so training and
@@ -214,6 +240,13 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) af[s] = fr[s * 64 + lane];
 
+    // this lane's biases (output channels 4g..4g+3; channel 0 for layer 3)
+    float bias4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (EPI == EPI_OUT) bias4[0] = a.bias[0];
+    else if (EPI != EPI_DGRAD)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bias4[j] = a.bias[4 * g + j];
+
     const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
     uint4 stage[NIT];
     // plane zz of the tile + ring into registers (zero outside the volume)
@@ -248,6 +281,18 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
     store_plane(z0 + 1);
     __syncthreads();
 
+    // per-lane tap geometry of every K step, fixed over the march: ring slot
+    // offset dz (0..2) and the point offset within a staged plane
+    int tdz[STEPS], tpo[STEPS], tc0[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+        const int kb = 32 * s + 8 * g;
+        int tap = kb / CIN;
+        tap = tap > 26 ? 26 : tap;              // padding steps: zero weights
+        tdz[s] = tap / 9;
+        tpo[s] = ((tap / 3) % 3) * ZHX + tap % 3;
+        tc0[s] = kb % CIN;
+    }
     constexpr int NR = 2;                       // rows per wave and pass, two passes per plane
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 1 < z1;
@@ -260,17 +305,12 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
         // B fragments of step s+1 are read from LDS while the MFMAs of step s
         // run (two register sets)
         auto fetch = [&](const int s, bf16x8 *bv) {
-            const int kb = 32 * s + 8 * g;
-            int tap = kb / CIN;
-            const int c0 = kb % CIN;
-            tap = tap > 26 ? 26 : tap;          // padding steps: zero weights
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-            const uint16_t *pl = ring + ((z + dz - 1) & 3) * PLANE;
+            const uint16_t *pl = ring + ((z + tdz[s] - 1) & 3) * PLANE;
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
                 const int row = wave + 4 * (2 * rp + j);   // tile row row/2, half row%2
-                const int pt = (row / 2 + dy) * ZHX + (row % 2) * 16 + n + dx;
-                const int cs = CIN == 16 ? (c0 ^ (((pt >> 2) & 1) << 3)) : c0;
+                const int pt = (row / 2) * ZHX + (row % 2) * 16 + n + tpo[s];
+                const int cs = CIN == 16 ? (tc0[s] ^ (((pt >> 2) & 1) << 3)) : tc0[s];
                 bv[j] = *reinterpret_cast<const bf16x8 *>(pl + pt * CIN + cs);
             }
         };
@@ -287,7 +327,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             const int row = wave + 4 * (2 * rp + j);
-            epilogue<EPI>(a, acc[j], x0 + (row % 2) * 16 + n, y0 + row / 2, z, g);
+            epilogue<EPI>(a, acc[j], x0 + (row % 2) * 16 + n, y0 + row / 2, z, g, bias4);
         }
         }
         if (more) store_plane(z + 2);           // slot of plane z-2, read by nobody now
