@@ -127,6 +127,26 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * (4, 1, 8, 12)). */
 int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int flags);
 
+/* Exchange mode of the halo update around each step (paper, section on
+ * computation/communication patterns: the "basic" and "full" patterns).
+ *   FD_XCHG_BASIC  the exchange finishes before the step kernel starts
+ *                  (the default).
+ *   FD_XCHG_FULL   the exchange runs on a second stream of this handle while
+ *                  the step kernel computes the CORE, the points whose
+ *                  stencil reads no HALO (every index in [r, n - r)); after
+ *                  it completes, the REMAINDER (two z slabs of whole planes,
+ *                  two y slabs, two x faces, all r deep) is computed.  The
+ *                  caller's stream waits for the exchange before any later
+ *                  work, so the call stays stream-ordered.
+ * Results are bit-identical in both modes.  Full mode needs a 3-D acoustic
+ * grid with FD_BC_LOOPBACK, every extent > 2 r, and a z-marching tile
+ * (by > 0); FD_ENOTSUP otherwise, FD_EINVAL for an unknown mode.  The first
+ * switch to full mode creates the second stream (default priority) and two
+ * events; nothing on the device is allocated.  While full mode is on,
+ * fd_set_tile rejects by = 0. */
+enum { FD_XCHG_BASIC = 0, FD_XCHG_FULL = 1 };
+int fd_set_exchange_mode(fd_grid *g, int mode);
+
 /* Autotuner: pick the 3-D step kernel's tile for this handle by timed
  * search (each candidate (by, ry, nzb, xcd) launched a few times on scratch
  * fields of this handle's shape, fastest kept), then apply it.  With
@@ -233,8 +253,9 @@ int fd_unpack_halo(const fd_grid *g, float *field_dev, unsigned face_mask,
  * next n launches of the step kernel made by fd_forward / fd_adjoint (on the
  * stream they run on); fd_profile_end synchronises those events and returns
  * the summed kernel time in milliseconds and the number of launches timed,
- * then disarms.  Creates events (host-side objects), allocates no device
- * memory. */
+ * then disarms.  In FD_XCHG_FULL mode one timed launch spans the CORE, the
+ * overlapped exchange and the REMAINDER kernels.  Creates events (host-side
+ * objects), allocates no device memory. */
 int fd_profile_begin(fd_grid *g, int max_launches);
 int fd_profile_end(fd_grid *g, double *total_ms, int *launches);
 

@@ -117,7 +117,12 @@ void make_geometry(const fd_grid_desc &d, int ndim, const int n[3], const double
     p.gx = (float)gmax(h[2]);
     p.inv_nbl = d.nbl > 0 ? 1.0f / (float)d.nbl : 0.0f;
     p.half_dt = (float)(0.5 * d.dt);
-
+    const int ext[3] = {p.nz, p.ny, p.nx};
+    for (int a = 0; a < 3; ++a) {
+        p.sl[a] = d.nbl;
+        p.sh[a] = ext[a] - 1 - d.nbl;
+    }
+    p.xlo = 0;
 }
 
 // Leapfrog stability: v dt sqrt(S sum 1/h^2) <= 2 with S the bound of the
@@ -144,6 +149,12 @@ static void free_grid(fd_grid *g)
 {
     if (!g) return;
     prof_release(g);
+    if (g->xs) {
+        (void)hipStreamSynchronize(g->xs);
+        (void)hipStreamDestroy(g->xs);
+    }
+    if (g->xfork) (void)hipEventDestroy(g->xfork);
+    if (g->xjoin) (void)hipEventDestroy(g->xjoin);
     (void)hipFree(g->vdt2);
     for (float *&p : g->tti) (void)hipFree(p);
     for (float *&p : g->facebuf) (void)hipFree(p);
@@ -170,12 +181,13 @@ static int validate_sparse(const fd_grid *g, const fd_sparse *sp, const void *va
 }
 
 // step kernel launch, bracketed by timing events while profiling is armed
-static int timed_step(fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+static int timed_step(fd_grid *g, float *u, const float *um, float *up, hipStream_t s)
 {
     const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
     if (t && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
         return set_error(FD_EDEVICE, "hipEventRecord failed");
-    int rc = launch_step(g, u, um, up, s);
+    int rc = g->xmode == FD_XCHG_FULL ? launch_step_full(g, u, um, up, s)
+                                      : launch_step(g, u, um, up, s);
     if (rc) return rc;
     if (t) {
         if (hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
@@ -199,6 +211,18 @@ static void prof_release(fd_grid *g)
 static int halo_exchange_loopback(fd_grid *g, float *field, hipStream_t s)
 {
     return launch_loopback(g, field, g->facebuf, s);
+}
+
+// One time level: the halo update of u and the step u, u- -> u+.  Basic
+// mode exchanges first, then steps; full mode overlaps the two inside
+// launch_step_full.
+static int exchange_and_step(fd_grid *g, float *u, const float *um, float *up, hipStream_t s)
+{
+    if (g->xmode != FD_XCHG_FULL && g->d.boundary == FD_BC_LOOPBACK) {
+        const int rc = halo_exchange_loopback(g, u, s);
+        if (rc) return rc;
+    }
+    return timed_step(g, u, um, up, s);
 }
 
 }  // namespace fd
@@ -328,6 +352,8 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
 {
     if (!g) return set_error(FD_EINVAL, "fd_set_tile: null handle");
     if (by == 0) {   // simple kernel
+        if (g->xmode == FD_XCHG_FULL)
+            return set_error(FD_EINVAL, "full exchange mode needs a z-marching tile");
         g->tune = Tuning{0, 0, 0, 0};
         return FD_OK;
     }
@@ -338,6 +364,36 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
     if (!known || nzb < 1 || xcd < 0 || xcd > 31 || ((xcd & kTileWide) && !wide_ok))
         return set_error(FD_EINVAL, "unsupported tile shape");
     g->tune = Tuning{by, ry, nzb, xcd};
+    return FD_OK;
+}
+
+int fd_set_exchange_mode(fd_grid *g, int mode)
+{
+    if (!g) return set_error(FD_EINVAL, "fd_set_exchange_mode: null handle");
+    if (mode != FD_XCHG_BASIC && mode != FD_XCHG_FULL)
+        return set_error(FD_EINVAL, "fd_set_exchange_mode: unknown mode");
+    if (mode == FD_XCHG_BASIC) {
+        g->xmode = mode;
+        return FD_OK;
+    }
+    if (g->ndim != 3 || g->d.physics != FD_ACOUSTIC || g->d.boundary != FD_BC_LOOPBACK)
+        return set_error(FD_ENOTSUP, "full exchange mode: 3-D acoustic loopback grids only");
+    for (int a = 0; a < 3; ++a)
+        if (g->n[a] <= 2 * g->r)
+            return set_error(FD_ENOTSUP, "full exchange mode: every extent must exceed 2 r");
+    if (g->tune.by == 0)
+        return set_error(FD_ENOTSUP, "full exchange mode needs a z-marching tile");
+    DeviceGuard dg(g->d.device);
+    if (!g->xs && hipStreamCreateWithFlags(&g->xs, hipStreamNonBlocking) != hipSuccess) {
+        g->xs = nullptr;
+        return set_error(FD_EDEVICE, "exchange stream creation failed");
+    }
+    for (hipEvent_t *e : {&g->xfork, &g->xjoin})
+        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+            *e = nullptr;
+            return set_error(FD_EDEVICE, "exchange event creation failed");
+        }
+    g->xmode = mode;
     return FD_OK;
 }
 
@@ -507,8 +563,7 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
                 (rc = launch_copy(c1, prev, g->L.field_elems, s)))
                 return rc;
         }
-        if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, cur, s))) return rc;
-        if ((rc = timed_step(g, cur, prev, prev, s))) return rc;
+        if ((rc = exchange_and_step(g, cur, prev, prev, s))) return rc;
         inj.vals = inj.n ? q_dev + (int64_t)n * inj.n : nullptr;
         smp.out = smp.n ? d_dev + (int64_t)n * smp.n : nullptr;
         if ((rc = launch_sparse(g, prev, inj, smp, s))) return rc;
@@ -536,8 +591,7 @@ int fd_step(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src, co
                    src && src->n ? q_dev : nullptr, nullptr, (float)(1.0 / cell_volume(g))};
     SparseArgs smp{rec ? rec->n : 0, rec ? rec->base_dev : nullptr, rec ? rec->frac_dev : nullptr,
                    nullptr, rec && rec->n ? d_dev : nullptr, 1.0f};
-    if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, u_dev, s))) return rc;
-    if ((rc = timed_step(g, u_dev, um_up_dev, um_up_dev, s))) return rc;
+    if ((rc = exchange_and_step(g, u_dev, um_up_dev, um_up_dev, s))) return rc;
     return launch_sparse(g, um_up_dev, inj, smp, s);
 }
 
@@ -592,16 +646,13 @@ int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const 
                 return rc;
             for (int i = 0; i < hi - lo; ++i) {
                 float *cur = slot_dev[i + 1], *prv = slot_dev[i], *out = slot_dev[i + 2];
-                if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, cur, s)))
-                    return rc;
-                if ((rc = timed_step(g, cur, prv, out, s))) return rc;
+                if ((rc = exchange_and_step(g, cur, prv, out, s))) return rc;
                 fsrc.vals = fsrc.n ? q_dev + (int64_t)(lo + i) * fsrc.n : nullptr;
                 if ((rc = launch_sparse(g, out, fsrc, none, s))) return rc;
             }
         }
         for (int n = hi - 1; n >= lo; --n) {
-            if (g->d.boundary == FD_BC_LOOPBACK && (rc = halo_exchange_loopback(g, lam, s))) return rc;
-            if ((rc = timed_step(g, lam, lamo, lamo, s))) return rc;
+            if ((rc = exchange_and_step(g, lam, lamo, lamo, s))) return rc;
             inj.vals = inj.n ? resid_dev + (int64_t)n * inj.n : nullptr;
             smp.out = smp.n ? qadj_dev + (int64_t)n * smp.n : nullptr;
             if ((rc = launch_sparse(g, lamo, inj, smp, s))) return rc;

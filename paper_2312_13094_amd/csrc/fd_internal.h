@@ -31,6 +31,14 @@ struct StepParams {
     float gz, gy, gx;             // damping gamma_max per axis (1/s)
     float inv_nbl;                // 1 / nbl
     float half_dt;                // dt / 2
+    // damping layer edges per axis (z, y, x) in the launch's own indices:
+    // index i is in the layer below sl (depth sl - i) or above sh (depth
+    // i - sh).  nbl and n - 1 - nbl for a whole grid; shifted by the origin
+    // when a launch covers a sub-box of it.
+    int sl[3], sh[3];
+    // first x column written by a launch (0 for a whole grid; a sub-box
+    // keeps its x origin on a multiple of 64 columns and masks below xlo)
+    int xlo;
 };
 
 // Damping rate along one axis at DOMAIN index i: gamma_max * xi^2 with xi the
@@ -43,13 +51,33 @@ __host__ __device__ inline float sponge1(int i, int n, int nbl, float inv_nbl, f
     return gmax * xi * xi;
 }
 
+// The same damping rate along axis ax (0 z, 1 y, 2 x) at index i of a
+// launch (whole grid or sub-box); same arithmetic as sponge1 for a whole grid.
+__device__ inline float sponge_ax(const StepParams &p, int ax, int i, float gmax)
+{
+    float xi = 0.0f;
+    if (i < p.sl[ax]) xi = (float)(p.sl[ax] - i) * p.inv_nbl;
+    else if (i > p.sh[ax]) xi = (float)(i - p.sh[ax]) * p.inv_nbl;
+    return gmax * xi * xi;
+}
+
 // a = (dt/2) * gamma(z, y, x)
 __device__ inline float damp_a(const StepParams &p, int z, int y, int x)
 {
     if (p.nbl <= 0) return 0.0f;
-    float g = sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) + sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx);
-    if (p.ny > 1) g += sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy);
+    float g = sponge_ax(p, 0, z, p.gz) + sponge_ax(p, 2, x, p.gx);
+    if (p.ny > 1) g += sponge_ax(p, 1, y, p.gy);
     return p.half_dt * g;
+}
+
+// The damped leapfrog update (appendix "Isotropic acoustic"): given u, u-,
+// v^2 dt^2, the Laplacian and a = gamma dt / 2, returns
+// u + [(1 - a)(u - u-) + v^2 dt^2 lap] / (1 + a).  Every acoustic step kernel
+// goes through this one expression, so they round identically.
+__device__ __forceinline__ float leapfrog_update(float uc, float um, float vdt2, float lap,
+                                                float a)
+{
+    return uc + ((1.0f - a) * (uc - um) + vdt2 * lap) / (1.0f + a);
 }
 
 // Node (z, y, x) and multilinear weight of corner c of a sparse point's
@@ -138,6 +166,9 @@ struct fd_grid {
     bool model_loaded = false;
     std::vector<hipEvent_t> prof_ev;  // armed step-kernel timing events (pairs)
     int prof_used = 0;
+    int xmode = 0;                    // FD_XCHG_BASIC / FD_XCHG_FULL
+    hipStream_t xs = nullptr;         // exchange stream of full mode
+    hipEvent_t xfork = nullptr, xjoin = nullptr;
 };
 
 namespace fd {
@@ -175,10 +206,13 @@ int check_launch(const char *what);
 int launch_step(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s);
 int launch_step_simple(const fd_grid *g, const float *u, const float *um, float *up,
                        hipStream_t s);
+// step of full exchange mode: loopback exchange of u on g->xs overlapped
+// with the CORE on s, then the REMAINDER on s (k_acoustic.hip)
+int launch_step_full(fd_grid *g, float *u, const float *um, float *up, hipStream_t s);
 // z-marching step for stencil radius R (k_step_radius.hip, one object per R)
 template <int R>
-int launch_zmarch_radius(const fd_grid *g, const float *u, const float *um, float *up,
-                         hipStream_t s);
+int launch_zmarch_radius(const fd_grid *g, const StepParams &p, const Tuning &t, const float *u,
+                         const float *um, float *up, hipStream_t s);
 int launch_sparse(const fd_grid *g, float *u, const SparseArgs &inj, const SparseArgs &smp,
                   hipStream_t s);
 int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *const *buf,

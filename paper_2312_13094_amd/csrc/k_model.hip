@@ -63,8 +63,8 @@ __global__ __launch_bounds__(256) void k_imaging(const float *__restrict__ lam,
         const int64_t j = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y + x;
         float gam = 0.0f;
         if (p.nbl > 0) {
-            gam = sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) + sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx);
-            if (p.ny > 1) gam += sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy);
+            gam = sponge_ax(p, 0, z, p.gz) + sponge_ax(p, 2, x, p.gx);
+            if (p.ny > 1) gam += sponge_ax(p, 1, y, p.gy);
         }
         const float a = up[j], b = u0[j], c = um[j];
         const float dE = ((a - b) - (b - c)) * inv_dt2 + gam * (a - c) * inv_2dt;

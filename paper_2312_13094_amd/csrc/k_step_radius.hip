@@ -36,14 +36,14 @@ __global__ __launch_bounds__(64 * BY) void k_acoustic_zmarch(
 }
 
 template <int R, int BY, int RY, int PF, bool NTS, bool RING, int CX = 1>
-static void zmarch_v(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+static void zmarch_v(const fd_grid *g, const StepParams &p, const Tuning &t, const float *u,
+                     const float *um, float *up, hipStream_t s)
 {
-    const StepParams &p = g->sp;
     constexpr int TX = 64 * CX, TY = BY * RY;
-    const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
+    const int nzb = t.nzb > 0 ? t.nzb : 64;
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY, nzc = (p.nz + nzb - 1) / nzb;
     const unsigned nb = (unsigned)ntx * nty * nzc;
-    const int remap = ((g->tune.flags & kTileXcd) && nb % 8 == 0) ? 1 : 0;
+    const int remap = ((t.flags & kTileXcd) && nb % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS, RING, CX>), dim3(nb), dim3(64, BY), 0,
                        s, u, um, up, g->vdt2, p, ntx, nty, nzb, remap);
 }
@@ -51,44 +51,46 @@ static void zmarch_v(const fd_grid *g, const float *u, const float *um, float *u
 // 128-wide tiles (two columns per lane): ring body, tiles (8,2) (4,2) (4,4)
 // only ((8,4) would spill registers)
 template <int R, int BY, int RY>
-static bool zmarch_wide(const fd_grid *g, const float *u, const float *um, float *up,
-                        hipStream_t s)
+static bool zmarch_wide(const fd_grid *g, const StepParams &p, const Tuning &t, const float *u,
+                        const float *um, float *up, hipStream_t s)
 {
     if constexpr ((BY == 8 && RY == 2) || (BY == 4 && (RY == 2 || RY == 4))) {
-        if (g->tune.flags & kTileNts) zmarch_v<R, BY, RY, 1, true, true, 2>(g, u, um, up, s);
-        else zmarch_v<R, BY, RY, 1, false, true, 2>(g, u, um, up, s);
+        if (t.flags & kTileNts) zmarch_v<R, BY, RY, 1, true, true, 2>(g, p, t, u, um, up, s);
+        else zmarch_v<R, BY, RY, 1, false, true, 2>(g, p, t, u, um, up, s);
         return true;
     }
     return false;
 }
 
 template <int R, int BY, int RY>
-static bool zmarch(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+static bool zmarch(const fd_grid *g, const StepParams &p, const Tuning &t, const float *u,
+                   const float *um, float *up, hipStream_t s)
 {
-    const int f = g->tune.flags;
+    const int f = t.flags;
     const bool pf2 = f & kTilePf2, nts = f & kTileNts, ring = f & kTileRing;
-    if (f & kTileWide) return zmarch_wide<R, BY, RY>(g, u, um, up, s);
-    if (ring && nts) zmarch_v<R, BY, RY, 1, true, true>(g, u, um, up, s);
-    else if (ring) zmarch_v<R, BY, RY, 1, false, true>(g, u, um, up, s);
-    else if (pf2 && nts) zmarch_v<R, BY, RY, 2, true, false>(g, u, um, up, s);
-    else if (pf2) zmarch_v<R, BY, RY, 2, false, false>(g, u, um, up, s);
-    else if (nts) zmarch_v<R, BY, RY, 1, true, false>(g, u, um, up, s);
-    else zmarch_v<R, BY, RY, 1, false, false>(g, u, um, up, s);
+    if (f & kTileWide) return zmarch_wide<R, BY, RY>(g, p, t, u, um, up, s);
+    if (ring && nts) zmarch_v<R, BY, RY, 1, true, true>(g, p, t, u, um, up, s);
+    else if (ring) zmarch_v<R, BY, RY, 1, false, true>(g, p, t, u, um, up, s);
+    else if (pf2 && nts) zmarch_v<R, BY, RY, 2, true, false>(g, p, t, u, um, up, s);
+    else if (pf2) zmarch_v<R, BY, RY, 2, false, false>(g, p, t, u, um, up, s);
+    else if (nts) zmarch_v<R, BY, RY, 1, true, false>(g, p, t, u, um, up, s);
+    else zmarch_v<R, BY, RY, 1, false, false>(g, p, t, u, um, up, s);
     return true;
 }
 
 template <int R>
-int launch_zmarch_radius(const fd_grid *g, const float *u, const float *um, float *up, hipStream_t s)
+int launch_zmarch_radius(const fd_grid *g, const StepParams &p, const Tuning &t, const float *u,
+                         const float *um, float *up, hipStream_t s)
 {
-    const int by = g->tune.by, ry = g->tune.ry;
+    const int by = t.by, ry = t.ry;
     bool ok = false;
-    if (by == 4 && ry == 4) ok = zmarch<R, 4, 4>(g, u, um, up, s);
-    else if (by == 4 && ry == 2) ok = zmarch<R, 4, 2>(g, u, um, up, s);
-    else if (by == 4 && ry == 8) ok = zmarch<R, 4, 8>(g, u, um, up, s);
-    else if (by == 8 && ry == 2) ok = zmarch<R, 8, 2>(g, u, um, up, s);
-    else if (by == 8 && ry == 4) ok = zmarch<R, 8, 4>(g, u, um, up, s);
-    else if (by == 2 && ry == 8) ok = zmarch<R, 2, 8>(g, u, um, up, s);
-    else if (by == 4 && ry == 1) ok = zmarch<R, 4, 1>(g, u, um, up, s);
+    if (by == 4 && ry == 4) ok = zmarch<R, 4, 4>(g, p, t, u, um, up, s);
+    else if (by == 4 && ry == 2) ok = zmarch<R, 4, 2>(g, p, t, u, um, up, s);
+    else if (by == 4 && ry == 8) ok = zmarch<R, 4, 8>(g, p, t, u, um, up, s);
+    else if (by == 8 && ry == 2) ok = zmarch<R, 8, 2>(g, p, t, u, um, up, s);
+    else if (by == 8 && ry == 4) ok = zmarch<R, 8, 4>(g, p, t, u, um, up, s);
+    else if (by == 2 && ry == 8) ok = zmarch<R, 2, 8>(g, p, t, u, um, up, s);
+    else if (by == 4 && ry == 1) ok = zmarch<R, 4, 1>(g, p, t, u, um, up, s);
     if (!ok) return set_error(FD_EINVAL, "unsupported tile shape");
     return FD_OK;
 }
@@ -172,8 +174,8 @@ int launch_batch_radius(const BatchShot *shots, int nshots, int total, const Tun
     return FD_OK;
 }
 
-template int launch_zmarch_radius<FD_RADIUS>(const fd_grid *, const float *, const float *,
-                                             float *, hipStream_t);
+template int launch_zmarch_radius<FD_RADIUS>(const fd_grid *, const StepParams &, const Tuning &,
+                                             const float *, const float *, float *, hipStream_t);
 template int launch_batch_radius<FD_RADIUS>(const BatchShot *, int, int, const Tuning &, int, int,
                                             int, hipStream_t);
 

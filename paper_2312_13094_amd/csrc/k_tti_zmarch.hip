@@ -310,7 +310,7 @@ __global__ __launch_bounds__(64 * kTtiBy) void k_tti_div_zm(
     };
     if (z0 < z1) prefetch(z0);
 
-    const float ax = sp.nbl > 0 ? sponge1(x, sp.nx, sp.nbl, sp.inv_nbl, sp.gx) : 0.0f;
+    const float ax = sp.nbl > 0 ? sponge_ax(sp, 2, x, sp.gx) : 0.0f;
     for (int z = z0; z < z1; ++z) {
         float pc[RY], pmv[RY], rc[RY], rmv[RY], cc[RY], cp[RY], cxx[RY];
         float *t1w = lw1[z & 1], *t1s = ls1[z & 1], *t2w = lw2[z & 1], *t2s = ls2[z & 1];
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64 * kTtiBy) void k_tti_div_zm(
         if (z + 1 < z1) prefetch(z + 1);
         __syncthreads();
 
-        const float az = sp.nbl > 0 ? sponge1(z, sp.nz, sp.nbl, sp.inv_nbl, sp.gz) : 0.0f;
+        const float az = sp.nbl > 0 ? sponge_ax(sp, 0, z, sp.gz) : 0.0f;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int ly = wy * RY + j;
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(64 * kTtiBy) void k_tti_div_zm(
             }
             const int y = yb + j;
             // same summation order as damp_a(): (z + x) + y
-            const float ayy = sp.nbl > 0 ? sponge1(y, sp.ny, sp.nbl, sp.inv_nbl, sp.gy) : 0.0f;
+            const float ayy = sp.nbl > 0 ? sponge_ax(sp, 1, y, sp.gy) : 0.0f;
             const float a = sp.half_dt * ((az + ax) + ayy);
             const float inv = 1.0f / (1.0f + a);
             const float pn = pc[j] + ((1.0f - a) * (pc[j] - pmv[j]) + cp[j] * h1 + cxx[j] * h2) * inv;

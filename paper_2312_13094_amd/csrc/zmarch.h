@@ -19,8 +19,9 @@ struct ZTile {
     static constexpr int LDS = 2 * LY * LX;   // floats, double buffered
 };
 
-// One block's z-march over tile (tx, ty) and z chunk zc of a grid described
-// by p; u -> up with up possibly aliasing um (in place).  `lds` holds
+// One block's z-march over tile (tx, ty) and z chunk zc of the box that p
+// describes (a whole DOMAIN, or a sub-box whose x columns below p.xlo are
+// read but not written); u -> up with up possibly aliasing um (in place).  `lds` holds
 // ZTile<R,BY,RY>::LDS floats.  PF planes of loads are kept in flight ahead of
 // the plane being computed; NTS stores u+ with the non-temporal hint (it is
 // not read again in this step).
@@ -49,14 +50,15 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
     const float *vo = vdt2 + p.offset;
     float *upo = up + p.offset;
 
-    // which of this thread's rows are loadable (inside DOMAIN + halo) and
-    // which are written (inside DOMAIN)
-    const bool xl = x < p.nx + R;
+    // which of this thread's rows are loadable (inside the launch box plus
+    // its R-wide rim) and which are written (inside the box, x >= p.xlo)
+    const bool xl = x >= p.xlo - R && x < p.nx + R;
+    const bool xw = x >= p.xlo && x < p.nx;
     bool rl[RY], ro[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         rl[j] = xl && (yb + j) < p.ny + R;
-        ro[j] = x < p.nx && (yb + j) < p.ny;
+        ro[j] = xw && (yb + j) < p.ny;
     }
 
     // halo descriptors, fixed over z: element offset within a plane, LDS slot
@@ -70,7 +72,7 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
         const int yy = row < R ? y0 - R + row : y0 + TY + (row - R);
         const int ly = row < R ? row : TY + row;
         const int xx = x0 + col;
-        hyk[k] = e < NHY && yy < p.ny + R && xx < p.nx + R;
+        hyk[k] = e < NHY && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
         hyo[k] = (int64_t)yy * PY + xx;
         hys[k] = ly * LX + col + R;
     }
@@ -81,7 +83,7 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
         const int yy = y0 + row;
         const int xx = c < R ? x0 - R + c : x0 + TX + (c - R);
         const int lx = c < R ? c : TX + c;
-        hxk[k] = e < NHX && yy < p.ny + R && xx < p.nx + R;
+        hxk[k] = e < NHX && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
         hxo[k] = (int64_t)yy * PY + xx;
         hxs[k] = (row + R) * LX + lx;
     }
@@ -116,7 +118,7 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
     for (int d = 0; d < PF; ++d)
         if (z0 + d < z1) prefetch(z0 + d, d);
 
-    const float ax = p.nbl > 0 ? sponge1(x, p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+    const float ax = p.nbl > 0 ? sponge_ax(p, 2, x, p.gx) : 0.0f;
     for (int zb = z0; zb < z1; zb += PF) {
 #pragma unroll
         for (int d = 0; d < PF; ++d) {
@@ -148,7 +150,7 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
                     if (tid + k * NT < NHX) t[hxs[k]] = chx[k];
                 __syncthreads();
 
-                const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
+                const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
 #pragma unroll
                 for (int j = 0; j < RY; ++j) {
                     const float *c = t + (wy * RY + j + R) * LX + lane + R;
@@ -163,9 +165,9 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
                     const float lap = p.c0 * uc + lz + ly + lx;
                     const int y = yb + j;
                     // same summation order as damp_a(): (z + x) + y
-                    const float ay = p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
+                    const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
                     const float a = p.half_dt * ((az + ax) + ay);
-                    const float val = uc + ((1.0f - a) * (uc - cm[j]) + cv[j] * lap) / (1.0f + a);
+                    const float val = leapfrog_update(uc, cm[j], cv[j], lap, a);
                     if (ro[j]) {
                         float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + x;
                         if (NTS) __builtin_nontemporal_store(val, dst);
@@ -219,8 +221,8 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
         xs[c] = x0 + lane + 64 * c;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            rl[c][j] = xs[c] < p.nx + R && (yb + j) < p.ny + R;
-            ro[c][j] = xs[c] < p.nx && (yb + j) < p.ny;
+            rl[c][j] = xs[c] >= p.xlo - R && xs[c] < p.nx + R && (yb + j) < p.ny + R;
+            ro[c][j] = xs[c] >= p.xlo && xs[c] < p.nx && (yb + j) < p.ny;
         }
     }
     int64_t hyo[HY], hxo[HX];
@@ -233,7 +235,7 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
         const int yy = row < R ? y0 - R + row : y0 + TY + (row - R);
         const int ly = row < R ? row : TY + row;
         const int xx = x0 + col;
-        hyk[k] = e < NHY && yy < p.ny + R && xx < p.nx + R;
+        hyk[k] = e < NHY && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
         hyo[k] = (int64_t)yy * PY + xx;
         hys[k] = ly * LX + col + R;
     }
@@ -244,7 +246,7 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
         const int yy = y0 + row;
         const int xx = c < R ? x0 - R + c : x0 + TX + (c - R);
         const int lx = c < R ? c : TX + c;
-        hxk[k] = e < NHX && yy < p.ny + R && xx < p.nx + R;
+        hxk[k] = e < NHX && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
         hxo[k] = (int64_t)yy * PY + xx;
         hxs[k] = (row + R) * LX + lx;
     }
@@ -294,7 +296,7 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
     float ax[CX];
 #pragma unroll
     for (int c = 0; c < CX; ++c)
-        ax[c] = p.nbl > 0 ? sponge1(xs[c], p.nx, p.nbl, p.inv_nbl, p.gx) : 0.0f;
+        ax[c] = p.nbl > 0 ? sponge_ax(p, 2, xs[c], p.gx) : 0.0f;
     for (int zb = z0; zb < z1; zb += NR) {
 #pragma unroll
         for (int d = 0; d < NR; ++d) {
@@ -329,7 +331,7 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
                 if (z + NR < z1) load_halo(z + NR, d);
                 __syncthreads();
 
-                const float az = p.nbl > 0 ? sponge1(z, p.nz, p.nbl, p.inv_nbl, p.gz) : 0.0f;
+                const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
 #pragma unroll
                 for (int c = 0; c < CX; ++c)
 #pragma unroll
@@ -346,10 +348,9 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
                         const float lap = p.c0 * uc + lz + ly + lx;
                         const int y = yb + j;
                         const float ay =
-                            p.nbl > 0 ? sponge1(y, p.ny, p.nbl, p.inv_nbl, p.gy) : 0.0f;
+                            p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
                         const float a = p.half_dt * ((az + ax[c]) + ay);
-                        const float val =
-                            uc + ((1.0f - a) * (uc - cm[c][j]) + cv[c][j] * lap) / (1.0f + a);
+                        const float val = leapfrog_update(uc, cm[c][j], cv[c][j], lap, a);
                         if (ro[c][j]) {
                             float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + xs[c];
                             if (NTS) __builtin_nontemporal_store(val, dst);

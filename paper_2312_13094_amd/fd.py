@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfd.so")
 FD_OK, FD_EINVAL, FD_ENOMEM, FD_EDEVICE, FD_EUNSTABLE, FD_ENOTSUP = 0, -1, -2, -3, -4, -5
 FD_ACOUSTIC, FD_TTI = 0, 1
 FD_BC_ZERO, FD_BC_LOOPBACK, FD_BC_EXTERNAL = 0, 1, 2
+FD_XCHG_BASIC, FD_XCHG_FULL = 0, 1
 ALL_FACES = 0x3F
 
 
@@ -64,6 +65,7 @@ def lib():
     L.fd_destroy_grid.restype = None
     L.fd_field_layout.argtypes = [vp, P(Layout)]
     L.fd_set_tile.argtypes = [vp, i, i, i, i]
+    L.fd_set_exchange_mode.argtypes = [vp, i]
     L.fd_sparse_prepare.argtypes = [vp, P(ctypes.c_double), i, P(ctypes.c_int32),
                                     P(ctypes.c_float)]
     L.fd_set_model.argtypes = [vp, vp, P(vp), vp]
@@ -201,6 +203,11 @@ class Grid:
     # -- API -----------------------------------------------------------------
     def set_tile(self, by, ry=1, nzb=64, xcd=1):
         _check(lib().fd_set_tile(self.handle, by, ry, nzb, xcd))
+
+    def set_exchange_mode(self, mode):
+        """FD_XCHG_BASIC (exchange, then step) or FD_XCHG_FULL (exchange on a
+        second stream overlapped with the CORE, then the REMAINDER)."""
+        _check(lib().fd_set_exchange_mode(self.handle, mode))
 
     def autotune(self, cache_path=None):
         """Timed tile search (or cache lookup); returns ((by, ry, nzb, xcd), ms)."""
