@@ -219,6 +219,75 @@ def cfg_tti(n: int = 384, nt: int = 500, seed: int = 3, so: int = 12, nbl: int =
                src, rec, q, fields=f)
 
 
+# Sums sum_k |c_k| of the staggered first-derivative weights of each space
+# order; the velocity-stress leapfrog is stable for
+# vp dt sqrt(sum 1/h^2) sum_k |c_k| <= 1.  Used only to choose a time step.
+_STAG = {2: 1.0, 4: 7.0 / 6.0, 8: 1.286309523809524, 12: 1.3390636273448773,
+         16: 1.3703812355179543}
+
+
+def elastic_stable_dt(so: int, h: float, vmax: float, frac: float = 0.5) -> float:
+    return frac * h / (vmax * math.sqrt(3.0) * _STAG[so])
+
+
+@dataclass
+class Elastic:
+    """Isotropic elastic workload: P and S velocities and density per node,
+    an explosive source and receivers (they record the trace of the stress)."""
+    name: str
+    shape: tuple
+    spacing: tuple
+    so: int
+    nbl: int
+    dt: float
+    nt: int
+    vmax: float
+    boundary: int
+    src: np.ndarray
+    rec: np.ndarray
+    q: np.ndarray
+    vp_profile: np.ndarray              # [nz]: the model is flat in x, y
+    vs_profile: np.ndarray
+    rho_profile: np.ndarray
+
+    @property
+    def points(self):
+        return int(np.prod(self.shape))
+
+    def fields(self):
+        """DOMAIN-shaped float32 (vp, vs, rho)."""
+        out = []
+        for p in (self.vp_profile, self.vs_profile, self.rho_profile):
+            out.append(np.ascontiguousarray(
+                np.broadcast_to(p.reshape(-1, 1, 1), self.shape)).astype(np.float32))
+        return tuple(out)
+
+
+def cfg_elastic(n: int = 512, nt: int = 300, seed: int = 4, so: int = 8, nbl: int = 40,
+                boundary: int = 1) -> Elastic:
+    """3-D layered isotropic elastic on an n^3 DOMAIN (benchmark: 512^3, so 8,
+    300 steps): vp from the seeded layered profile (1.5-4.5 km/s), vs = vp /
+    sqrt(3) (a Poisson solid), rho = 310 vp^0.25 kg/m^3 (Gardner's relation);
+    40-point sponge, 15 Hz Ricker explosive source near the top, a line of
+    receivers, h = 10 m, dt at 0.5 CFL, loopback halos for all nine
+    components."""
+    h = 10.0
+    vp = layered_profile(n, seed).astype(np.float64)
+    vs = vp / math.sqrt(3.0)
+    rho = 310.0 * vp ** 0.25
+    vmax = 4500.0
+    dt = elastic_stable_dt(so, h, vmax)
+    s = n / 512.0
+    c = (n / 2 - 0.5) * h
+    src = np.array([[(50.5 * s) * h, c, c]])
+    rz = round(45 * s)
+    rec = np.array([[rz * h, c, (i * (n - 1) / max(n - 1, 1)) * h] for i in range(n)])
+    q = ricker(nt, dt, 15.0)[:, None]
+    return Elastic("elastic3d_%dcube_so%d_layered" % (n, so), (n, n, n), (h, h, h), so, nbl, dt,
+                   nt, vmax, boundary, src, rec, q, vp.astype(np.float32),
+                   vs.astype(np.float32), rho.astype(np.float32))
+
+
 @dataclass
 class FWIBatch:
     """Batched-gradient workload: a full model (layered + Gaussian anomaly),
