@@ -145,6 +145,100 @@ def bench_tti(args):
                          "algorithmic_bytes_per_launch": alg}}
 
 
+def elastic_cpu_baseline(c, budget_s):
+    """The FP64 elastic oracle (numpy) on a 128^3 box of the same layered
+    medium: per-step cost from 1- and 3-step runs, then as many steps as fit
+    in about `budget_s` seconds."""
+    import numpy as np
+
+    import oracle as O
+    import oracle.elastic as E
+    m = 128
+    shape = (m, m, m)
+    og = O.Grid(shape, c.spacing, so=c.so, dt=c.dt, nbl=c.nbl, vmax=c.vmax, bc=c.boundary)
+    med = [np.broadcast_to(p[:m].astype(np.float64)[:, None, None], shape)
+           for p in (c.vp_profile, c.vs_profile, c.rho_profile)]
+    src = np.array([[min(c.src[0, 0], (m - 1) * c.spacing[0]), (m / 2 - 0.5) * c.spacing[1],
+                     (m / 2 - 0.5) * c.spacing[2]]])
+    q = c.q.astype(np.float64)
+
+    def run(nt):
+        t0 = time.perf_counter()
+        E.forward(og, *med, src=src, q=q[:nt], nt=nt)
+        return time.perf_counter() - t0
+
+    t1, t3 = run(1), run(3)
+    per = max((t3 - t1) / 2.0, t3 / 6.0, 1e-3)
+    nt = int(max(1, min(c.nt, round(budget_s / per))))
+    total = run(nt)
+    # per-step time net of the fixed set-up (medium, sponge) of one call
+    net = max(total - (t1 - per), per)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(m ** 3 * nt / net / 1e9, 4), "unit": "Gpts/s", "cores": threads,
+            "nproc": os.cpu_count(), "kind": "oracle",
+            "sample": "128^3 box (top of the same layered medium), %d of %d time steps, FP64 "
+                      "numpy oracle (%.1f s, set-up excluded)" % (nt, c.nt, net)}
+
+
+def bench_elastic(args):
+    """Isotropic elastic velocity-stress, 512^3, so 8, 363 steps (Gpts/s;
+    one update is the velocity pass and the stress pass)."""
+    import torch
+
+    from paper_2312_13094_amd import fd, synth
+    c = synth.cfg_elastic(n=args.n)
+    g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, boundary=c.boundary,
+                physics=fd.FD_ELASTIC)
+    if args.tile:
+        g.set_tile(*[int(t) for t in args.tile.split(",")])
+    n = c.shape[0]
+    prof = [torch.from_numpy(p).cuda()[:, None, None].expand(n, n, n).contiguous()
+            for p in (c.vp_profile, c.vs_profile, c.rho_profile)]
+    g.set_model(prof[0], prof[1:])
+    del prof
+    st = [g.field() for _ in range(9)]
+    S, R = g.sparse(c.src), g.sparse(c.rec)
+    q = torch.from_numpy(c.q).cuda()
+    d = torch.zeros((c.nt, R.n), device="cuda")
+    for _ in range(args.warmup):
+        g.forward(st, S, q, R, d, c.nt)
+    torch.cuda.synchronize()
+    g.profile_begin(2 * args.steps * c.nt)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.forward(st, S, q, R, d, c.nt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, nl = g.profile_end()
+    if not torch.isfinite(d).all():
+        print("non-finite traces", file=sys.stderr)
+        sys.exit(1)
+    g.close()
+    del st
+    torch.cuda.empty_cache()
+    gpts = c.points * c.nt * args.steps / wall / 1e9
+    per_update = kms / max(nl // 2, 1)
+    alg = 140 * c.points
+    out = {"metric": "Gpts/s, 3D so-8 isotropic elastic", "value": round(gpts, 3),
+           "unit": "Gpts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": c.name + "_%dsteps_loopback_halo" % c.nt,
+                      "shape": list(c.shape), "space_order": c.so, "time_steps": c.nt,
+                      "sponge": c.nbl, "components": 9, "tile": args.tile or "default"},
+           "roofline": {"bound": "hbm", "achieved": round(alg / (per_update * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / (per_update * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": None,
+                        "kernel": "elastic velocity pass + stress pass (one update; 60 + 80 B/pt)",
+                        "avg_update_ms": round(per_update, 5), "launches_timed": nl,
+                        "algorithmic_bytes_per_update": alg},
+           "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = elastic_cpu_baseline(c, args.cpu_budget)
+    return out
+
+
 def bench_fwi(args):
     """Batched FWI gradient: 16 shots, apertures 192^3..320^3 inside a 512^3
     layered + anomaly model, so 8, 800 steps, checkpoint every 50, one graph."""
@@ -278,7 +372,7 @@ def main():
                     help="(default; kept for older command lines) time a plain 2 GiB copy first")
     ap.add_argument("--no-copy", action="store_true", help="skip the 2 GiB copy calibration")
     ap.add_argument("--workload", default="acoustic",
-                    choices=["acoustic", "tti", "fwi", "learned"],
+                    choices=["acoustic", "tti", "fwi", "learned", "elastic"],
                     help="acoustic = the headline line; the others print their own line")
     ap.add_argument("--train-models", type=int, default=64)
     ap.add_argument("--train-iters", type=int, default=3000)
@@ -291,7 +385,8 @@ def main():
         sys.exit(2)
 
     if args.workload != "acoustic":
-        fn = {"tti": bench_tti, "fwi": bench_fwi, "learned": bench_learned}[args.workload]
+        fn = {"tti": bench_tti, "fwi": bench_fwi, "learned": bench_learned,
+              "elastic": bench_elastic}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 

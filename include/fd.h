@@ -45,7 +45,19 @@ enum {
     FD_ENOTSUP = -5     /* valid request this build does not implement */
 };
 
-enum { FD_ACOUSTIC = 0, FD_TTI = 1 };
+/* Physics of a handle:
+ *   FD_ACOUSTIC  equation (acou), second order in time, state {u, u-};
+ *   FD_TTI       the pseudo-acoustic TTI system (appendix "Anisotropic
+ *                acoustic (TTI)"), state {p, p-, r, r-};
+ *   FD_ELASTIC   the isotropic elastic velocity-stress system (appendix
+ *                "Isotropic elastic", equation (elas1)), first order in
+ *                time on a staggered grid, state of nine components
+ *                {vx, vy, vz, txx, tyy, tzz, txy, txz, tyz} updated in place.
+ *                Storage index (z, y, x) holds vx at x+1/2, vy at y+1/2,
+ *                vz at z+1/2, the normal stresses at the node, txy at
+ *                (y+1/2, x+1/2), txz at (z+1/2, x+1/2), tyz at (z+1/2, y+1/2).
+ *                3-D only; FD_BC_ZERO or FD_BC_LOOPBACK. */
+enum { FD_ACOUSTIC = 0, FD_TTI = 1, FD_ELASTIC = 2 };
 
 /* How the halo of the propagated field is refreshed before every step:
  *   FD_BC_ZERO      never written: stays as the caller allocated it (zero);
@@ -64,11 +76,12 @@ typedef struct {
     double spacing[3];      /* metres, same order as shape */
     int space_order;        /* even, 2..16 (TTI: 4..12) */
     int nbl;                /* damping-layer width in points, inside DOMAIN; 0 = none */
-    int physics;            /* FD_ACOUSTIC or FD_TTI */
+    int physics;            /* FD_ACOUSTIC, FD_TTI or FD_ELASTIC */
     int boundary;           /* FD_BC_* */
     double dt;              /* seconds */
-    double vmax;            /* upper bound of the velocity model (m/s); sets the
-                               damping strength and the stability check */
+    double vmax;            /* upper bound of the velocity model (m/s; FD_ELASTIC:
+                               of the P velocity); sets the damping strength and
+                               the stability check */
     double eps_max;         /* TTI: upper bound of epsilon (stability check); else 0 */
     int device;             /* HIP device ordinal */
 } fd_grid_desc;
@@ -99,7 +112,9 @@ typedef struct {
 /* Validate `desc`, compute the layout and FP32 stencil weights, and allocate
  * the handle's own device memory (model coefficients and, for
  * FD_BC_LOOPBACK, six face buffers).  Returns FD_EUNSTABLE if
- * vmax*dt/h exceeds the leapfrog stability limit of the space order. */
+ * vmax*dt/h exceeds the leapfrog stability limit of the space order
+ * (FD_ELASTIC: vmax dt sqrt(sum 1/h^2) sum_k |c_k| <= 1 with c_k the
+ * staggered first-derivative weights). */
 int fd_create_grid(const fd_grid_desc *desc, fd_grid **out);
 
 void fd_destroy_grid(fd_grid *g);
@@ -170,15 +185,32 @@ int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n,
 /* Load the model.  vel_dev is DOMAIN-shaped dense (nz, ny, nx) float32 in
  * m/s.  For FD_TTI, tti_dev = {epsilon, delta, theta, phi} DOMAIN-shaped
  * (theta: tilt from vertical, phi: azimuth, radians); NULL for acoustic.
- * Builds the handle's v^2 dt^2 coefficient field on the device, then
- * synchronises `stream` to check max(vel) <= vmax (FD_EUNSTABLE otherwise). */
+ * For FD_ELASTIC, vel_dev is the P velocity and tti_dev = {vs, rho}: S
+ * velocity (m/s) and density (kg/m^3) per node.  The library then builds
+ * the medium at every component's position: buoyancy 1/rho averaged over
+ * the two nodes along a velocity's staggered axis, mu = rho vs^2 averaged
+ * over the four nodes of a shear stress's staggered plane, lambda = rho
+ * (vp^2 - 2 vs^2) and mu at the node for the normal stresses (node values
+ * beyond DOMAIN repeat the last one), each times dt.
+ * Builds the handle's coefficient fields on the device, then synchronises
+ * `stream` to check max(vel) <= vmax (FD_EUNSTABLE otherwise; FD_ELASTIC
+ * also needs rho > 0 and 0 <= vs < vp sqrt(3)/2, i.e. mu >= 0 and
+ * 3 lambda + 2 mu > 0). */
 int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream);
 
 /* Forward modelling: nt leapfrog updates of equation (acou) (or the TTI
  * system), each followed by source injection and receiver sampling.
  *   state_dev  acoustic {u^n, u^(n-1)}, TTI {p^n, p^(n-1), r^n, r^(n-1)}:
  *              padded fields, in/out; on return they hold the states nt
- *              updates later in the same order.
+ *              updates later in the same order.  FD_ELASTIC: the nine
+ *              components in place (velocities at n - 1/2, stresses at n
+ *              on entry); update k computes v^(k+1/2) from the stresses,
+ *              then tau^(k+1) from the new velocities, with the halos of
+ *              the six stresses, then of the three velocities, refreshed
+ *              first for FD_BC_LOOPBACK.  Sources are explosive: q[k] w /
+ *              h^3 times dt / (1 + gamma dt / 2) is added to txx, tyy and
+ *              tzz at each node; receivers record txx + tyy + tzz.  No
+ *              checkpoints (FD_ENOTSUP).
  *   src, q_dev ns sources and their signatures q[nt][ns]; update k uses q[k]
  *              to produce the state at k+1.  src may be NULL (no source).
  *   rec, d_dev nr receivers, traces d[nt][nr]: d[k] sampled after update k.
@@ -254,7 +286,8 @@ int fd_unpack_halo(const fd_grid *g, float *field_dev, unsigned face_mask,
  * stream they run on); fd_profile_end synchronises those events and returns
  * the summed kernel time in milliseconds and the number of launches timed,
  * then disarms.  In FD_XCHG_FULL mode one timed launch spans the CORE, the
- * overlapped exchange and the REMAINDER kernels.  Creates events (host-side
+ * overlapped exchange and the REMAINDER kernels; an FD_ELASTIC update
+ * times two launches (the velocity pass and the stress pass).  Creates events (host-side
  * objects), allocates no device memory. */
 int fd_profile_begin(fd_grid *g, int max_launches);
 int fd_profile_end(fd_grid *g, double *total_ms, int *launches);

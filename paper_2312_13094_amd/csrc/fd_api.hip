@@ -50,6 +50,24 @@ static void d1_weights(int r, double *a)
     }
 }
 
+// FP64 staggered first-derivative weights of order 2r (unit spacing; the
+// difference of values at +-(k - 1/2)): the product form
+// c_k = (-1)^(k+1) / (2k - 1) prod_{j != k} (2j-1)^2 / |(2j-1)^2 - (2k-1)^2|,
+// which makes the difference exact on polynomials of degree <= 2r.
+static void stag_weights(int r, double *c)
+{
+    for (int k = 1; k <= r; ++k) {
+        const double ok = 2.0 * k - 1.0;
+        double prod = 1.0;
+        for (int j = 1; j <= r; ++j) {
+            if (j == k) continue;
+            const double oj = 2.0 * j - 1.0;
+            prod *= oj * oj / std::fabs(oj * oj - ok * ok);
+        }
+        c[k - 1] = ((k % 2) ? 1.0 : -1.0) * prod / ok;
+    }
+}
+
 // peak of the squared first-derivative symbol (2 sum_k a_k sin k xi)^2
 static double d1_symbol_peak(int r)
 {
@@ -108,6 +126,14 @@ void make_geometry(const fd_grid_desc &d, int ndim, const int n[3], const double
         p.dy[k] = (float)(ak / h[1]);
         p.dx[k] = (float)(ak / h[2]);
     }
+    double c1[kMaxR];
+    stag_weights(r, c1);
+    for (int k = 0; k < kMaxR; ++k) {
+        const double ck = k < r ? c1[k] : 0.0;
+        p.sz[k] = (float)(ck / h[0]);
+        p.sy[k] = (float)(ck / h[1]);
+        p.sx[k] = (float)(ck / h[2]);
+    }
     p.c0 = (float)(w[0] / (h[0] * h[0]) + w[0] / (h[2] * h[2]) +
                    (ndim == 3 ? w[0] / (h[1] * h[1]) : 0.0));
     const double lnR = std::log(1.0e3);
@@ -136,6 +162,13 @@ int check_stability(const fd_grid_desc &d, int ndim, const double h[3], int r)
     double ih2 = 1.0 / (h[0] * h[0]) + 1.0 / (h[2] * h[2]);
     if (ndim == 3) ih2 += 1.0 / (h[1] * h[1]);
     if (d.physics == FD_TTI) S = d1_symbol_peak(r) * (1.0 + 2.0 * d.eps_max);
+    if (d.physics == FD_ELASTIC) {
+        // the staggered derivative's symbol peaks at 2 sum |c_k| / h
+        double c[kMaxR], sum = 0.0;
+        stag_weights(r, c);
+        for (int k = 0; k < r; ++k) sum += std::fabs(c[k]);
+        S = 4.0 * sum * sum;
+    }
     if (d.vmax * d.dt * std::sqrt(S * ih2) > 2.0 * (1.0 + 1e-12))
         return set_error(FD_EUNSTABLE, "time step exceeds the leapfrog stability limit");
     return FD_OK;
@@ -157,6 +190,7 @@ static void free_grid(fd_grid *g)
     if (g->xjoin) (void)hipEventDestroy(g->xjoin);
     (void)hipFree(g->vdt2);
     for (float *&p : g->tti) (void)hipFree(p);
+    for (float *&p : g->el) (void)hipFree(p);
     for (float *&p : g->facebuf) (void)hipFree(p);
     for (float *&p : g->inter) (void)hipFree(p);
     (void)hipFree(g->scratch_u32);
@@ -241,8 +275,13 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     if (d.ndim != 2 && d.ndim != 3) return set_error(FD_EINVAL, "ndim must be 2 or 3");
     if (d.space_order < 2 || d.space_order > 16 || d.space_order % 2)
         return set_error(FD_EINVAL, "space_order must be even, 2..16");
-    if (d.physics != FD_ACOUSTIC && d.physics != FD_TTI)
+    if (d.physics != FD_ACOUSTIC && d.physics != FD_TTI && d.physics != FD_ELASTIC)
         return set_error(FD_EINVAL, "unknown physics");
+    if (d.physics == FD_ELASTIC) {
+        if (d.ndim != 3) return set_error(FD_EINVAL, "elastic needs a 3-D grid");
+        if (d.boundary == FD_BC_EXTERNAL)
+            return set_error(FD_ENOTSUP, "elastic supports the zero and loopback halos");
+    }
     if (d.physics == FD_TTI) {
         if (d.ndim != 3 || d.space_order < 4 || d.space_order > 12)
             return set_error(FD_EINVAL, "TTI needs a 3-D grid and space order 4..12");
@@ -298,14 +337,21 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
         delete g;
         return set_error(FD_EDEVICE, "cannot select device");
     }
-    if (hipMalloc(&g->vdt2, L.field_bytes) != hipSuccess ||
-        hipMalloc(&g->scratch_u32, 256) != hipSuccess) {
+    if (hipMalloc(&g->scratch_u32, 256) != hipSuccess) {
         free_grid(g);
         return set_error(FD_ENOMEM, "device allocation failed");
     }
-    if (hipMemset(g->vdt2, 0, L.field_bytes) != hipSuccess) {
+    if (d.physics == FD_ELASTIC) {
+        for (int i = 0; i < 8; ++i)
+            if (hipMalloc(&g->el[i], L.field_bytes) != hipSuccess ||
+                hipMemset(g->el[i], 0, L.field_bytes) != hipSuccess) {
+                free_grid(g);
+                return set_error(FD_ENOMEM, "elastic medium allocation failed");
+            }
+    } else if (hipMalloc(&g->vdt2, L.field_bytes) != hipSuccess ||
+               hipMemset(g->vdt2, 0, L.field_bytes) != hipSuccess) {
         free_grid(g);
-        return set_error(FD_EDEVICE, "hipMemset failed");
+        return set_error(FD_ENOMEM, "device allocation failed");
     }
     if (d.physics == FD_TTI) {
         for (int i = 0; i < 4; ++i)
@@ -422,15 +468,18 @@ int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n, int32_t *
 int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream)
 {
     if (!g || !vel_dev) return set_error(FD_EINVAL, "fd_set_model: null argument");
-    const bool tti = g->d.physics == FD_TTI;
+    const bool tti = g->d.physics == FD_TTI, el = g->d.physics == FD_ELASTIC;
     if (tti && (!tti_dev || !tti_dev[0] || !tti_dev[1] || !tti_dev[2] || !tti_dev[3]))
         return set_error(FD_EINVAL, "fd_set_model: TTI needs epsilon, delta, theta, phi");
+    if (el && (!tti_dev || !tti_dev[0] || !tti_dev[1]))
+        return set_error(FD_EINVAL, "fd_set_model: elastic needs vs and rho");
     DeviceGuard dg(g->d.device);
     hipStream_t s = (hipStream_t)stream;
     if (hipMemsetAsync(g->scratch_u32, 0, 2 * sizeof(unsigned), s) != hipSuccess)
         return set_error(FD_EDEVICE, "hipMemsetAsync failed");
-    int rc = tti ? launch_tti_model(g, vel_dev, tti_dev, g->scratch_u32, s)
-                 : launch_build_vdt2(g, vel_dev, g->vdt2, g->scratch_u32, s);
+    int rc = tti  ? launch_tti_model(g, vel_dev, tti_dev, g->scratch_u32, s)
+             : el ? launch_el_model(g, vel_dev, tti_dev[0], tti_dev[1], g->scratch_u32, s)
+                  : launch_build_vdt2(g, vel_dev, g->vdt2, g->scratch_u32, s);
     if (rc) return rc;
     unsigned bits[2] = {0u, 0u};
     if (hipMemcpyAsync(bits, g->scratch_u32, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s) !=
@@ -447,6 +496,10 @@ int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, 
     if (tti && !(emax <= (float)g->d.eps_max * (1.0f + 1e-6f) + 1e-12f)) {
         g->model_loaded = false;
         return set_error(FD_EUNSTABLE, "epsilon exceeds eps_max, or epsilon/delta <= -1/2");
+    }
+    if (el && bits[1] != 0u) {
+        g->model_loaded = false;
+        return set_error(FD_EUNSTABLE, "elastic medium needs rho > 0 and 0 <= vs < vp sqrt(3)/2");
     }
     g->model_loaded = true;
     return FD_OK;
@@ -526,6 +579,42 @@ static int forward_tti(fd_grid *g, float *const *st, SparseArgs inj, SparseArgs 
     return FD_OK;
 }
 
+// nt updates of the elastic system: per update the velocity pass, then the
+// stress pass (halos of the stresses, then of the velocities, refreshed
+// before them for the loopback boundary), then the explosive source and
+// the stress-trace receivers.  Each pass is one timed launch.
+static int forward_elastic(fd_grid *g, float *const *f, SparseArgs inj, SparseArgs smp,
+                           const float *q_dev, float *d_dev, int nt, hipStream_t s)
+{
+    int rc;
+    const bool loop = g->d.boundary == FD_BC_LOOPBACK;
+    auto timed = [&](bool stress) -> int {
+        const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
+        if (t && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
+            return set_error(FD_EDEVICE, "hipEventRecord failed");
+        const int r = stress ? launch_el_stress(g, f, s) : launch_el_velocity(g, f, s);
+        if (r) return r;
+        if (t) {
+            if (hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
+                return set_error(FD_EDEVICE, "hipEventRecord failed");
+            ++g->prof_used;
+        }
+        return FD_OK;
+    };
+    for (int n = 0; n < nt; ++n) {
+        for (int k = 3; loop && k < 9; ++k)
+            if ((rc = launch_loopback(g, f[k], g->facebuf, s))) return rc;
+        if ((rc = timed(false))) return rc;
+        for (int k = 0; loop && k < 3; ++k)
+            if ((rc = launch_loopback(g, f[k], g->facebuf, s))) return rc;
+        if ((rc = timed(true))) return rc;
+        inj.vals = inj.n ? q_dev + (int64_t)n * inj.n : nullptr;
+        smp.out = smp.n ? d_dev + (int64_t)n * smp.n : nullptr;
+        if ((rc = launch_el_sparse(g, f, inj, smp, s))) return rc;
+    }
+    return FD_OK;
+}
+
 int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const float *q_dev,
                const fd_sparse *rec, float *d_dev, int nt, float *const *ckpt_dev,
                int ckpt_every, void *stream)
@@ -538,6 +627,13 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
          state_dev[2] == state_dev[0] || state_dev[2] == state_dev[1] ||
          state_dev[3] == state_dev[0] || state_dev[3] == state_dev[1]))
         return set_error(FD_EINVAL, "fd_forward: TTI needs four distinct state fields");
+    if (g->d.physics == FD_ELASTIC) {
+        for (int i = 0; i < 9; ++i)
+            for (int j = 0; j < i + 1; ++j)
+                if (!state_dev[i] || (j < i && state_dev[i] == state_dev[j]))
+                    return set_error(FD_EINVAL, "fd_forward: elastic needs nine distinct fields");
+        if (ckpt_dev) return set_error(FD_ENOTSUP, "fd_forward: no checkpoints for elastic");
+    }
     if (!g->model_loaded) return set_error(FD_EINVAL, "fd_forward: no model loaded");
     if (ckpt_dev && ckpt_every < 1) return set_error(FD_EINVAL, "fd_forward: ckpt_every < 1");
     int rc = validate_sparse(g, src, q_dev, "sources");
@@ -554,6 +650,10 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
                    nullptr, nullptr, 1.0f};
     if (g->d.physics == FD_TTI)
         return forward_tti(g, state_dev, inj, smp, q_dev, d_dev, nt, ckpt_dev, ckpt_every, s);
+    if (g->d.physics == FD_ELASTIC) {
+        inj.scale = (float)(g->d.dt / cell_volume(g));
+        return forward_elastic(g, state_dev, inj, smp, q_dev, d_dev, nt, s);
+    }
     float *cur = state_dev[0], *prev = state_dev[1];
     for (int n = 0; n < nt; ++n) {
         if (ckpt_dev && n % ckpt_every == 0) {
@@ -686,6 +786,8 @@ int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *gr
                             void *stream)
 {
     if (!g || !grad_m_dev || !grad_v_dev) return set_error(FD_EINVAL, "bad argument");
+    if (g->d.physics != FD_ACOUSTIC)
+        return set_error(FD_ENOTSUP, "fd_gradient_to_velocity: acoustic physics only");
     if (!g->model_loaded) return set_error(FD_EINVAL, "no model loaded");
     DeviceGuard dg(g->d.device);
     return launch_grad_to_vel(g, grad_m_dev, grad_v_dev, (hipStream_t)stream);

@@ -28,6 +28,7 @@ struct StepParams {
     float cx[kMaxR + 1];          // w_k / h_x^2
     float c0;                     // cz[0] + cy[0] + cx[0]
     float dz[kMaxR], dy[kMaxR], dx[kMaxR];  // first-derivative a_k / h per axis (TTI)
+    float sz[kMaxR], sy[kMaxR], sx[kMaxR];  // staggered first-derivative c_k / h (elastic)
     float gz, gy, gx;             // damping gamma_max per axis (1/s)
     float inv_nbl;                // 1 / nbl
     float half_dt;                // dt / 2
@@ -160,6 +161,9 @@ struct fd_grid {
     fd::Tuning tune;
     float *vdt2 = nullptr;        // padded v^2 dt^2
     float *tti[4] = {nullptr, nullptr, nullptr, nullptr};  // padded eps, delta, theta, phi
+    // elastic medium times dt at each component's position (padded):
+    // b dt at vx, vy, vz; lambda dt, mu dt at nodes; mu dt at txy, txz, tyz
+    float *el[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float *facebuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float *inter[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // TTI pass-1 output
     unsigned *scratch_u32 = nullptr;  // small device scratch (model checks)
@@ -231,6 +235,15 @@ int launch_tti_model(const fd_grid *g, const float *vel, const float *const *tti
                      hipStream_t s);
 int launch_tti_step(const fd_grid *g, const float *p, const float *pm, float *pp, const float *r,
                     const float *rm, float *rp, hipStream_t s);
+// isotropic elastic (k_elastic.hip): medium build with validity flags, the
+// velocity and stress passes in place on the nine components {vx, vy, vz,
+// txx, tyy, tzz, txy, txz, tyz}, and explosive-source / stress-trace sparse
+int launch_el_model(const fd_grid *g, const float *vp, const float *vs, const float *rho,
+                    unsigned *flags, hipStream_t s);
+int launch_el_velocity(const fd_grid *g, float *const *f, hipStream_t s);
+int launch_el_stress(const fd_grid *g, float *const *f, hipStream_t s);
+int launch_el_sparse(const fd_grid *g, float *const *f, const SparseArgs &inj,
+                     const SparseArgs &smp, hipStream_t s);
 // z-marching TTI passes (k_tti_zmarch.hip), used by launch_tti_step for 3-D
 // grids whose tile is not the one-thread-per-point kernel
 int launch_tti_step_zm(const fd_grid *g, const float *p, const float *pm, float *pp,

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfd.so")
 
 FD_OK, FD_EINVAL, FD_ENOMEM, FD_EDEVICE, FD_EUNSTABLE, FD_ENOTSUP = 0, -1, -2, -3, -4, -5
-FD_ACOUSTIC, FD_TTI = 0, 1
+FD_ACOUSTIC, FD_TTI, FD_ELASTIC = 0, 1, 2
+ELASTIC_FIELDS = ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
 FD_BC_ZERO, FD_BC_LOOPBACK, FD_BC_EXTERNAL = 0, 1, 2
 FD_XCHG_BASIC, FD_XCHG_FULL = 0, 1
 ALL_FACES = 0x3F

@@ -263,10 +263,10 @@ class Elastic:
         return tuple(out)
 
 
-def cfg_elastic(n: int = 512, nt: int = 300, seed: int = 4, so: int = 8, nbl: int = 40,
+def cfg_elastic(n: int = 512, nt: int = 363, seed: int = 4, so: int = 8, nbl: int = 40,
                 boundary: int = 1) -> Elastic:
     """3-D layered isotropic elastic on an n^3 DOMAIN (benchmark: 512^3, so 8,
-    300 steps): vp from the seeded layered profile (1.5-4.5 km/s), vs = vp /
+    363 steps, the paper's elastic step count for 512 ms): vp from the seeded layered profile (1.5-4.5 km/s), vs = vp /
     sqrt(3) (a Poisson solid), rho = 310 vp^0.25 kg/m^3 (Gardner's relation);
     40-point sponge, 15 Hz Ricker explosive source near the top, a line of
     receivers, h = 10 m, dt at 0.5 CFL, loopback halos for all nine
