@@ -133,7 +133,10 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * (by, ry) = (8,2) (4,2) (4,4)).  by = 0 selects the
  * one-thread-per-point kernel.  FD_TTI grids use only by = 0 (the
  * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 8
- * tile with nzb planes per block).  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
+ * tile with nzb planes per block).  FD_ELASTIC grids: by = 0 selects the
+ * one-thread-per-point passes, (by, ry) = (4, 2) the z-marching passes on
+ * 64 x 8 tiles with nzb planes per block (the default, with the deepest of
+ * 256 .. 8 planes giving 1024 blocks; flags are ignored).  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
  * arithmetic per point).  A 3-D grid starts with (8, 2, nzb, 28), nzb the
  * largest of 128, 64, 32 giving 512 blocks ((8, 2, 128, 28) at 512^3);

@@ -330,7 +330,9 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     make_geometry(d, g->ndim, g->n, g->h, r, g->L, g->sp);
     const fd_layout &L = g->L;
 
-    g->tune = d.ndim == 3 ? default_tuning(g->n) : Tuning{0, 0, 0, 0};
+    g->tune = d.physics == FD_ELASTIC ? el_default_tuning(g->n)
+              : d.ndim == 3            ? default_tuning(g->n)
+                                       : Tuning{0, 0, 0, 0};
 
     DeviceGuard dg(d.device);
     if (!dg.ok()) {
@@ -404,6 +406,12 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
         return FD_OK;
     }
     if (g->ndim != 3) return set_error(FD_EINVAL, "tiles apply to 3-D grids");
+    if (g->d.physics == FD_ELASTIC) {
+        if (by != 4 || ry != 2 || nzb < 1 || xcd < 0 || xcd > 31)
+            return set_error(FD_EINVAL, "elastic tiles: (by, ry) = (4, 2) or by = 0");
+        g->tune = Tuning{4, 2, nzb, 0};
+        return FD_OK;
+    }
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||
                        (by == 8 && (ry == 2 || ry == 4)) || (by == 2 && ry == 8);
     const bool wide_ok = (by == 8 && ry == 2) || (by == 4 && (ry == 2 || ry == 4));

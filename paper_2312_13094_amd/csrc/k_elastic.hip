@@ -33,7 +33,7 @@ struct ElMedium {
 };
 
 enum { VX, VY, VZ, TXX, TYY, TZZ, TXY, TXZ, TYZ };
-enum { BX, BY, BZ, LAM, MU, MXY, MXZ, MYZ };
+enum { M_BX, M_BY, M_BZ, M_LAM, M_MU, M_MXY, M_MXZ, M_MYZ };
 
 template <int R>
 __device__ __forceinline__ float dp(const float *__restrict__ f, const int64_t i, const int64_t s,
@@ -88,14 +88,14 @@ __global__ __launch_bounds__(256) void k_el_model(const float *__restrict__ vp,
         const float a = vp[i], s = vs[i], r = rho[i];
         const float m0 = r * s * s;
         const int64_t j = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y + x;
-        med.m[BX][j] = 0.5f * (b(i) + b(i + ox)) * dt;
-        med.m[BY][j] = 0.5f * (b(i) + b(i + oy)) * dt;
-        med.m[BZ][j] = 0.5f * (b(i) + b(i + oz)) * dt;
-        med.m[LAM][j] = (r * a * a - 2.0f * m0) * dt;
-        med.m[MU][j] = m0 * dt;
-        med.m[MXY][j] = 0.25f * (m0 + mu(i + ox) + mu(i + oy) + mu(i + ox + oy)) * dt;
-        med.m[MXZ][j] = 0.25f * (m0 + mu(i + ox) + mu(i + oz) + mu(i + ox + oz)) * dt;
-        med.m[MYZ][j] = 0.25f * (m0 + mu(i + oy) + mu(i + oz) + mu(i + oy + oz)) * dt;
+        med.m[M_BX][j] = 0.5f * (b(i) + b(i + ox)) * dt;
+        med.m[M_BY][j] = 0.5f * (b(i) + b(i + oy)) * dt;
+        med.m[M_BZ][j] = 0.5f * (b(i) + b(i + oz)) * dt;
+        med.m[M_LAM][j] = (r * a * a - 2.0f * m0) * dt;
+        med.m[M_MU][j] = m0 * dt;
+        med.m[M_MXY][j] = 0.25f * (m0 + mu(i + ox) + mu(i + oy) + mu(i + ox + oy)) * dt;
+        med.m[M_MXZ][j] = 0.25f * (m0 + mu(i + ox) + mu(i + oz) + mu(i + ox + oz)) * dt;
+        med.m[M_MYZ][j] = 0.25f * (m0 + mu(i + oy) + mu(i + oz) + mu(i + oy + oz)) * dt;
         // positive floats order like their bit patterns; flag <= 0 / NaN as +inf
         const unsigned bits = (a > 0.0f) ? __float_as_uint(a) : 0x7f800000u;
         mx = bits > mx ? bits : mx;
@@ -131,9 +131,9 @@ __global__ __launch_bounds__(256) void k_el_velocity_pt(ElState st, const ElMedi
                      dm<R>(st.f[TYZ], i, PZ, p.sz);
     const float rz = dm<R>(st.f[TXZ], i, 1, p.sx) + dm<R>(st.f[TYZ], i, PY, p.sy) +
                      dp<R>(st.f[TZZ], i, PZ, p.sz);
-    st.f[VX][i] = damped(st.f[VX][i], med.m[BX][i] * rx, a);
-    st.f[VY][i] = damped(st.f[VY][i], med.m[BY][i] * ry, a);
-    st.f[VZ][i] = damped(st.f[VZ][i], med.m[BZ][i] * rz, a);
+    st.f[VX][i] = damped(st.f[VX][i], med.m[M_BX][i] * rx, a);
+    st.f[VY][i] = damped(st.f[VY][i], med.m[M_BY][i] * ry, a);
+    st.f[VZ][i] = damped(st.f[VZ][i], med.m[M_BZ][i] * rz, a);
 }
 
 template <int R>
@@ -155,17 +155,423 @@ __global__ __launch_bounds__(256) void k_el_stress_pt(ElState st, const ElMedium
     const float *vx = st.f[VX], *vy = st.f[VY], *vz = st.f[VZ];
     const float exx = dm<R>(vx, i, 1, p.sx), eyy = dm<R>(vy, i, PY, p.sy),
                 ezz = dm<R>(vz, i, PZ, p.sz);
-    const float lt = med.m[LAM][i] * ((exx + eyy) + ezz);
-    const float m2 = 2.0f * med.m[MU][i];
+    const float lt = med.m[M_LAM][i] * ((exx + eyy) + ezz);
+    const float m2 = 2.0f * med.m[M_MU][i];
     st.f[TXX][i] = damped(st.f[TXX][i], lt + m2 * exx, a);
     st.f[TYY][i] = damped(st.f[TYY][i], lt + m2 * eyy, a);
     st.f[TZZ][i] = damped(st.f[TZZ][i], lt + m2 * ezz, a);
     st.f[TXY][i] = damped(st.f[TXY][i],
-                          med.m[MXY][i] * (dp<R>(vx, i, PY, p.sy) + dp<R>(vy, i, 1, p.sx)), a);
+                          med.m[M_MXY][i] * (dp<R>(vx, i, PY, p.sy) + dp<R>(vy, i, 1, p.sx)), a);
     st.f[TXZ][i] = damped(st.f[TXZ][i],
-                          med.m[MXZ][i] * (dp<R>(vx, i, PZ, p.sz) + dp<R>(vz, i, 1, p.sx)), a);
+                          med.m[M_MXZ][i] * (dp<R>(vx, i, PZ, p.sz) + dp<R>(vz, i, 1, p.sx)), a);
     st.f[TYZ][i] = damped(st.f[TYZ][i],
-                          med.m[MYZ][i] * (dp<R>(vy, i, PZ, p.sz) + dp<R>(vz, i, PY, p.sy)), a);
+                          med.m[M_MYZ][i] * (dp<R>(vy, i, PZ, p.sz) + dp<R>(vz, i, PY, p.sy)), a);
+}
+
+// ---------------------------------------------------------------------------
+// z-marching passes
+//
+// A block of 64 x BY threads owns a 64 x (BY*RY) column tile and marches
+// along a chunk of nzb planes.  Fields differentiated along z travel in
+// per-thread register queues of 2R+1 planes; fields differentiated along x
+// or y are staged plane by plane in LDS with an R-wide rim (double
+// buffered, one barrier per plane).  The next plane's loads are issued
+// before the current plane is computed.  The point's own fields (the
+// components it updates and its medium) are streamed with the non-temporal
+// hint.  Sums, damping and updates are those of the one-thread-per-point
+// kernels, term for term.
+//
+// velocity pass: queues txz, tyz, tzz; LDS txx (x rim), txy (x and y),
+//                txz (x), tyy (y), tyz (y)
+// stress pass:   queues vx, vy, vz; LDS vx, vy, vz (x and y rims)
+// ---------------------------------------------------------------------------
+
+template <int R, int BY, int RY>
+struct ElZm {
+    static constexpr int TX = 64, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R, PL = LY * LX;
+    static constexpr int NT = 64 * BY;
+    static constexpr int NHY = 2 * R * TX, NHX = 2 * R * TY;
+    static constexpr int HY = (NHY + NT - 1) / NT, HX = (NHX + NT - 1) / NT;
+};
+
+// Offsets (within a plane, from the DOMAIN origin), LDS slots and in-range
+// flags of this thread's share of a tile's y rim and x rim.
+template <int R, int BY, int RY>
+struct ElRim {
+    using T = ElZm<R, BY, RY>;
+    int64_t yo[T::HY], xo[T::HX];
+    int ys[T::HY], xs[T::HX];
+    bool yk[T::HY], xk[T::HX];
+
+    __device__ __forceinline__ ElRim(const StepParams &p, const int x0, const int y0, const int tid)
+    {
+#pragma unroll
+        for (int k = 0; k < T::HY; ++k) {
+            const int e = tid + k * T::NT;
+            const int row = e / T::TX, col = e % T::TX;
+            const int yy = row < R ? y0 - R + row : y0 + T::TY + (row - R);
+            const int ly = row < R ? row : T::TY + row;
+            const int xx = x0 + col;
+            yk[k] = e < T::NHY && yy < p.ny + R && xx < p.nx + R;
+            yo[k] = (int64_t)yy * p.pitch_y + xx;
+            ys[k] = ly * T::LX + col + R;
+        }
+#pragma unroll
+        for (int k = 0; k < T::HX; ++k) {
+            const int e = tid + k * T::NT;
+            const int row = e / (2 * R), c = e % (2 * R);
+            const int yy = y0 + row;
+            const int xx = c < R ? x0 - R + c : x0 + T::TX + (c - R);
+            const int lx = c < R ? c : T::TX + c;
+            xk[k] = e < T::NHX && yy < p.ny + R && xx < p.nx + R;
+            xo[k] = (int64_t)yy * p.pitch_y + xx;
+            xs[k] = (row + R) * T::LX + lx;
+        }
+    }
+};
+
+template <bool NT_>
+__device__ __forceinline__ float ld(const float *p)
+{
+    if constexpr (NT_) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// staggered sums over LDS (stride 1 or LX) and over a z queue (centre R)
+template <int R, int S>
+__device__ __forceinline__ float dp_l(const float *c, const float *w)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) acc += w[k - 1] * (c[k * S] - c[-(k - 1) * S]);
+    return acc;
+}
+
+template <int R, int S>
+__device__ __forceinline__ float dm_l(const float *c, const float *w)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) acc += w[k - 1] * (c[(k - 1) * S] - c[-k * S]);
+    return acc;
+}
+
+template <int R>
+__device__ __forceinline__ float dp_q(const float *q, const float *w)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) acc += w[k - 1] * (q[R + k] - q[R - (k - 1)]);
+    return acc;
+}
+
+template <int R>
+__device__ __forceinline__ float dm_q(const float *q, const float *w)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) acc += w[k - 1] * (q[R + (k - 1)] - q[R - k]);
+    return acc;
+}
+
+template <int R, int BY, int RY>
+__global__ __launch_bounds__(64 * BY) void k_el_velocity_zm(ElState st, const ElMedium med,
+                                                            const StepParams p, const int ntx,
+                                                            const int nty, const int nzb)
+{
+    using T = ElZm<R, BY, RY>;
+    constexpr int Q = 2 * R + 1;
+    __shared__ float lds[2][5][T::PL];   // txx, txy, txz, tyy, tyz
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int zc = b / nty;
+    const int lane = threadIdx.x, wy = threadIdx.y, tid = wy * 64 + lane;
+    const int x0 = tx * T::TX, y0 = ty * T::TY, x = x0 + lane, yb = y0 + wy * RY;
+    const int z0 = zc * nzb, z1 = min(z0 + nzb, p.nz);
+    const int64_t PZ = p.pitch_z, PY = p.pitch_y;
+    const float *fxx = st.f[TXX] + p.offset, *fxy = st.f[TXY] + p.offset,
+                *fxz = st.f[TXZ] + p.offset, *fyy = st.f[TYY] + p.offset,
+                *fyz = st.f[TYZ] + p.offset, *fzz = st.f[TZZ] + p.offset;
+    float *vx = st.f[VX] + p.offset, *vy = st.f[VY] + p.offset, *vz = st.f[VZ] + p.offset;
+    const float *bx = med.m[M_BX] + p.offset, *by = med.m[M_BY] + p.offset,
+                *bz = med.m[M_BZ] + p.offset;
+    bool rl[RY], ro[RY];
+    int64_t col[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        rl[j] = x < p.nx + R && yb + j < p.ny + R;
+        ro[j] = x < p.nx && yb + j < p.ny;
+        col[j] = (int64_t)(yb + j) * PY + x;
+    }
+    const ElRim<R, BY, RY> rim(p, x0, y0, tid);
+
+    float qxz[RY][Q], qyz[RY][Q], qzz[RY][Q];
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) {
+            const int64_t o = (int64_t)(z0 - R + k) * PZ + col[j];
+            qxz[j][k + 1] = rl[j] ? fxz[o] : 0.0f;
+            qyz[j][k + 1] = rl[j] ? fyz[o] : 0.0f;
+            qzz[j][k + 1] = rl[j] ? fzz[o] : 0.0f;
+        }
+    // loads of one plane: queue fronts (z + R), LDS centres, rims, own fields
+    float nfxz[RY], nfyz[RY], nfzz[RY], ncxx[RY], ncxy[RY], ncyy[RY];
+    float nv[3][RY], nb[3][RY];
+    float nyh[3][T::HY], nxh[3][T::HX];   // y rims of txy, tyy, tyz; x rims of txx, txy, txz
+    auto prefetch = [&](const int z) {
+        const int64_t pz = (int64_t)z * PZ;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int64_t o = pz + col[j];
+            nfxz[j] = rl[j] ? fxz[o + R * PZ] : 0.0f;
+            nfyz[j] = rl[j] ? fyz[o + R * PZ] : 0.0f;
+            nfzz[j] = rl[j] ? fzz[o + R * PZ] : 0.0f;
+            ncxx[j] = rl[j] ? fxx[o] : 0.0f;
+            ncxy[j] = rl[j] ? fxy[o] : 0.0f;
+            ncyy[j] = rl[j] ? fyy[o] : 0.0f;
+            nv[0][j] = ro[j] ? ld<true>(vx + o) : 0.0f;
+            nv[1][j] = ro[j] ? ld<true>(vy + o) : 0.0f;
+            nv[2][j] = ro[j] ? ld<true>(vz + o) : 0.0f;
+            nb[0][j] = ro[j] ? ld<true>(bx + o) : 0.0f;
+            nb[1][j] = ro[j] ? ld<true>(by + o) : 0.0f;
+            nb[2][j] = ro[j] ? ld<true>(bz + o) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < T::HY; ++k) {
+            nyh[0][k] = rim.yk[k] ? fxy[pz + rim.yo[k]] : 0.0f;
+            nyh[1][k] = rim.yk[k] ? fyy[pz + rim.yo[k]] : 0.0f;
+            nyh[2][k] = rim.yk[k] ? fyz[pz + rim.yo[k]] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < T::HX; ++k) {
+            nxh[0][k] = rim.xk[k] ? fxx[pz + rim.xo[k]] : 0.0f;
+            nxh[1][k] = rim.xk[k] ? fxy[pz + rim.xo[k]] : 0.0f;
+            nxh[2][k] = rim.xk[k] ? fxz[pz + rim.xo[k]] : 0.0f;
+        }
+    };
+    if (z0 < z1) prefetch(z0);
+
+    const float ax = p.nbl > 0 ? sponge_ax(p, 2, x, p.gx) : 0.0f;
+    for (int z = z0; z < z1; ++z) {
+        float cxx[RY], cxy[RY], cyy[RY], cv[3][RY], cb[3][RY], cyh[3][T::HY], cxh[3][T::HX];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) {
+                qxz[j][k] = qxz[j][k + 1];
+                qyz[j][k] = qyz[j][k + 1];
+                qzz[j][k] = qzz[j][k + 1];
+            }
+            qxz[j][2 * R] = nfxz[j];
+            qyz[j][2 * R] = nfyz[j];
+            qzz[j][2 * R] = nfzz[j];
+            cxx[j] = ncxx[j];
+            cxy[j] = ncxy[j];
+            cyy[j] = ncyy[j];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cv[c][j] = nv[c][j];
+                cb[c][j] = nb[c][j];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k) cyh[c][k] = nyh[c][k];
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k) cxh[c][k] = nxh[c][k];
+        }
+        if (z + 1 < z1) prefetch(z + 1);
+
+        float(*L)[T::PL] = lds[z & 1];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int c = (wy * RY + j + R) * T::LX + lane + R;
+            L[0][c] = cxx[j];
+            L[1][c] = cxy[j];
+            L[2][c] = qxz[j][R];
+            L[3][c] = cyy[j];
+            L[4][c] = qyz[j][R];
+        }
+#pragma unroll
+        for (int k = 0; k < T::HY; ++k)
+            if (tid + k * T::NT < T::NHY) {
+                L[1][rim.ys[k]] = cyh[0][k];
+                L[3][rim.ys[k]] = cyh[1][k];
+                L[4][rim.ys[k]] = cyh[2][k];
+            }
+#pragma unroll
+        for (int k = 0; k < T::HX; ++k)
+            if (tid + k * T::NT < T::NHX) {
+                L[0][rim.xs[k]] = cxh[0][k];
+                L[1][rim.xs[k]] = cxh[1][k];
+                L[2][rim.xs[k]] = cxh[2][k];
+            }
+        __syncthreads();
+
+        const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int c = (wy * RY + j + R) * T::LX + lane + R;
+            constexpr int LXs = T::LX;
+            const float rx = dp_l<R, 1>(&L[0][c], p.sx) + dm_l<R, LXs>(&L[1][c], p.sy) +
+                             dm_q<R>(qxz[j], p.sz);
+            const float ry = dm_l<R, 1>(&L[1][c], p.sx) + dp_l<R, LXs>(&L[3][c], p.sy) +
+                             dm_q<R>(qyz[j], p.sz);
+            const float rz = dm_l<R, 1>(&L[2][c], p.sx) + dm_l<R, LXs>(&L[4][c], p.sy) +
+                             dp_q<R>(qzz[j], p.sz);
+            const int y = yb + j;
+            const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
+            const float a = p.half_dt * ((az + ax) + ay);
+            if (ro[j]) {
+                const int64_t o = (int64_t)z * PZ + col[j];
+                __builtin_nontemporal_store(damped(cv[0][j], cb[0][j] * rx, a), vx + o);
+                __builtin_nontemporal_store(damped(cv[1][j], cb[1][j] * ry, a), vy + o);
+                __builtin_nontemporal_store(damped(cv[2][j], cb[2][j] * rz, a), vz + o);
+            }
+        }
+    }
+}
+
+template <int R, int BY, int RY>
+__global__ __launch_bounds__(64 * BY) void k_el_stress_zm(ElState st, const ElMedium med,
+                                                          const StepParams p, const int ntx,
+                                                          const int nty, const int nzb)
+{
+    using T = ElZm<R, BY, RY>;
+    constexpr int Q = 2 * R + 1;
+    __shared__ float lds[2][3][T::PL];   // vx, vy, vz
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int zc = b / nty;
+    const int lane = threadIdx.x, wy = threadIdx.y, tid = wy * 64 + lane;
+    const int x0 = tx * T::TX, y0 = ty * T::TY, x = x0 + lane, yb = y0 + wy * RY;
+    const int z0 = zc * nzb, z1 = min(z0 + nzb, p.nz);
+    const int64_t PZ = p.pitch_z, PY = p.pitch_y;
+    const float *fv[3] = {st.f[VX] + p.offset, st.f[VY] + p.offset, st.f[VZ] + p.offset};
+    float *ft[6];
+    const float *fm[5];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ft[c] = st.f[TXX + c] + p.offset;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) fm[c] = med.m[M_LAM + c] + p.offset;
+    bool rl[RY], ro[RY];
+    int64_t col[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        rl[j] = x < p.nx + R && yb + j < p.ny + R;
+        ro[j] = x < p.nx && yb + j < p.ny;
+        col[j] = (int64_t)(yb + j) * PY + x;
+    }
+    const ElRim<R, BY, RY> rim(p, x0, y0, tid);
+
+    float q[3][RY][Q];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k)
+                q[c][j][k + 1] = rl[j] ? fv[c][(int64_t)(z0 - R + k) * PZ + col[j]] : 0.0f;
+    float nf[3][RY], nt[6][RY], nm[5][RY], nyh[3][T::HY], nxh[3][T::HX];
+    auto prefetch = [&](const int z) {
+        const int64_t pz = (int64_t)z * PZ;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int64_t o = pz + col[j];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) nf[c][j] = rl[j] ? fv[c][o + R * PZ] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) nt[c][j] = ro[j] ? ld<true>(ft[c] + o) : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) nm[c][j] = ro[j] ? ld<true>(fm[c] + o) : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k)
+                nyh[c][k] = rim.yk[k] ? fv[c][pz + rim.yo[k]] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k)
+                nxh[c][k] = rim.xk[k] ? fv[c][pz + rim.xo[k]] : 0.0f;
+        }
+    };
+    if (z0 < z1) prefetch(z0);
+
+    const float ax = p.nbl > 0 ? sponge_ax(p, 2, x, p.gx) : 0.0f;
+    for (int z = z0; z < z1; ++z) {
+        float ct[6][RY], cm[5][RY], cyh[3][T::HY], cxh[3][T::HX];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + 1];
+                q[c][j][2 * R] = nf[c][j];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) ct[c][j] = nt[c][j];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) cm[c][j] = nm[c][j];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k) cyh[c][k] = nyh[c][k];
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k) cxh[c][k] = nxh[c][k];
+        }
+        if (z + 1 < z1) prefetch(z + 1);
+
+        float(*L)[T::PL] = lds[z & 1];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int c = (wy * RY + j + R) * T::LX + lane + R;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) L[f][c] = q[f][j][R];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k)
+                if (tid + k * T::NT < T::NHY) L[f][rim.ys[k]] = cyh[f][k];
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k)
+                if (tid + k * T::NT < T::NHX) L[f][rim.xs[k]] = cxh[f][k];
+        }
+        __syncthreads();
+
+        const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int c = (wy * RY + j + R) * T::LX + lane + R;
+            constexpr int LXs = T::LX;
+            const float exx = dm_l<R, 1>(&L[0][c], p.sx), eyy = dm_l<R, LXs>(&L[1][c], p.sy),
+                        ezz = dm_q<R>(q[2][j], p.sz);
+            const float lt = cm[0][j] * ((exx + eyy) + ezz);
+            const float m2 = 2.0f * cm[1][j];
+            const float sxy = cm[2][j] * (dp_l<R, LXs>(&L[0][c], p.sy) + dp_l<R, 1>(&L[1][c], p.sx));
+            const float sxz = cm[3][j] * (dp_q<R>(q[0][j], p.sz) + dp_l<R, 1>(&L[2][c], p.sx));
+            const float syz = cm[4][j] * (dp_q<R>(q[1][j], p.sz) + dp_l<R, LXs>(&L[2][c], p.sy));
+            const int y = yb + j;
+            const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
+            const float a = p.half_dt * ((az + ax) + ay);
+            if (ro[j]) {
+                const int64_t o = (int64_t)z * PZ + col[j];
+                __builtin_nontemporal_store(damped(ct[0][j], lt + m2 * exx, a), ft[0] + o);
+                __builtin_nontemporal_store(damped(ct[1][j], lt + m2 * eyy, a), ft[1] + o);
+                __builtin_nontemporal_store(damped(ct[2][j], lt + m2 * ezz, a), ft[2] + o);
+                __builtin_nontemporal_store(damped(ct[3][j], sxy, a), ft[3] + o);
+                __builtin_nontemporal_store(damped(ct[4][j], sxz, a), ft[4] + o);
+                __builtin_nontemporal_store(damped(ct[5][j], syz, a), ft[5] + o);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -220,6 +626,20 @@ template <int R>
 void el_pass_r(const fd_grid *g, float *const *f, const bool stress, hipStream_t s)
 {
     const StepParams &p = g->sp;
+    if (g->tune.by > 0) {
+        // z-marching passes on 64 x 8 tiles (4 waves, 2 rows per thread)
+        constexpr int BY = 4, RY = 2, TY = BY * RY;
+        const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
+        const int ntx = (p.nx + 63) / 64, nty = (p.ny + TY - 1) / TY;
+        const unsigned nb = (unsigned)ntx * nty * ((p.nz + nzb - 1) / nzb);
+        if (stress)
+            hipLaunchKernelGGL((k_el_stress_zm<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s,
+                               state_of(f), medium_of(g), p, ntx, nty, nzb);
+        else
+            hipLaunchKernelGGL((k_el_velocity_zm<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s,
+                               state_of(f), medium_of(g), p, ntx, nty, nzb);
+        return;
+    }
     const int nxb = (p.nx + 63) / 64, nyb = (p.ny + 3) / 4;
     const unsigned nb = (unsigned)nxb * nyb * p.nz;
     if (stress)

@@ -25,10 +25,12 @@ def _medium(shape, rng):
     return vp, vs, rho
 
 
-def _gpu_run(shape, h, so, dt, nbl, bc, vp, vs, rho, src, q, rec, nt, state=None):
+def _gpu_run(shape, h, so, dt, nbl, bc, vp, vs, rho, src, q, rec, nt, state=None, tile=None):
     import torch
     FD = _fd()
     g = FD.Grid(shape, h, so, dt, 3500.0, nbl=nbl, boundary=bc, physics=FD.FD_ELASTIC)
+    if tile is not None:
+        g.set_tile(*tile)
     g.set_model(to_dev(vp), [to_dev(vs), to_dev(rho)])
     f = [g.field() for _ in range(9)]
     if state is not None:
@@ -45,6 +47,7 @@ def _gpu_run(shape, h, so, dt, nbl, bc, vp, vs, rho, src, q, rec, nt, state=None
     return out, dd
 
 
+@pytest.mark.parametrize("tile", [None, (0,)], ids=["zmarch", "points"])
 @pytest.mark.parametrize("shape,so,nbl,bc", [
     ((20, 22, 70), 8, 4, 0),      # two 64-column tiles with a ragged tail, sponge
     ((17, 13, 19), 4, 3, 1),      # loopback halos of all nine components
@@ -52,7 +55,7 @@ def _gpu_run(shape, h, so, dt, nbl, bc, vp, vs, rho, src, q, rec, nt, state=None
     ((9, 10, 11), 2, 2, 0),       # radius 1
     ((24, 20, 66), 8, 5, 1),
 ])
-def test_elastic_matches_oracle(shape, so, nbl, bc):
+def test_elastic_matches_oracle(shape, so, nbl, bc, tile):
     rng = np.random.default_rng(sum(shape) + so)
     h = (10.0, 9.0, 11.0)
     vp, vs, rho = _medium(shape, rng)
@@ -65,7 +68,7 @@ def test_elastic_matches_oracle(shape, so, nbl, bc):
     # coupling term and every halo is exercised from the first update
     state = {f: (rng.standard_normal(shape) * (1e-3 if f[0] == "v" else 1e3)).astype(np.float32)
              for f in E.FIELDS}
-    got, dg = _gpu_run(shape, h, so, dt, nbl, bc, vp, vs, rho, src, q, rec, nt, state)
+    got, dg = _gpu_run(shape, h, so, dt, nbl, bc, vp, vs, rho, src, q, rec, nt, state, tile)
     og = O.Grid(shape, h, so=so, dt=dt, nbl=nbl, vmax=3500.0, bc=bc)
     ost = E.zero_state(og)
     for f in E.FIELDS:
@@ -77,6 +80,37 @@ def test_elastic_matches_oracle(shape, so, nbl, bc):
         err = rel_l2(got[f], og.interior(want[f]))
         assert err <= 2e-5, (f, err)
     assert rel_l2(dg, dw) <= 2e-5
+
+
+@pytest.mark.parametrize("so", [4, 8, 12])
+def test_elastic_zmarch_bit_identical_across_chunks(so):
+    """The z-marching passes give identical bits for every z chunk (the
+    arithmetic of a point does not depend on the tiling); the
+    one-thread-per-point passes agree with them to FP32 rounding (the
+    compiler may fuse their multiply-adds differently)."""
+    rng = np.random.default_rng(so)
+    shape, h = (21, 19, 70), (10.0, 9.0, 11.0)
+    vp, vs, rho = _medium(shape, rng)
+    dt = synth.elastic_stable_dt(so, min(h), 3500.0)
+    nt = 12
+    src = np.array([[80.0, 90.0, 300.0]])
+    rec = np.stack([rng.uniform(0.0, (s - 1) * hh, 10) for s, hh in zip(shape, h)], 1)
+    q = (synth.ricker(nt, dt, 60.0, t0=0.01)[:, None] * 1e6).astype(np.float32)
+    state = {f: (rng.standard_normal(shape) * (1e-3 if f[0] == "v" else 1e3)).astype(np.float32)
+             for f in E.FIELDS}
+    base = None
+    for tile in [(4, 2, 64, 0), (4, 2, 5, 0), (4, 2, 1, 0), (4, 2, 21, 0)]:
+        got, d = _gpu_run(shape, h, so, dt, 4, 1, vp, vs, rho, src, q, rec, nt, state, tile)
+        if base is None:
+            base = (got, d)
+            continue
+        for f in E.FIELDS:
+            np.testing.assert_array_equal(got[f], base[0][f], err_msg=str((tile, f)))
+        np.testing.assert_array_equal(d, base[1])
+    got, d = _gpu_run(shape, h, so, dt, 4, 1, vp, vs, rho, src, q, rec, nt, state, (0,))
+    for f in E.FIELDS:
+        assert rel_l2(got[f], base[0][f]) <= 1e-6, f
+    assert rel_l2(d, base[1]) <= 1e-6
 
 
 def test_elastic_source_only_first_update():
