@@ -181,22 +181,26 @@ def elastic_cpu_baseline(c, budget_s):
 
 
 def bench_elastic(args):
-    """Isotropic elastic velocity-stress, 512^3, so 8, 363 steps (Gpts/s;
-    one update is the velocity pass and the stress pass)."""
+    """Isotropic elastic velocity-stress, 512^3, so 8, 363 steps, or (visco)
+    the visco-elastic system with one relaxation mechanism, 512^3, so 8, 251
+    steps (Gpts/s; one update is the velocity pass and the stress pass, or
+    the stress-memory pass)."""
     import torch
 
     from paper_2312_13094_amd import fd, synth
-    c = synth.cfg_elastic(n=args.n)
+    visco = args.workload == "visco"
+    c = synth.cfg_visco(n=args.n) if visco else synth.cfg_elastic(n=args.n)
     g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, boundary=c.boundary,
-                physics=fd.FD_ELASTIC)
+                physics=fd.FD_VISCO if visco else fd.FD_ELASTIC)
     if args.tile:
         g.set_tile(*[int(t) for t in args.tile.split(",")])
     n = c.shape[0]
+    profs = c.profiles() if visco else (c.vp_profile, c.vs_profile, c.rho_profile)
     prof = [torch.from_numpy(p).cuda()[:, None, None].expand(n, n, n).contiguous()
-            for p in (c.vp_profile, c.vs_profile, c.rho_profile)]
+            for p in profs]
     g.set_model(prof[0], prof[1:])
     del prof
-    st = [g.field() for _ in range(9)]
+    st = [g.field() for _ in range(15 if visco else 9)]
     S, R = g.sparse(c.src), g.sparse(c.rec)
     q = torch.from_numpy(c.q).cuda()
     d = torch.zeros((c.nt, R.n), device="cuda")
@@ -218,23 +222,28 @@ def bench_elastic(args):
     torch.cuda.empty_cache()
     gpts = c.points * c.nt * args.steps / wall / 1e9
     per_update = kms / max(nl // 2, 1)
-    alg = 140 * c.points
-    out = {"metric": "Gpts/s, 3D so-8 isotropic elastic", "value": round(gpts, 3),
+    bpp = 224 if visco else 140
+    alg = bpp * c.points
+    out = {"metric": "Gpts/s, 3D so-8 %s" % ("visco-elastic" if visco else "isotropic elastic"),
+           "value": round(gpts, 3),
            "unit": "Gpts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": c.name + "_%dsteps_loopback_halo" % c.nt,
                       "shape": list(c.shape), "space_order": c.so, "time_steps": c.nt,
-                      "sponge": c.nbl, "components": 9, "tile": args.tile or "default"},
+                      "sponge": c.nbl, "components": 15 if visco else 9,
+                      "tile": args.tile or "default"},
            "roofline": {"bound": "hbm", "achieved": round(alg / (per_update * 1e-3) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / (per_update * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                         "traffic": None,
-                        "kernel": "elastic velocity pass + stress pass (one update; 60 + 80 B/pt)",
+                        "kernel": ("velocity pass + stress-memory pass (one update; 60 + 164 "
+                                   "B/pt)") if visco else
+                                  "elastic velocity pass + stress pass (one update; 60 + 80 B/pt)",
                         "avg_update_ms": round(per_update, 5), "launches_timed": nl,
                         "algorithmic_bytes_per_update": alg},
            "cpu_baseline": None}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not visco:
         out["cpu_baseline"] = elastic_cpu_baseline(c, args.cpu_budget)
     return out
 
@@ -372,7 +381,7 @@ def main():
                     help="(default; kept for older command lines) time a plain 2 GiB copy first")
     ap.add_argument("--no-copy", action="store_true", help="skip the 2 GiB copy calibration")
     ap.add_argument("--workload", default="acoustic",
-                    choices=["acoustic", "tti", "fwi", "learned", "elastic"],
+                    choices=["acoustic", "tti", "fwi", "learned", "elastic", "visco"],
                     help="acoustic = the headline line; the others print their own line")
     ap.add_argument("--train-models", type=int, default=64)
     ap.add_argument("--train-iters", type=int, default=3000)
@@ -386,7 +395,7 @@ def main():
 
     if args.workload != "acoustic":
         fn = {"tti": bench_tti, "fwi": bench_fwi, "learned": bench_learned,
-              "elastic": bench_elastic}[args.workload]
+              "elastic": bench_elastic, "visco": bench_elastic}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
 

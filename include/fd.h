@@ -56,8 +56,18 @@ enum {
  *                Storage index (z, y, x) holds vx at x+1/2, vy at y+1/2,
  *                vz at z+1/2, the normal stresses at the node, txy at
  *                (y+1/2, x+1/2), txz at (z+1/2, x+1/2), tyz at (z+1/2, y+1/2).
- *                3-D only; FD_BC_ZERO or FD_BC_LOOPBACK. */
-enum { FD_ACOUSTIC = 0, FD_TTI = 1, FD_ELASTIC = 2 };
+ *                3-D only; FD_BC_ZERO or FD_BC_LOOPBACK.
+ *   FD_VISCO     the visco-elastic system with one relaxation mechanism
+ *                (appendix "Visco-elastic", equations (model-equations)),
+ *                the staggered grid of FD_ELASTIC plus six memory variables
+ *                {rxx, ryy, rzz, rxy, rxz, ryz} at their stresses' positions:
+ *                fifteen components in place.  The memory forcing carries
+ *                the factors (tau_e / tau_s - 1), so tau_e = tau_s gives the
+ *                elastic system; the memory variables advance by explicit
+ *                Euler (first order in time, undamped), then the stresses
+ *                take them at the new time level.  3-D only; FD_BC_ZERO or
+ *                FD_BC_LOOPBACK. */
+enum { FD_ACOUSTIC = 0, FD_TTI = 1, FD_ELASTIC = 2, FD_VISCO = 3 };
 
 /* How the halo of the propagated field is refreshed before every step:
  *   FD_BC_ZERO      never written: stays as the caller allocated it (zero);
@@ -76,12 +86,13 @@ typedef struct {
     double spacing[3];      /* metres, same order as shape */
     int space_order;        /* even, 2..16 (TTI: 4..12) */
     int nbl;                /* damping-layer width in points, inside DOMAIN; 0 = none */
-    int physics;            /* FD_ACOUSTIC, FD_TTI or FD_ELASTIC */
+    int physics;            /* FD_ACOUSTIC, FD_TTI, FD_ELASTIC or FD_VISCO */
     int boundary;           /* FD_BC_* */
     double dt;              /* seconds */
     double vmax;            /* upper bound of the velocity model (m/s; FD_ELASTIC:
-                               of the P velocity); sets the damping strength and
-                               the stability check */
+                               of the P velocity; FD_VISCO: of the unrelaxed P
+                               velocity vp sqrt(tau_ep / tau_s)); sets the damping
+                               strength and the stability check */
     double eps_max;         /* TTI: upper bound of epsilon (stability check); else 0 */
     int device;             /* HIP device ordinal */
 } fd_grid_desc;
@@ -113,8 +124,8 @@ typedef struct {
  * the handle's own device memory (model coefficients and, for
  * FD_BC_LOOPBACK, six face buffers).  Returns FD_EUNSTABLE if
  * vmax*dt/h exceeds the leapfrog stability limit of the space order
- * (FD_ELASTIC: vmax dt sqrt(sum 1/h^2) sum_k |c_k| <= 1 with c_k the
- * staggered first-derivative weights). */
+ * (FD_ELASTIC, FD_VISCO: vmax dt sqrt(sum 1/h^2) sum_k |c_k| <= 1 with c_k
+ * the staggered first-derivative weights). */
 int fd_create_grid(const fd_grid_desc *desc, fd_grid **out);
 
 void fd_destroy_grid(fd_grid *g);
@@ -136,7 +147,9 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * tile with nzb planes per block).  FD_ELASTIC grids: by = 0 selects the
  * one-thread-per-point passes, (by, ry) = (4, 2) the z-marching passes on
  * 64 x 8 tiles with nzb planes per block (the default, with the deepest of
- * 256 .. 8 planes giving 1024 blocks; flags are ignored).  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
+ * 256 .. 8 planes giving 1024 blocks; flags are ignored).  FD_VISCO grids
+ * take the same tiles for their velocity pass; their stress-memory pass is
+ * one thread per point.  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same
  * arithmetic per point).  A 3-D grid starts with (8, 2, nzb, 28), nzb the
  * largest of 128, 64, 32 giving 512 blocks ((8, 2, 128, 28) at 512^3);
@@ -198,7 +211,18 @@ int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n,
  * Builds the handle's coefficient fields on the device, then synchronises
  * `stream` to check max(vel) <= vmax (FD_EUNSTABLE otherwise; FD_ELASTIC
  * also needs rho > 0 and 0 <= vs < vp sqrt(3)/2, i.e. mu >= 0 and
- * 3 lambda + 2 mu > 0). */
+ * 3 lambda + 2 mu > 0).
+ * For FD_VISCO, vel_dev is the relaxed P velocity (pi = rho vp^2) and
+ * tti_dev = {vs, rho, tau_ep, tau_es, tau_s} (vs relaxed, mu = rho vs^2;
+ * strain relaxation times for P and S and the stress relaxation time, in
+ * seconds, per node).  The library builds b dt at the velocities as for
+ * FD_ELASTIC; at nodes pi tau_ep/tau_s dt, mu tau_es/tau_s dt,
+ * pi (tau_ep/tau_s - 1), mu (tau_es/tau_s - 1) and dt/tau_s; at each
+ * shear-stress position the means over the four nodes of its plane of
+ * mu tau_es/tau_s (times dt), mu (tau_es/tau_s - 1) and 1/tau_s (times dt).
+ * Checks: unrelaxed vp sqrt(tau_ep/tau_s) <= vmax, rho > 0, 0 <= vs,
+ * 4 vs^2 < 3 vp^2 relaxed and unrelaxed, tau_ep >= tau_s, tau_es >= tau_s
+ * and tau_s >= dt (FD_EUNSTABLE otherwise). */
 int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream);
 
 /* Forward modelling: nt leapfrog updates of equation (acou) (or the TTI
@@ -213,7 +237,9 @@ int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, 
  *              first for FD_BC_LOOPBACK.  Sources are explosive: q[k] w /
  *              h^3 times dt / (1 + gamma dt / 2) is added to txx, tyy and
  *              tzz at each node; receivers record txx + tyy + tzz.  No
- *              checkpoints (FD_ENOTSUP).
+ *              checkpoints (FD_ENOTSUP).  FD_VISCO: the fifteen components
+ *              (memory variables at n like the stresses); the same update
+ *              with the stress pass replaced by the stress-memory pass.
  *   src, q_dev ns sources and their signatures q[nt][ns]; update k uses q[k]
  *              to produce the state at k+1.  src may be NULL (no source).
  *   rec, d_dev nr receivers, traces d[nt][nr]: d[k] sampled after update k.

@@ -162,7 +162,7 @@ int check_stability(const fd_grid_desc &d, int ndim, const double h[3], int r)
     double ih2 = 1.0 / (h[0] * h[0]) + 1.0 / (h[2] * h[2]);
     if (ndim == 3) ih2 += 1.0 / (h[1] * h[1]);
     if (d.physics == FD_TTI) S = d1_symbol_peak(r) * (1.0 + 2.0 * d.eps_max);
-    if (d.physics == FD_ELASTIC) {
+    if (d.physics == FD_ELASTIC || d.physics == FD_VISCO) {
         // the staggered derivative's symbol peaks at 2 sum |c_k| / h
         double c[kMaxR], sum = 0.0;
         stag_weights(r, c);
@@ -275,9 +275,10 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     if (d.ndim != 2 && d.ndim != 3) return set_error(FD_EINVAL, "ndim must be 2 or 3");
     if (d.space_order < 2 || d.space_order > 16 || d.space_order % 2)
         return set_error(FD_EINVAL, "space_order must be even, 2..16");
-    if (d.physics != FD_ACOUSTIC && d.physics != FD_TTI && d.physics != FD_ELASTIC)
+    if (d.physics != FD_ACOUSTIC && d.physics != FD_TTI && d.physics != FD_ELASTIC &&
+        d.physics != FD_VISCO)
         return set_error(FD_EINVAL, "unknown physics");
-    if (d.physics == FD_ELASTIC) {
+    if (d.physics == FD_ELASTIC || d.physics == FD_VISCO) {
         if (d.ndim != 3) return set_error(FD_EINVAL, "elastic needs a 3-D grid");
         if (d.boundary == FD_BC_EXTERNAL)
             return set_error(FD_ENOTSUP, "elastic supports the zero and loopback halos");
@@ -330,7 +331,8 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     make_geometry(d, g->ndim, g->n, g->h, r, g->L, g->sp);
     const fd_layout &L = g->L;
 
-    g->tune = d.physics == FD_ELASTIC ? el_default_tuning(g->n)
+    const bool staggered = d.physics == FD_ELASTIC || d.physics == FD_VISCO;
+    g->tune = staggered             ? el_default_tuning(g->n)
               : d.ndim == 3            ? default_tuning(g->n)
                                        : Tuning{0, 0, 0, 0};
 
@@ -343,8 +345,8 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
         free_grid(g);
         return set_error(FD_ENOMEM, "device allocation failed");
     }
-    if (d.physics == FD_ELASTIC) {
-        for (int i = 0; i < 8; ++i)
+    if (staggered) {
+        for (int i = 0; i < (d.physics == FD_VISCO ? 17 : 8); ++i)
             if (hipMalloc(&g->el[i], L.field_bytes) != hipSuccess ||
                 hipMemset(g->el[i], 0, L.field_bytes) != hipSuccess) {
                 free_grid(g);
@@ -406,7 +408,7 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
         return FD_OK;
     }
     if (g->ndim != 3) return set_error(FD_EINVAL, "tiles apply to 3-D grids");
-    if (g->d.physics == FD_ELASTIC) {
+    if (g->d.physics == FD_ELASTIC || g->d.physics == FD_VISCO) {
         if (by != 4 || ry != 2 || nzb < 1 || xcd < 0 || xcd > 31)
             return set_error(FD_EINVAL, "elastic tiles: (by, ry) = (4, 2) or by = 0");
         g->tune = Tuning{4, 2, nzb, 0};
@@ -476,17 +478,23 @@ int fd_sparse_prepare(const fd_grid *g, const double *coords_m, int n, int32_t *
 int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, void *stream)
 {
     if (!g || !vel_dev) return set_error(FD_EINVAL, "fd_set_model: null argument");
-    const bool tti = g->d.physics == FD_TTI, el = g->d.physics == FD_ELASTIC;
+    const bool tti = g->d.physics == FD_TTI, el = g->d.physics == FD_ELASTIC,
+               vi = g->d.physics == FD_VISCO;
     if (tti && (!tti_dev || !tti_dev[0] || !tti_dev[1] || !tti_dev[2] || !tti_dev[3]))
         return set_error(FD_EINVAL, "fd_set_model: TTI needs epsilon, delta, theta, phi");
     if (el && (!tti_dev || !tti_dev[0] || !tti_dev[1]))
         return set_error(FD_EINVAL, "fd_set_model: elastic needs vs and rho");
+    if (vi && (!tti_dev || !tti_dev[0] || !tti_dev[1] || !tti_dev[2] || !tti_dev[3] ||
+               !tti_dev[4]))
+        return set_error(FD_EINVAL,
+                         "fd_set_model: visco-elastic needs vs, rho, tau_ep, tau_es, tau_s");
     DeviceGuard dg(g->d.device);
     hipStream_t s = (hipStream_t)stream;
     if (hipMemsetAsync(g->scratch_u32, 0, 2 * sizeof(unsigned), s) != hipSuccess)
         return set_error(FD_EDEVICE, "hipMemsetAsync failed");
     int rc = tti  ? launch_tti_model(g, vel_dev, tti_dev, g->scratch_u32, s)
              : el ? launch_el_model(g, vel_dev, tti_dev[0], tti_dev[1], g->scratch_u32, s)
+             : vi ? launch_vi_model(g, vel_dev, tti_dev, g->scratch_u32, s)
                   : launch_build_vdt2(g, vel_dev, g->vdt2, g->scratch_u32, s);
     if (rc) return rc;
     unsigned bits[2] = {0u, 0u};
@@ -508,6 +516,11 @@ int fd_set_model(fd_grid *g, const float *vel_dev, const float *const *tti_dev, 
     if (el && bits[1] != 0u) {
         g->model_loaded = false;
         return set_error(FD_EUNSTABLE, "elastic medium needs rho > 0 and 0 <= vs < vp sqrt(3)/2");
+    }
+    if (vi && bits[1] != 0u) {
+        g->model_loaded = false;
+        return set_error(FD_EUNSTABLE, "visco-elastic medium needs rho > 0, 0 <= vs < vp sqrt(3)/2 "
+                                       "(relaxed and unrelaxed), tau_ep, tau_es >= tau_s >= dt");
     }
     g->model_loaded = true;
     return FD_OK;
@@ -600,7 +613,9 @@ static int forward_elastic(fd_grid *g, float *const *f, SparseArgs inj, SparseAr
         const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
         if (t && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
             return set_error(FD_EDEVICE, "hipEventRecord failed");
-        const int r = stress ? launch_el_stress(g, f, s) : launch_el_velocity(g, f, s);
+        const int r = !stress                      ? launch_el_velocity(g, f, s)
+                      : g->d.physics == FD_VISCO ? launch_vi_stress(g, f, s)
+                                                 : launch_el_stress(g, f, s);
         if (r) return r;
         if (t) {
             if (hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
@@ -635,11 +650,13 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
          state_dev[2] == state_dev[0] || state_dev[2] == state_dev[1] ||
          state_dev[3] == state_dev[0] || state_dev[3] == state_dev[1]))
         return set_error(FD_EINVAL, "fd_forward: TTI needs four distinct state fields");
-    if (g->d.physics == FD_ELASTIC) {
-        for (int i = 0; i < 9; ++i)
+    if (g->d.physics == FD_ELASTIC || g->d.physics == FD_VISCO) {
+        const int nf = g->d.physics == FD_VISCO ? 15 : 9;
+        for (int i = 0; i < nf; ++i)
             for (int j = 0; j < i + 1; ++j)
                 if (!state_dev[i] || (j < i && state_dev[i] == state_dev[j]))
-                    return set_error(FD_EINVAL, "fd_forward: elastic needs nine distinct fields");
+                    return set_error(FD_EINVAL, "fd_forward: elastic needs nine distinct fields, "
+                                                "visco-elastic fifteen");
         if (ckpt_dev) return set_error(FD_ENOTSUP, "fd_forward: no checkpoints for elastic");
     }
     if (!g->model_loaded) return set_error(FD_EINVAL, "fd_forward: no model loaded");
@@ -658,7 +675,7 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
                    nullptr, nullptr, 1.0f};
     if (g->d.physics == FD_TTI)
         return forward_tti(g, state_dev, inj, smp, q_dev, d_dev, nt, ckpt_dev, ckpt_every, s);
-    if (g->d.physics == FD_ELASTIC) {
+    if (g->d.physics == FD_ELASTIC || g->d.physics == FD_VISCO) {
         inj.scale = (float)(g->d.dt / cell_volume(g));
         return forward_elastic(g, state_dev, inj, smp, q_dev, d_dev, nt, s);
     }

@@ -173,7 +173,10 @@ struct fd_grid {
     float *tti[4] = {nullptr, nullptr, nullptr, nullptr};  // padded eps, delta, theta, phi
     // elastic medium times dt at each component's position (padded):
     // b dt at vx, vy, vz; lambda dt, mu dt at nodes; mu dt at txy, txz, tyz
-    float *el[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // visco-elastic: 17 fields (b dt at the velocities; at nodes the unrelaxed
+    // moduli times dt, the memory forcing moduli and dt / tau_s; the same
+    // three at each shear-stress position)
+    float *el[17] = {};
     float *facebuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     float *inter[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // TTI pass-1 output
     unsigned *scratch_u32 = nullptr;  // small device scratch (model checks)
@@ -254,6 +257,12 @@ int launch_el_velocity(const fd_grid *g, float *const *f, hipStream_t s);
 int launch_el_stress(const fd_grid *g, float *const *f, hipStream_t s);
 int launch_el_sparse(const fd_grid *g, float *const *f, const SparseArgs &inj,
                      const SparseArgs &smp, hipStream_t s);
+// visco-elastic (k_elastic.hip): medium build from vp and aux = {vs, rho,
+// tau_ep, tau_es, tau_s}; the stress-memory pass on the fifteen components
+// (the velocity pass is the elastic one)
+int launch_vi_model(const fd_grid *g, const float *vp, const float *const *aux, unsigned *flags,
+                    hipStream_t s);
+int launch_vi_stress(const fd_grid *g, float *const *f, hipStream_t s);
 // z-marching TTI passes (k_tti_zmarch.hip), used by launch_tti_step for 3-D
 // grids whose tile is not the one-thread-per-point kernel
 int launch_tti_step_zm(const fd_grid *g, const float *p, const float *pm, float *pp,

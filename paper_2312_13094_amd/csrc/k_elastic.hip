@@ -575,6 +575,289 @@ __global__ __launch_bounds__(64 * BY) void k_el_stress_zm(ElState st, const ElMe
 }
 
 // ---------------------------------------------------------------------------
+// visco-elastic stress-memory pass (one relaxation mechanism; paper,
+// appendix "Visco-elastic", equations (model-equations)).  With strain rates
+// e from the new velocities, tr = exx + eyy + ezz, dev = e_ii - tr:
+//   r_ii+ = r_ii - KS (r_ii + PD tr + 2 MD dev)
+//   s_ii+ = [(1 - a) s_ii + PU tr + 2 MU dev + dt r_ii+] / (1 + a)
+//   r_ij+ = r_ij - KS_ij (r_ij + MD_ij (e_ij + e_ji))
+//   s_ij+ = [(1 - a) s_ij + MU_ij (e_ij + e_ji) + dt r_ij+] / (1 + a)
+// PU = pi tau_ep/tau_s dt, MU = mu tau_es/tau_s dt (unrelaxed moduli),
+// PD = pi (tau_ep/tau_s - 1), MD = mu (tau_es/tau_s - 1) (memory forcing),
+// KS = dt / tau_s; at shear positions the means over the four nodes of the
+// staggered plane.  Bytes per point: read 6 s, 6 r, 3 v, 14 coefficients;
+// write 6 s, 6 r (164 B).
+// ---------------------------------------------------------------------------
+
+struct ViState {
+    float *f[15];       // vx, vy, vz, txx, tyy, tzz, txy, txz, tyz, rxx, ryy, rzz, rxy, rxz, ryz
+};
+
+struct ViMedium {
+    float *m[17];
+};
+
+enum { V_BX, V_BY, V_BZ, V_PU, V_MU, V_PD, V_MD, V_KS,
+       V_MUXY, V_MDXY, V_KSXY, V_MUXZ, V_MDXZ, V_KSXZ, V_MUYZ, V_MDYZ, V_KSYZ };
+enum { RXX = 9, RYY, RZZ, RXY, RXZ, RYZ };
+
+__global__ __launch_bounds__(256) void k_vi_model(const float *__restrict__ vp,
+                                                  const float *__restrict__ vs,
+                                                  const float *__restrict__ rho,
+                                                  const float *__restrict__ tep,
+                                                  const float *__restrict__ tes,
+                                                  const float *__restrict__ ts, ViMedium med,
+                                                  unsigned *flags, const StepParams p,
+                                                  const float dt)
+{
+    const int64_t n = (int64_t)p.nz * p.ny * p.nx;
+    const int64_t SY = p.nx, SZ = (int64_t)p.ny * p.nx;
+    unsigned mx = 0u, bad = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % p.nx);
+        const int64_t t = i / p.nx;
+        const int y = (int)(t % p.ny);
+        const int z = (int)(t / p.ny);
+        const int64_t ox = x + 1 < p.nx ? 1 : 0;
+        const int64_t oy = y + 1 < p.ny ? SY : 0;
+        const int64_t oz = z + 1 < p.nz ? SZ : 0;
+        auto b = [&](int64_t j) { return 1.0f / rho[j]; };
+        auto muu = [&](int64_t j) { return rho[j] * vs[j] * vs[j] * (tes[j] / ts[j]); };
+        auto mud = [&](int64_t j) { return rho[j] * vs[j] * vs[j] * (tes[j] / ts[j] - 1.0f); };
+        auto ks = [&](int64_t j) { return 1.0f / ts[j]; };
+        const float a = vp[i], s = vs[i], r = rho[i];
+        const float pi = r * a * a, mu = r * s * s;
+        const int64_t j = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y + x;
+        med.m[V_BX][j] = 0.5f * (b(i) + b(i + ox)) * dt;
+        med.m[V_BY][j] = 0.5f * (b(i) + b(i + oy)) * dt;
+        med.m[V_BZ][j] = 0.5f * (b(i) + b(i + oz)) * dt;
+        med.m[V_PU][j] = pi * (tep[i] / ts[i]) * dt;
+        med.m[V_MU][j] = mu * (tes[i] / ts[i]) * dt;
+        med.m[V_PD][j] = pi * (tep[i] / ts[i] - 1.0f);
+        med.m[V_MD][j] = mu * (tes[i] / ts[i] - 1.0f);
+        med.m[V_KS][j] = dt / ts[i];
+        const int64_t pl[3][2] = {{oy, ox}, {oz, ox}, {oz, oy}};   // xy, xz, yz planes
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int64_t u = pl[q][0], v = pl[q][1];
+            med.m[V_MUXY + 3 * q][j] = 0.25f * (muu(i) + muu(i + u) + muu(i + v) + muu(i + u + v)) * dt;
+            med.m[V_MDXY + 3 * q][j] = 0.25f * (mud(i) + mud(i + u) + mud(i + v) + mud(i + u + v));
+            med.m[V_KSXY + 3 * q][j] = 0.25f * (ks(i) + ks(i + u) + ks(i + v) + ks(i + u + v)) * dt;
+        }
+        // unrelaxed P velocity against vmax; positive floats order like
+        // their bit patterns, <= 0 / NaN flagged as +inf
+        const float vpu = a * sqrtf(tep[i] / ts[i]);
+        const unsigned bits = (vpu > 0.0f) ? __float_as_uint(vpu) : 0x7f800000u;
+        mx = bits > mx ? bits : mx;
+        if (!(r > 0.0f) || !(s >= 0.0f) || !(ts[i] >= dt) || !(tep[i] >= ts[i]) ||
+            !(tes[i] >= ts[i]) || !(4.0f * s * s < 3.0f * a * a) ||
+            !(4.0f * s * s * tes[i] < 3.0f * a * a * tep[i]))
+            bad = 1u;
+    }
+    atomicMax(flags, mx);
+    if (bad) atomicOr(flags + 1, 1u);
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_vi_stress_pt(ViState st, const ViMedium med,
+                                                      const StepParams p, const int nxb,
+                                                      const int nyb)
+{
+    int b = blockIdx.x;
+    const int xb = b % nxb;
+    b /= nxb;
+    const int yb = b % nyb;
+    const int z = b / nyb;
+    const int x = xb * 64 + threadIdx.x;
+    const int y = yb * 4 + threadIdx.y;
+    if (x >= p.nx || y >= p.ny) return;
+    const int64_t PY = p.pitch_y, PZ = p.pitch_z;
+    const int64_t i = p.offset + (int64_t)z * PZ + (int64_t)y * PY + x;
+    const float a = damp_a(p, z, y, x);
+    const float dt = 2.0f * p.half_dt;
+    const float *vx = st.f[VX], *vy = st.f[VY], *vz = st.f[VZ];
+    const float e[3] = {dm<R>(vx, i, 1, p.sx), dm<R>(vy, i, PY, p.sy), dm<R>(vz, i, PZ, p.sz)};
+    const float tr = (e[0] + e[1]) + e[2];
+    const float pu = med.m[V_PU][i], mu = med.m[V_MU][i], pd = med.m[V_PD][i],
+                md = med.m[V_MD][i], ks = med.m[V_KS][i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float dev = e[c] - tr;
+        const float r0 = st.f[RXX + c][i];
+        const float r1 = r0 - ks * (r0 + pd * tr + 2.0f * md * dev);
+        st.f[RXX + c][i] = r1;
+        st.f[TXX + c][i] = damped(st.f[TXX + c][i], pu * tr + 2.0f * mu * dev + dt * r1, a);
+    }
+    const float sh[3] = {dp<R>(vx, i, PY, p.sy) + dp<R>(vy, i, 1, p.sx),
+                         dp<R>(vx, i, PZ, p.sz) + dp<R>(vz, i, 1, p.sx),
+                         dp<R>(vy, i, PZ, p.sz) + dp<R>(vz, i, PY, p.sy)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float r0 = st.f[RXY + c][i];
+        const float r1 = r0 - med.m[V_KSXY + 3 * c][i] * (r0 + med.m[V_MDXY + 3 * c][i] * sh[c]);
+        st.f[RXY + c][i] = r1;
+        st.f[TXY + c][i] = damped(st.f[TXY + c][i], med.m[V_MUXY + 3 * c][i] * sh[c] + dt * r1, a);
+    }
+}
+
+// The stress-memory pass as a z-march: queues of vx, vy, vz; LDS planes of
+// vx, vy, vz with both rims; the point's six stresses, six memory
+// variables and fourteen coefficients streamed with the non-temporal hint.
+template <int R, int BY, int RY>
+__global__ __launch_bounds__(64 * BY) void k_vi_stress_zm(ViState st, const ViMedium med,
+                                                          const StepParams p, const int ntx,
+                                                          const int nty, const int nzb)
+{
+    using T = ElZm<R, BY, RY>;
+    constexpr int Q = 2 * R + 1;
+    constexpr int NC = 14;                // coefficients V_PU .. V_KSYZ
+    __shared__ float lds[2][3][T::PL];    // vx, vy, vz
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int zc = b / nty;
+    const int lane = threadIdx.x, wy = threadIdx.y, tid = wy * 64 + lane;
+    const int x0 = tx * T::TX, y0 = ty * T::TY, x = x0 + lane, yb = y0 + wy * RY;
+    const int z0 = zc * nzb, z1 = min(z0 + nzb, p.nz);
+    const int64_t PZ = p.pitch_z, PY = p.pitch_y;
+    const float dt = 2.0f * p.half_dt;
+    const float *fv[3] = {st.f[VX] + p.offset, st.f[VY] + p.offset, st.f[VZ] + p.offset};
+    float *fs[12];                        // txx .. tyz, rxx .. ryz
+    const float *fm[NC];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) fs[c] = st.f[TXX + c] + p.offset;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fm[c] = med.m[V_PU + c] + p.offset;
+    bool rl[RY], ro[RY];
+    int64_t col[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        rl[j] = x < p.nx + R && yb + j < p.ny + R;
+        ro[j] = x < p.nx && yb + j < p.ny;
+        col[j] = (int64_t)(yb + j) * PY + x;
+    }
+    const ElRim<R, BY, RY> rim(p, x0, y0, tid);
+
+    float q[3][RY][Q];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k)
+                q[c][j][k + 1] = rl[j] ? fv[c][(int64_t)(z0 - R + k) * PZ + col[j]] : 0.0f;
+    float nf[3][RY], ns[12][RY], nm[NC][RY], nyh[3][T::HY], nxh[3][T::HX];
+    auto prefetch = [&](const int z) {
+        const int64_t pz = (int64_t)z * PZ;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int64_t o = pz + col[j];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) nf[c][j] = rl[j] ? fv[c][o + R * PZ] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) ns[c][j] = ro[j] ? ld<true>(fs[c] + o) : 0.0f;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) nm[c][j] = ro[j] ? ld<true>(fm[c] + o) : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k)
+                nyh[c][k] = rim.yk[k] ? fv[c][pz + rim.yo[k]] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k)
+                nxh[c][k] = rim.xk[k] ? fv[c][pz + rim.xo[k]] : 0.0f;
+        }
+    };
+    if (z0 < z1) prefetch(z0);
+
+    const float ax = p.nbl > 0 ? sponge_ax(p, 2, x, p.gx) : 0.0f;
+    for (int z = z0; z < z1; ++z) {
+        float cs[12][RY], cm[NC][RY], cyh[3][T::HY], cxh[3][T::HX];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + 1];
+                q[c][j][2 * R] = nf[c][j];
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) cs[c][j] = ns[c][j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) cm[c][j] = nm[c][j];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k) cyh[c][k] = nyh[c][k];
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k) cxh[c][k] = nxh[c][k];
+        }
+        if (z + 1 < z1) prefetch(z + 1);
+
+        float(*L)[T::PL] = lds[z & 1];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int c = (wy * RY + j + R) * T::LX + lane + R;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) L[f][c] = q[f][j][R];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+#pragma unroll
+            for (int k = 0; k < T::HY; ++k)
+                if (tid + k * T::NT < T::NHY) L[f][rim.ys[k]] = cyh[f][k];
+#pragma unroll
+            for (int k = 0; k < T::HX; ++k)
+                if (tid + k * T::NT < T::NHX) L[f][rim.xs[k]] = cxh[f][k];
+        }
+        __syncthreads();
+
+        const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int c = (wy * RY + j + R) * T::LX + lane + R;
+            constexpr int LXs = T::LX;
+            const float e[3] = {dm_l<R, 1>(&L[0][c], p.sx), dm_l<R, LXs>(&L[1][c], p.sy),
+                                dm_q<R>(q[2][j], p.sz)};
+            const float tr = (e[0] + e[1]) + e[2];
+            const float sh[3] = {dp_l<R, LXs>(&L[0][c], p.sy) + dp_l<R, 1>(&L[1][c], p.sx),
+                                 dp_q<R>(q[0][j], p.sz) + dp_l<R, 1>(&L[2][c], p.sx),
+                                 dp_q<R>(q[1][j], p.sz) + dp_l<R, LXs>(&L[2][c], p.sy)};
+            const int y = yb + j;
+            const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
+            const float a = p.half_dt * ((az + ax) + ay);
+            // coefficient slots relative to V_PU
+            const float pu = cm[0][j], mu = cm[1][j], pd = cm[2][j], md = cm[3][j], ks = cm[4][j];
+            float outs[12];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const float dev = e[f] - tr;
+                const float r0 = cs[6 + f][j];
+                const float r1 = r0 - ks * (r0 + pd * tr + 2.0f * md * dev);
+                outs[6 + f] = r1;
+                outs[f] = damped(cs[f][j], pu * tr + 2.0f * mu * dev + dt * r1, a);
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const float r0 = cs[9 + f][j];
+                const float r1 = r0 - cm[7 + 3 * f][j] * (r0 + cm[6 + 3 * f][j] * sh[f]);
+                outs[9 + f] = r1;
+                outs[3 + f] = damped(cs[3 + f][j], cm[5 + 3 * f][j] * sh[f] + dt * r1, a);
+            }
+            if (ro[j]) {
+                const int64_t o = (int64_t)z * PZ + col[j];
+#pragma unroll
+                for (int f = 0; f < 12; ++f) __builtin_nontemporal_store(outs[f], fs[f] + o);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // explosive source and stress-trace receivers
 // ---------------------------------------------------------------------------
 
@@ -666,7 +949,67 @@ int el_pass(const fd_grid *g, float *const *f, const bool stress, hipStream_t s)
     return check_launch(stress ? "elastic stress pass" : "elastic velocity pass");
 }
 
+ViState vstate_of(float *const *f)
+{
+    ViState st;
+    for (int k = 0; k < 15; ++k) st.f[k] = f[k];
+    return st;
+}
+
+ViMedium vmedium_of(const fd_grid *g)
+{
+    ViMedium m;
+    for (int k = 0; k < 17; ++k) m.m[k] = g->el[k];
+    return m;
+}
+
+template <int R>
+void vi_pass_r(const fd_grid *g, float *const *f, hipStream_t s)
+{
+    const StepParams &p = g->sp;
+    if (g->tune.by > 0) {
+        // z-marching stress-memory pass on 64 x 8 tiles (8 waves, one row each)
+        constexpr int BY = 8, RY = 1, TY = BY * RY;
+        const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
+        const int ntx = (p.nx + 63) / 64, nty = (p.ny + TY - 1) / TY;
+        const unsigned nb = (unsigned)ntx * nty * ((p.nz + nzb - 1) / nzb);
+        hipLaunchKernelGGL((k_vi_stress_zm<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s,
+                           vstate_of(f), vmedium_of(g), p, ntx, nty, nzb);
+        return;
+    }
+    const int nxb = (p.nx + 63) / 64, nyb = (p.ny + 3) / 4;
+    const unsigned nb = (unsigned)nxb * nyb * p.nz;
+    hipLaunchKernelGGL((k_vi_stress_pt<R>), dim3(nb), dim3(64, 4), 0, s, vstate_of(f),
+                       vmedium_of(g), p, nxb, nyb);
+}
+
 }  // namespace
+
+int launch_vi_model(const fd_grid *g, const float *vp, const float *const *aux, unsigned *flags,
+                    hipStream_t s)
+{
+    const int64_t n = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_vi_model, dim3(nb), dim3(256), 0, s, vp, aux[0], aux[1], aux[2], aux[3],
+                       aux[4], vmedium_of(g), flags, g->sp, (float)g->d.dt);
+    return check_launch("visco-elastic medium");
+}
+
+int launch_vi_stress(const fd_grid *g, float *const *f, hipStream_t s)
+{
+    switch (g->r) {
+    case 1: vi_pass_r<1>(g, f, s); break;
+    case 2: vi_pass_r<2>(g, f, s); break;
+    case 3: vi_pass_r<3>(g, f, s); break;
+    case 4: vi_pass_r<4>(g, f, s); break;
+    case 5: vi_pass_r<5>(g, f, s); break;
+    case 6: vi_pass_r<6>(g, f, s); break;
+    case 7: vi_pass_r<7>(g, f, s); break;
+    case 8: vi_pass_r<8>(g, f, s); break;
+    default: return set_error(FD_EINVAL, "unsupported stencil radius");
+    }
+    return check_launch("visco-elastic stress-memory pass");
+}
 
 int launch_el_model(const fd_grid *g, const float *vp, const float *vs, const float *rho,
                     unsigned *flags, hipStream_t s)

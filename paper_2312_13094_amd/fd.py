@@ -17,8 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfd.so")
 
 FD_OK, FD_EINVAL, FD_ENOMEM, FD_EDEVICE, FD_EUNSTABLE, FD_ENOTSUP = 0, -1, -2, -3, -4, -5
-FD_ACOUSTIC, FD_TTI, FD_ELASTIC = 0, 1, 2
+FD_ACOUSTIC, FD_TTI, FD_ELASTIC, FD_VISCO = 0, 1, 2, 3
 ELASTIC_FIELDS = ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
+VISCO_FIELDS = ELASTIC_FIELDS + ("rxx", "ryy", "rzz", "rxy", "rxz", "ryz")
 FD_BC_ZERO, FD_BC_LOOPBACK, FD_BC_EXTERNAL = 0, 1, 2
 FD_XCHG_BASIC, FD_XCHG_FULL = 0, 1
 ALL_FACES = 0x3F
@@ -98,9 +99,15 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _ptr_array(ts):
+def _ptr_array(ts, need=0, what="pointer array"):
+    """A C array of device pointers.  The library reads a fixed number of
+    entries from it (given by the call and the handle), so a shorter list
+    is rejected here: reading past its end would pass stray addresses to
+    the kernels."""
     if ts is None:
         return None
+    if len(ts) < need:
+        raise FdError(FD_EINVAL, "%s: %d device arrays needed, %d given" % (what, need, len(ts)))
     arr = (ctypes.c_void_p * len(ts))()
     for k, t in enumerate(ts):
         arr[k] = None if t is None else t.data_ptr()
@@ -221,24 +228,45 @@ class Grid:
     def sparse(self, coords):
         return SparsePoints(self, coords)
 
+    # device arrays a call reads per physics: model aux fields, state fields
+    _AUX = {FD_ACOUSTIC: 0, FD_TTI: 4, FD_ELASTIC: 2, FD_VISCO: 5}
+    _NSTATE = {FD_ACOUSTIC: 2, FD_TTI: 4, FD_ELASTIC: 9, FD_VISCO: 15}
+
     def set_model(self, vel, tti=None):
-        arr = _ptr_array(tti) if tti is not None else None
+        """vel plus the physics' aux fields: TTI {eps, delta, theta, phi},
+        elastic {vs, rho}, visco-elastic {vs, rho, tau_ep, tau_es, tau_s}."""
+        need = self._AUX[self.physics]
+        if tti is not None and len(tti) != need:
+            raise FdError(FD_EINVAL, "set_model: %d aux fields for this physics, %d given"
+                          % (need, len(tti)))
+        arr = _ptr_array(tti, need, "set_model") if tti is not None else None
         _check(lib().fd_set_model(self.handle, _ptr(vel), arr, _stream(self.device)))
+
+    def _ckpt_need(self, nstate, nt, ckpt, every):
+        if ckpt is None or every < 1:
+            return 0
+        return nstate * ((int(nt) + every - 1) // every)
 
     def forward(self, states, src=None, q=None, rec=None, d=None, nt=0, ckpt=None,
                 ckpt_every=0):
+        ns = self._NSTATE[self.physics]
         _check(lib().fd_forward(
-            self.handle, _ptr_array(states), ctypes.byref(src.c) if src else None, _ptr(q),
-            ctypes.byref(rec.c) if rec else None, _ptr(d), int(nt), _ptr_array(ckpt),
+            self.handle, _ptr_array(states, ns, "forward states"),
+            ctypes.byref(src.c) if src else None, _ptr(q),
+            ctypes.byref(rec.c) if rec else None, _ptr(d), int(nt),
+            _ptr_array(ckpt, self._ckpt_need(ns, nt, ckpt, int(ckpt_every)), "checkpoints"),
             int(ckpt_every), _stream(self.device)))
 
     def adjoint(self, states, rec=None, resid=None, src=None, q=None, qadj=None, nt=0,
                 ckpt=None, ckpt_every=0, slots=None, grad_m=None):
+        k = int(ckpt_every)
         _check(lib().fd_adjoint(
-            self.handle, _ptr_array(states), ctypes.byref(rec.c) if rec else None, _ptr(resid),
+            self.handle, _ptr_array(states, 2, "adjoint states"),
+            ctypes.byref(rec.c) if rec else None, _ptr(resid),
             ctypes.byref(src.c) if src else None, _ptr(q), _ptr(qadj), int(nt),
-            _ptr_array(ckpt), int(ckpt_every), _ptr_array(slots), _ptr(grad_m),
-            _stream(self.device)))
+            _ptr_array(ckpt, self._ckpt_need(2, nt, ckpt, k), "checkpoints"), k,
+            _ptr_array(slots, k + 2 if grad_m is not None and k >= 1 else 0, "slots"),
+            _ptr(grad_m), _stream(self.device)))
 
     def step(self, u, um_up, src=None, q=None, rec=None, d=None):
         """One update in place: um_up (u^(n-1)) becomes u^(n+1); q, d are this
@@ -256,11 +284,11 @@ class Grid:
                                              _stream(self.device)))
 
     def pack_halo(self, field, bufs, mask=ALL_FACES):
-        _check(lib().fd_pack_halo(self.handle, _ptr(field), mask, _ptr_array(bufs),
+        _check(lib().fd_pack_halo(self.handle, _ptr(field), mask, _ptr_array(bufs, 6, "faces"),
                                   _stream(self.device)))
 
     def unpack_halo(self, field, bufs, mask=ALL_FACES):
-        _check(lib().fd_unpack_halo(self.handle, _ptr(field), mask, _ptr_array(bufs),
+        _check(lib().fd_unpack_halo(self.handle, _ptr(field), mask, _ptr_array(bufs, 6, "faces"),
                                     _stream(self.device)))
 
     def profile_begin(self, max_launches):
@@ -331,7 +359,9 @@ class Batch:
         _check(lib().fd_batch_set_model(self.handle, _ptr(vel_full), _stream(self.device)))
 
     def gradient(self, q, dobs, d, grad_v):
-        _check(lib().fd_batch_gradient(self.handle, _ptr_array(q), _ptr_array(dobs), _ptr_array(d),
+        n = self.nshots
+        _check(lib().fd_batch_gradient(self.handle, _ptr_array(q, n, "q"),
+                                       _ptr_array(dobs, n, "dobs"), _ptr_array(d, n, "d"),
                                        _ptr(grad_v), _stream(self.device)))
 
     def close(self):

@@ -288,6 +288,61 @@ def cfg_elastic(n: int = 512, nt: int = 363, seed: int = 4, so: int = 8, nbl: in
                    vs.astype(np.float32), rho.astype(np.float32))
 
 
+def sls_times(q, f0):
+    """(tau_e, tau_s) of one standard linear solid whose quality factor
+    peaks at q at frequency f0 (Blanch et al. 1995): w0 = 2 pi f0,
+    tau_s = (sqrt(1 + 1/q^2) - 1/q) / w0, tau_e = 1 / (w0^2 tau_s)."""
+    w0 = 2.0 * math.pi * f0
+    ts = (np.sqrt(1.0 + 1.0 / (q * q)) - 1.0 / q) / w0
+    return 1.0 / (w0 * w0 * ts), ts
+
+
+@dataclass
+class Visco(Elastic):
+    """Visco-elastic workload: the elastic one plus the relaxation times
+    (tau_ep, tau_es, tau_s) per depth."""
+    tep_profile: np.ndarray = None
+    tes_profile: np.ndarray = None
+    ts_profile: np.ndarray = None
+
+    def fields(self):
+        """DOMAIN-shaped float32 (vp, vs, rho, tau_ep, tau_es, tau_s)."""
+        out = []
+        for p in (self.vp_profile, self.vs_profile, self.rho_profile, self.tep_profile,
+                  self.tes_profile, self.ts_profile):
+            out.append(np.ascontiguousarray(
+                np.broadcast_to(p.reshape(-1, 1, 1), self.shape)).astype(np.float32))
+        return tuple(out)
+
+    def profiles(self):
+        return (self.vp_profile, self.vs_profile, self.rho_profile, self.tep_profile,
+                self.tes_profile, self.ts_profile)
+
+
+def cfg_visco(n: int = 512, nt: int = 251, seed: int = 4, so: int = 8, nbl: int = 40,
+              boundary: int = 1, f0: float = 15.0) -> Visco:
+    """3-D layered visco-elastic on an n^3 DOMAIN (benchmark: 512^3, so 8,
+    251 steps, the paper's visco-elastic step count for 512 ms): the elastic
+    workload's vp, vs, rho with quality factors Qp = 40 vp / 1 km/s and
+    Qs = Qp / 2 (stiffer layers attenuate less), one relaxation mechanism
+    centred on the 15 Hz source frequency."""
+    e = cfg_elastic(n=n, nt=nt, seed=seed, so=so, nbl=nbl, boundary=boundary)
+    vp = e.vp_profile.astype(np.float64)
+    qp = 40.0 * vp / 1000.0
+    qs = qp / 2.0
+    tep, ts = sls_times(qp, f0)
+    # one stress relaxation time per node (the P mechanism's); the S strain
+    # relaxation time then solves Qs(w0) = (1 + w0^2 tes ts) / (w0 (tes - ts)) = qs
+    w0 = 2.0 * math.pi * f0
+    tes = (qs * w0 * ts + 1.0) / (w0 * (qs - w0 * ts))
+    vmax = float(np.max(vp * np.sqrt(tep / ts))) * 1.001
+    dt = elastic_stable_dt(so, e.spacing[0], vmax)
+    q = ricker(nt, dt, f0)[:, None]
+    return Visco("visco3d_%dcube_so%d_layered" % (n, so), e.shape, e.spacing, so, nbl, dt, nt,
+                 vmax, boundary, e.src, e.rec, q, e.vp_profile, e.vs_profile, e.rho_profile,
+                 tep.astype(np.float32), tes.astype(np.float32), ts.astype(np.float32))
+
+
 @dataclass
 class FWIBatch:
     """Batched-gradient workload: a full model (layered + Gaussian anomaly),

@@ -81,3 +81,18 @@ def test_null_arguments(lib):
     assert lib.fd_forward(None, None, None, None, None, None, 0, None, 0, None) == fd.FD_EINVAL
     assert lib.fd_pack_halo(None, None, 0, None, None) == fd.FD_EINVAL
     assert lib.fd_halo_face_elems(None, 0) < 0
+
+
+def test_binding_rejects_short_pointer_arrays():
+    """The library reads a fixed number of device pointers from an array
+    argument (per physics and call); the binding refuses a shorter list
+    before the call, so no stray address can reach a kernel."""
+    from paper_2312_13094_amd import fd
+    with pytest.raises(fd.FdError) as e:
+        fd._ptr_array([None] * 4, 5, "set_model")
+    assert e.value.code == fd.FD_EINVAL
+    assert fd._ptr_array([None] * 5, 5) is not None
+    assert fd._ptr_array(None, 5) is None
+    assert fd.Grid._AUX == {fd.FD_ACOUSTIC: 0, fd.FD_TTI: 4, fd.FD_ELASTIC: 2, fd.FD_VISCO: 5}
+    assert fd.Grid._NSTATE == {fd.FD_ACOUSTIC: 2, fd.FD_TTI: 4, fd.FD_ELASTIC: 9,
+                               fd.FD_VISCO: 15}
