@@ -145,6 +145,27 @@ def bench_tti(args):
                          "algorithmic_bytes_per_launch": alg}}
 
 
+EL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elastic_step_512cube_so8_traffic.json")
+
+
+def _el_traffic(tile, n):
+    """HBM bytes per elastic update (both passes) from the committed PMC
+    summary, or None if absent, taken on other kernel sources, another tile
+    or another size."""
+    try:
+        with open(EL_TRAFFIC_FILE) as f:
+            t = json.load(f)
+        h = hashlib.sha256()
+        for p in t["kernel_sources"]:
+            with open(os.path.join(ROOT, p), "rb") as f:
+                h.update(f.read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if t.get("kernel_source_sha256") != h.hexdigest() or t.get("tile") != tile or n != 512:
+        return None
+    return t.get("hbm_bytes_per_update")
+
+
 def elastic_cpu_baseline(c, budget_s):
     """The FP64 elastic oracle (numpy) on a 128^3 box of the same layered
     medium: per-step cost from 1- and 3-step runs, then as many steps as fit
@@ -189,7 +210,8 @@ def bench_elastic(args):
 
     from paper_2312_13094_amd import fd, synth
     visco = args.workload == "visco"
-    c = synth.cfg_visco(n=args.n) if visco else synth.cfg_elastic(n=args.n)
+    kw = {"nt": args.el_nt} if args.el_nt else {}
+    c = synth.cfg_visco(n=args.n, **kw) if visco else synth.cfg_elastic(n=args.n, **kw)
     g = fd.Grid(c.shape, c.spacing, c.so, c.dt, c.vmax, nbl=c.nbl, boundary=c.boundary,
                 physics=fd.FD_VISCO if visco else fd.FD_ELASTIC)
     if args.tile:
@@ -236,7 +258,7 @@ def bench_elastic(args):
            "roofline": {"bound": "hbm", "achieved": round(alg / (per_update * 1e-3) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / (per_update * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                        "traffic": None,
+                        "traffic": None if visco else _el_traffic(args.tile or "default", args.n),
                         "kernel": ("velocity pass + stress-memory pass (one update; 60 + 164 "
                                    "B/pt)") if visco else
                                   "elastic velocity pass + stress pass (one update; 60 + 80 B/pt)",
@@ -383,6 +405,8 @@ def main():
     ap.add_argument("--workload", default="acoustic",
                     choices=["acoustic", "tti", "fwi", "learned", "elastic", "visco"],
                     help="acoustic = the headline line; the others print their own line")
+    ap.add_argument("--el-nt", type=int, default=0,
+                    help="elastic / visco updates per bench step (default: the workload's 363 / 251)")
     ap.add_argument("--train-models", type=int, default=64)
     ap.add_argument("--train-iters", type=int, default=3000)
     ap.add_argument("--test-models", type=int, default=8)

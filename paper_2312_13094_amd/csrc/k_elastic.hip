@@ -910,17 +910,25 @@ void el_pass_r(const fd_grid *g, float *const *f, const bool stress, hipStream_t
 {
     const StepParams &p = g->sp;
     if (g->tune.by > 0) {
-        // z-marching passes on 64 x 8 tiles (4 waves, 2 rows per thread)
-        constexpr int BY = 4, RY = 2, TY = BY * RY;
+        // z-marching passes on 64 x 8 tiles: 4 waves with 2 rows per thread,
+        // or 8 waves with one row each
         const int nzb = g->tune.nzb > 0 ? g->tune.nzb : 64;
-        const int ntx = (p.nx + 63) / 64, nty = (p.ny + TY - 1) / TY;
+        const int ntx = (p.nx + 63) / 64, nty = (p.ny + 7) / 8;
         const unsigned nb = (unsigned)ntx * nty * ((p.nz + nzb - 1) / nzb);
-        if (stress)
-            hipLaunchKernelGGL((k_el_stress_zm<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s,
+        if (g->tune.by == 8) {
+            if (stress)
+                hipLaunchKernelGGL((k_el_stress_zm<R, 8, 1>), dim3(nb), dim3(64, 8), 0, s,
+                                   state_of(f), medium_of(g), p, ntx, nty, nzb);
+            else
+                hipLaunchKernelGGL((k_el_velocity_zm<R, 8, 1>), dim3(nb), dim3(64, 8), 0, s,
+                                   state_of(f), medium_of(g), p, ntx, nty, nzb);
+        } else if (stress) {
+            hipLaunchKernelGGL((k_el_stress_zm<R, 4, 2>), dim3(nb), dim3(64, 4), 0, s,
                                state_of(f), medium_of(g), p, ntx, nty, nzb);
-        else
-            hipLaunchKernelGGL((k_el_velocity_zm<R, BY, RY>), dim3(nb), dim3(64, BY), 0, s,
+        } else {
+            hipLaunchKernelGGL((k_el_velocity_zm<R, 4, 2>), dim3(nb), dim3(64, 4), 0, s,
                                state_of(f), medium_of(g), p, ntx, nty, nzb);
+        }
         return;
     }
     const int nxb = (p.nx + 63) / 64, nyb = (p.ny + 3) / 4;

@@ -84,8 +84,8 @@ def test_elastic_matches_oracle(shape, so, nbl, bc, tile):
 
 @pytest.mark.parametrize("so", [4, 8, 12])
 def test_elastic_zmarch_bit_identical_across_chunks(so):
-    """The z-marching passes give identical bits for every z chunk (the
-    arithmetic of a point does not depend on the tiling); the
+    """The z-marching passes give identical bits for every z chunk and both
+    tile shapes (the arithmetic of a point does not depend on the tiling); the
     one-thread-per-point passes agree with them to FP32 rounding (the
     compiler may fuse their multiply-adds differently)."""
     rng = np.random.default_rng(so)
@@ -99,7 +99,8 @@ def test_elastic_zmarch_bit_identical_across_chunks(so):
     state = {f: (rng.standard_normal(shape) * (1e-3 if f[0] == "v" else 1e3)).astype(np.float32)
              for f in E.FIELDS}
     base = None
-    for tile in [(4, 2, 64, 0), (4, 2, 5, 0), (4, 2, 1, 0), (4, 2, 21, 0)]:
+    for tile in [(4, 2, 64, 0), (4, 2, 5, 0), (4, 2, 1, 0), (4, 2, 21, 0), (8, 1, 64, 0),
+                 (8, 1, 7, 0)]:
         got, d = _gpu_run(shape, h, so, dt, 4, 1, vp, vs, rho, src, q, rec, nt, state, tile)
         if base is None:
             base = (got, d)
