@@ -190,11 +190,14 @@ __global__ __launch_bounds__(256) void k_swap(float4 *a, float4 *b, int64_t n4)
     }
 }
 
-__global__ __launch_bounds__(256) void k_copy4(float4 *dst, const float4 *src, int64_t n4)
+// One 16-byte element per thread, non-temporal both ways: many short-lived
+// blocks keep the most loads in flight (a grid-stride loop over a capped
+// grid measured 4.7 TB/s on 2 GiB, this shape 6.6 TB/s).
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy4(v4f *dst, const v4f *src, int64_t n4)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 __global__ __launch_bounds__(256) void k_copy1(float *dst, const float *src, int64_t n)
@@ -210,9 +213,10 @@ int launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
     if (n % 4 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(src) % 16 == 0) {
         const int64_t n4 = n / 4;
-        const int nb = (int)std::min<int64_t>((n4 + 255) / 256, 16384);
-        hipLaunchKernelGGL(k_copy4, dim3(nb), dim3(256), 0, s, reinterpret_cast<float4 *>(dst),
-                           reinterpret_cast<const float4 *>(src), n4);
+        const int64_t nb = (n4 + 255) / 256;
+        if (nb > 0x7fffffff) return set_error(FD_EINVAL, "copy too large");
+        hipLaunchKernelGGL(k_copy4, dim3((unsigned)nb), dim3(256), 0, s,
+                           reinterpret_cast<v4f *>(dst), reinterpret_cast<const v4f *>(src), n4);
     } else {
         const int nb = (int)std::min<int64_t>((n + 255) / 256, 16384);
         hipLaunchKernelGGL(k_copy1, dim3(nb), dim3(256), 0, s, dst, src, n);

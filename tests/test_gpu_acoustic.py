@@ -156,7 +156,8 @@ def test_tiles_are_bit_identical():
                  (8, 4, 64, 0), (2, 8, 3, 1), (4, 4, 64, 2), (4, 4, 7, 3), (4, 2, 13, 6),
                  (8, 2, 9, 7), (4, 1, 5, 4), (4, 4, 64, 8), (8, 4, 11, 12), (4, 2, 3, 13),
                  (2, 8, 64, 9), (8, 2, 64, 12), (8, 4, 128, 12), (8, 2, 64, 28),
-                 (4, 4, 7, 20), (4, 4, 11, 16), (4, 2, 13, 29)]:
+                 (4, 4, 7, 20), (4, 4, 11, 16), (4, 2, 13, 29), (8, 2, 64, 30),
+                 (8, 2, 9, 31), (4, 4, 11, 26), (4, 1, 5, 10), (8, 4, 7, 14)]:
         u, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, 5, nbl=7, u0=u0, tile=tile)
         if base is None:
             base = u
