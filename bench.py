@@ -137,7 +137,8 @@ def bench_tti(args):
             "roofline": {"bound": "hbm", "achieved": round(alg / (avg * 1e-3) / 1e9, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": None,
+                         "traffic": _traffic_summary(TTI_TRAFFIC_FILE, "hbm_bytes_per_step",
+                                                     args.tile or "default", n == 384),
                          "kernel": ("k_tti_grad_zm + k_tti_div_zm" if zm else
                                     "k_tti_pass1 + k_tti_pass2") + " (one step, two passes "
                                    "moving 100 B/pt: 24 B of intermediates written and read)",
@@ -148,12 +149,15 @@ def bench_tti(args):
 EL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elastic_step_512cube_so8_traffic.json")
 
 
-def _el_traffic(tile, n):
-    """HBM bytes per elastic update (both passes) from the committed PMC
-    summary, or None if absent, taken on other kernel sources, another tile
-    or another size."""
+VI_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "visco_step_512cube_so8_traffic.json")
+TTI_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tti_step_384cube_so12_traffic.json")
+
+
+def _traffic_summary(path, key, tile, size_ok):
+    """HBM bytes per update (`key`) from a committed PMC summary, or None if
+    absent, taken on other kernel sources, another tile or another size."""
     try:
-        with open(EL_TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
         h = hashlib.sha256()
         for p in t["kernel_sources"]:
@@ -161,9 +165,14 @@ def _el_traffic(tile, n):
                 h.update(f.read())
     except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_source_sha256") != h.hexdigest() or t.get("tile") != tile or n != 512:
+    if t.get("kernel_source_sha256") != h.hexdigest() or t.get("tile") != tile or not size_ok:
         return None
-    return t.get("hbm_bytes_per_update")
+    return t.get(key)
+
+
+def _el_traffic(tile, n, visco=False):
+    return _traffic_summary(VI_TRAFFIC_FILE if visco else EL_TRAFFIC_FILE, "hbm_bytes_per_update",
+                            tile, n == 512)
 
 
 def elastic_cpu_baseline(c, budget_s):
@@ -258,7 +267,7 @@ def bench_elastic(args):
            "roofline": {"bound": "hbm", "achieved": round(alg / (per_update * 1e-3) / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(alg / (per_update * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                        "traffic": None if visco else _el_traffic(args.tile or "default", args.n),
+                        "traffic": _el_traffic(args.tile or "default", args.n, visco),
                         "kernel": ("velocity pass + stress-memory pass (one update; 60 + 164 "
                                    "B/pt)") if visco else
                                   "elastic velocity pass + stress pass (one update; 60 + 80 B/pt)",

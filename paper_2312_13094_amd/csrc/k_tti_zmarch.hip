@@ -20,7 +20,7 @@ namespace fd {
 
 namespace {
 
-constexpr int kTtiBy = 4, kTtiRy = 2;
+constexpr int kTtiBy = 8, kTtiRy = 2;
 
 // Which halo element of a 64 x TY tile's R-wide ring a thread stages: y ring
 // (rows above and below, 64 wide) or x ring (columns left and right, TY
