@@ -143,7 +143,7 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * columns wide with two columns per lane (with bit 3 behaviour; only for
  * (by, ry) = (8,2) (4,2) (4,4)).  by = 0 selects the
  * one-thread-per-point kernel.  FD_TTI grids use only by = 0 (the
- * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 8
+ * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 16
  * tile with nzb planes per block).  FD_ELASTIC grids: by = 0 selects the
  * one-thread-per-point passes, (by, ry) = (4, 2) or (8, 1) the z-marching
  * passes on 64 x 8 tiles with nzb planes per block ((4, 2) the default, with the deepest of
