@@ -145,9 +145,10 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * one-thread-per-point kernel.  FD_TTI grids use only by = 0 (the
  * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 16
  * tile with nzb planes per block).  FD_ELASTIC grids: by = 0 selects the
- * one-thread-per-point passes, (by, ry) = (4, 2) or (8, 1) the z-marching
- * passes on 64 x 8 tiles with nzb planes per block ((4, 2) the default, with the deepest of
- * 256 .. 8 planes giving 1024 blocks; flags are ignored).  FD_VISCO grids
+ * one-thread-per-point passes, (by, ry) = (4, 2), (8, 1) or (8, 2) the
+ * z-marching passes on 64 x (by ry) tiles with nzb planes per block ((8, 2)
+ * the default, with the deepest of 256 .. 8 planes giving 1024 blocks;
+ * flags are ignored).  FD_VISCO grids
  * take the same tiles for their velocity pass; their stress-memory pass is
  * one thread per point.  Supported (by, ry): (4,1) (4,2) (4,4) (4,8)
  * (8,2) (8,4) (2,8).  Results do not depend on the tile or flags (same

@@ -409,8 +409,9 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
     }
     if (g->ndim != 3) return set_error(FD_EINVAL, "tiles apply to 3-D grids");
     if (g->d.physics == FD_ELASTIC || g->d.physics == FD_VISCO) {
-        if (!((by == 4 && ry == 2) || (by == 8 && ry == 1)) || nzb < 1 || xcd < 0 || xcd > 31)
-            return set_error(FD_EINVAL, "elastic tiles: (by, ry) = (4, 2), (8, 1) or by = 0");
+        if (!((by == 4 && ry == 2) || (by == 8 && (ry == 1 || ry == 2))) || nzb < 1 || xcd < 0 ||
+            xcd > 31)
+            return set_error(FD_EINVAL, "elastic tiles: (by, ry) = (4, 2), (8, 1), (8, 2) or by = 0");
         g->tune = Tuning{by, ry, nzb, 0};
         return FD_OK;
     }

@@ -138,14 +138,14 @@ inline Tuning default_tuning(const int n[3])
     return Tuning{4, 1, 8, kTileRing | kTileNts};
 }
 
-// Elastic passes: z-marching 64 x 8 tiles, (by, ry) = (4, 2); the deepest
+// Elastic passes: z-marching 64 x 16 tiles, (by, ry) = (8, 2); the deepest
 // z chunk of 256 .. 8 planes that still gives 1024 blocks.
 inline Tuning el_default_tuning(const int n[3])
 {
-    const int64_t tiles = (int64_t)((n[2] + 63) / 64) * ((n[1] + 7) / 8);
+    const int64_t tiles = (int64_t)((n[2] + 63) / 64) * ((n[1] + 15) / 16);
     for (int nzb = 256; nzb > 8; nzb /= 2)
-        if (tiles * ((n[0] + nzb - 1) / nzb) >= 1024) return Tuning{4, 2, nzb, 0};
-    return Tuning{4, 2, 8, 0};
+        if (tiles * ((n[0] + nzb - 1) / nzb) >= 1024) return Tuning{8, 2, nzb, 0};
+    return Tuning{8, 2, 8, 0};
 }
 
 // One set of sparse points bound to a step.

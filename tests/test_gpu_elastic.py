@@ -100,7 +100,7 @@ def test_elastic_zmarch_bit_identical_across_chunks(so):
              for f in E.FIELDS}
     base = None
     for tile in [(4, 2, 64, 0), (4, 2, 5, 0), (4, 2, 1, 0), (4, 2, 21, 0), (8, 1, 64, 0),
-                 (8, 1, 7, 0)]:
+                 (8, 1, 7, 0), (8, 2, 64, 0), (8, 2, 3, 0)]:
         got, d = _gpu_run(shape, h, so, dt, 4, 1, vp, vs, rho, src, q, rec, nt, state, tile)
         if base is None:
             base = (got, d)

@@ -167,7 +167,7 @@ def test_visco_errors():
     assert code(lambda: g.set_model(full(3000.0), big)) == FD.FD_EUNSTABLE
     g.set_model(full(3000.0), ok)
     assert code(lambda: g.forward(f[:14] + [f[3]], nt=1)) == FD.FD_EINVAL      # aliasing
-    assert code(lambda: g.set_tile(8, 2, 64, 0)) == FD.FD_EINVAL
+    assert code(lambda: g.set_tile(8, 4, 64, 0)) == FD.FD_EINVAL
     assert code(lambda: g.adjoint(f[:2], nt=1)) == FD.FD_ENOTSUP
     g.forward(f, nt=0)
     g.close()
