@@ -175,26 +175,27 @@ def _el_traffic(tile, n, visco=False):
                             tile, n == 512)
 
 
-def elastic_cpu_baseline(c, budget_s):
-    """The FP64 elastic oracle (numpy) on a 128^3 box of the same layered
-    medium: per-step cost from 1- and 3-step runs, then as many steps as fit
-    in about `budget_s` seconds."""
+def elastic_cpu_baseline(c, budget_s, visco=False):
+    """The FP64 elastic (or visco-elastic) oracle (numpy) on a 128^3 box of
+    the same layered medium: per-step cost from 1- and 3-step runs, then as
+    many steps as fit in about `budget_s` seconds."""
     import numpy as np
 
     import oracle as O
     import oracle.elastic as E
+    import oracle.visco as V
     m = 128
     shape = (m, m, m)
     og = O.Grid(shape, c.spacing, so=c.so, dt=c.dt, nbl=c.nbl, vmax=c.vmax, bc=c.boundary)
-    med = [np.broadcast_to(p[:m].astype(np.float64)[:, None, None], shape)
-           for p in (c.vp_profile, c.vs_profile, c.rho_profile)]
+    profs = c.profiles() if visco else (c.vp_profile, c.vs_profile, c.rho_profile)
+    med = [np.broadcast_to(p[:m].astype(np.float64)[:, None, None], shape) for p in profs]
     src = np.array([[min(c.src[0, 0], (m - 1) * c.spacing[0]), (m / 2 - 0.5) * c.spacing[1],
                      (m / 2 - 0.5) * c.spacing[2]]])
     q = c.q.astype(np.float64)
 
     def run(nt):
         t0 = time.perf_counter()
-        E.forward(og, *med, src=src, q=q[:nt], nt=nt)
+        (V if visco else E).forward(og, *med, src=src, q=q[:nt], nt=nt)
         return time.perf_counter() - t0
 
     t1, t3 = run(1), run(3)
@@ -207,7 +208,8 @@ def elastic_cpu_baseline(c, budget_s):
     return {"value": round(m ** 3 * nt / net / 1e9, 4), "unit": "Gpts/s", "cores": threads,
             "nproc": os.cpu_count(), "kind": "oracle",
             "sample": "128^3 box (top of the same layered medium), %d of %d time steps, FP64 "
-                      "numpy oracle (%.1f s, set-up excluded)" % (nt, c.nt, net)}
+                      "numpy %s oracle (%.1f s, set-up excluded)"
+                      % (nt, c.nt, "visco-elastic" if visco else "elastic", net)}
 
 
 def bench_elastic(args):
@@ -274,8 +276,8 @@ def bench_elastic(args):
                         "avg_update_ms": round(per_update, 5), "launches_timed": nl,
                         "algorithmic_bytes_per_update": alg},
            "cpu_baseline": None}
-    if not args.no_cpu_baseline and not visco:
-        out["cpu_baseline"] = elastic_cpu_baseline(c, args.cpu_budget)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = elastic_cpu_baseline(c, args.cpu_budget, visco)
     return out
 
 
