@@ -53,7 +53,7 @@ int launch_batch_copy(const BatchShot *shots_dev, int nshots, int64_t max_stride
                       int fdst, hipStream_t s);
 int launch_batch_zero(const BatchShot *shots_dev, int nshots, int64_t max_stride, int f,
                       hipStream_t s);
-int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_pts, int flam,
+int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_rows, int flam,
                          int fup, int fu, int fum, float inv_dt2, float inv_2dt, hipStream_t s);
 int launch_batch_reduce(const BatchShot *shots_dev, int nshots, const int64_t full[3],
                         const float *vel_full, float *grad_v, hipStream_t s);

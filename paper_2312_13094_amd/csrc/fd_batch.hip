@@ -41,7 +41,7 @@ struct fd_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<const void *> key;
     size_t bytes = 0;
-    int64_t max_stride = 0, max_pts = 0;
+    int64_t max_stride = 0, max_pts = 0, max_rows = 0;
     bool model_loaded = false;
 };
 
@@ -158,7 +158,7 @@ int enqueue_schedule(fd_batch *b, float *grad_v, hipStream_t s)
             FD_TRY(launch_batch_sparse(T, ns, 2, n, lamo, hinv, s));
             std::swap(lam, lamo);
             const int i = n - lo;
-            FD_TRY(launch_batch_imaging(T, ns, b->max_pts, lam, slot0 + i + 2, slot0 + i + 1,
+            FD_TRY(launch_batch_imaging(T, ns, b->max_rows, lam, slot0 + i + 2, slot0 + i + 1,
                                         slot0 + i, inv_dt2, inv_2dt, s));
         }
     }
@@ -228,6 +228,7 @@ int fd_batch_create(const fd_grid_desc *common, int nshots, const int64_t *shape
         make_geometry(dd, 3, s.n, h, r, s.L, s.p);
         b->max_stride = std::max<int64_t>(b->max_stride, s.L.field_elems);
         b->max_pts = std::max<int64_t>(b->max_pts, (int64_t)s.n[0] * s.n[1] * s.n[2]);
+        b->max_rows = std::max<int64_t>(b->max_rows, (int64_t)s.n[0] * s.n[1]);
     }
     layout_blocks(b);
     DeviceGuard dg(d.device);

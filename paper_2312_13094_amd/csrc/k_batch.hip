@@ -119,39 +119,50 @@ int launch_batch_zero(const BatchShot *shots_dev, int nshots, int64_t max_stride
 }
 
 // g -= lambda * [((u+ - u) - (u - u-)) / dt^2 + gamma (u+ - u-) / (2 dt)]
-__global__ __launch_bounds__(256) void k_batch_imaging(const BatchShot *__restrict__ shots,
-                                                       const int flam, const int fup,
-                                                       const int fu, const int fum,
-                                                       const float inv_dt2, const float inv_2dt)
+// One wave per (z, y) row of a shot's DOMAIN, lanes along x: the row's
+// sponge terms in z and y are taken once, and no per-point 64-bit division
+// is needed to find a point's coordinates.  Every operand is streamed once
+// per launch (the fields of all shots far exceed the caches), so the loads
+// and the store carry non-temporal hints.
+constexpr int kImgRows = 4;   // rows (waves) per block
+
+__global__ __launch_bounds__(64 * kImgRows) void k_batch_imaging(
+    const BatchShot *__restrict__ shots, const int flam, const int fup, const int fu,
+    const int fum, const float inv_dt2, const float inv_2dt)
 {
     const BatchShot &S = shots[blockIdx.y];
     const StepParams &p = S.p;
-    const int64_t n = (int64_t)p.nz * p.ny * p.nx;
+    const int nrows = p.nz * p.ny;
     const float *lam = S.base + flam * S.stride, *up = S.base + fup * S.stride;
     const float *u0 = S.base + fu * S.stride, *um = S.base + fum * S.stride;
     float *g = S.base + kGrad * S.stride;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % p.nx);
-        const int64_t t = i / p.nx;
-        const int y = (int)(t % p.ny);
-        const int z = (int)(t / p.ny);
-        const int64_t j = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y + x;
-        float gam = 0.0f;
-        if (p.nbl > 0)
-            gam = sponge_ax(p, 0, z, p.gz) + sponge_ax(p, 2, x, p.gx) +
-                  sponge_ax(p, 1, y, p.gy);
-        const float a = up[j], b = u0[j], c = um[j];
-        g[j] -= lam[j] * (((a - b) - (b - c)) * inv_dt2 + gam * (a - c) * inv_2dt);
+    const bool damp = p.nbl > 0;
+    for (int row = blockIdx.x * kImgRows + threadIdx.y; row < nrows;
+         row += gridDim.x * kImgRows) {
+        const int z = row / p.ny, y = row - z * p.ny;
+        const float gzz = damp ? sponge_ax(p, 0, z, p.gz) : 0.0f;
+        const float gyy = damp ? sponge_ax(p, 1, y, p.gy) : 0.0f;
+        const int64_t j0 = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y;
+        for (int x = threadIdx.x; x < p.nx; x += 64) {
+            const int64_t j = j0 + x;
+            const float gam = damp ? (gzz + sponge_ax(p, 2, x, p.gx)) + gyy : 0.0f;
+            const float a = __builtin_nontemporal_load(up + j);
+            const float b = __builtin_nontemporal_load(u0 + j);
+            const float c = __builtin_nontemporal_load(um + j);
+            const float l = __builtin_nontemporal_load(lam + j);
+            const float gj = __builtin_nontemporal_load(g + j);
+            __builtin_nontemporal_store(
+                gj - l * (((a - b) - (b - c)) * inv_dt2 + gam * (a - c) * inv_2dt), g + j);
+        }
     }
 }
 
-int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_pts, int flam,
+int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_rows, int flam,
                          int fup, int fu, int fum, float inv_dt2, float inv_2dt, hipStream_t s)
 {
-    const int nb = (int)std::min<int64_t>((max_pts + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_batch_imaging, dim3(nb, nshots), dim3(256), 0, s, shots_dev, flam, fup,
-                       fu, fum, inv_dt2, inv_2dt);
+    const int nb = (int)std::min<int64_t>((max_rows + kImgRows - 1) / kImgRows, 65535);
+    hipLaunchKernelGGL(k_batch_imaging, dim3(nb, nshots), dim3(64, kImgRows), 0, s, shots_dev,
+                       flam, fup, fu, fum, inv_dt2, inv_2dt);
     return check_launch("batched imaging");
 }
 
