@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E, published
 STEP_BYTES_PER_POINT = 16             # read u, u-, v^2dt^2; write u+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "acoustic_step_512cube_so8_traffic.json")
 # sources of the step kernel and its launch wrapper (the default tile at
-# 512^3, (8, 2, 64) with the ring and non-temporal flags, is recorded in the
-# traffic summary itself)
+# 512^3, 128 x 16 columns with z chunks of 128, the halo ring and
+# non-temporal hints, is recorded in the traffic summary itself)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2312_13094_amd", "csrc", f)
                for f in ("zmarch.h", "k_step_radius.hip")]
 
