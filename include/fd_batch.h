@@ -74,7 +74,7 @@ int fd_batch_gradient(fd_batch *b, const float *const *q_dev, const float *const
 
 /* Apply a tile and flags (see fd_set_tile, 128-wide tiles included) to the
  * batched step kernel; invalidates the captured graph.  The default is
- * (4, 4, 64) with flag 4 (non-temporal hints only): on the 16-shot
+ * (4, 4, 32) with flag 4 (non-temporal hints only): on the 16-shot
  * gradient the halo-ring variants measured 17-28 % slower. */
 int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int flags);
 

@@ -32,7 +32,7 @@ struct fd_batch {
     int64_t full[3] = {0, 0, 0};
     std::vector<ShotHost> sh;
     fd::BatchShot *table = nullptr;
-    fd::Tuning tune{4, 4, 64, fd::kTileNts};
+    fd::Tuning tune{4, 4, 32, fd::kTileNts};
     int total_blocks = 0;
     const float *vel_full = nullptr;
     unsigned *scratch = nullptr;
