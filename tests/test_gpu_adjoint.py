@@ -91,7 +91,9 @@ def test_adjoint_matches_oracle(shape, so, nbl, bc):
 
 @pytest.mark.parametrize("shape,so,nbl,bc,nt,k", [((48, 52), 4, 8, 0, 90, 7),
                                                 ((24, 28, 66), 8, 5, 0, 70, 16),
-                                                ((26, 24, 64), 8, 5, 1, 50, 50)])
+                                                ((26, 24, 64), 8, 5, 1, 50, 50),
+                                                ((20, 22, 70), 8, 0, 0, 60, 11),
+                                                ((40, 130), 4, 0, 1, 60, 9)])
 def test_gradient_matches_oracle(shape, so, nbl, bc, nt, k):
     """Checkpoint every k steps (k need not divide nt), recompute each segment
     into k+2 slots, imaging condition fused into the adjoint sweep; FP32

@@ -10,9 +10,9 @@ from gpu_helpers import rel_l2, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _small_problem():
+def _small_problem(nbl=6):
     return synth.cfg_fwi_batch(n=64, nshots=3, side_lo=4, side_hi=6, unit=8, nt=70, ckpt_every=13,
-                               so=8, nbl=6, sigma=5.0)
+                               so=8, nbl=nbl, sigma=5.0)
 
 
 def _oracle_gradient(c, vstart, vtrue):
@@ -32,10 +32,11 @@ def _oracle_gradient(c, vstart, vtrue):
     return full * (-2.0 / vs ** 3), traces
 
 
-def test_batch_gradient_matches_per_shot_oracle():
+@pytest.mark.parametrize("nbl", [6, 0], ids=["sponge", "no_sponge"])
+def test_batch_gradient_matches_per_shot_oracle(nbl):
     import torch
     from paper_2312_13094_amd import fd
-    c = _small_problem()
+    c = _small_problem(nbl)
     vtrue, vstart = c.true_velocity(), c.start_velocity()
     og, traces = _oracle_gradient(c, vstart, vtrue)
     b = fd.Batch(c.spacing, c.so, c.dt, c.vmax, c.nbl, c.shapes, c.origins, c.full_shape, c.nt,
