@@ -197,12 +197,12 @@ __global__ __launch_bounds__(64 * kTtiBy) void k_tti_grad_zm(
             const float ar = az * grz + ay * gry + ax * grx;
             if (ro[j]) {
                 const int64_t i = o + (int64_t)z * PZ + (int64_t)(yb + j) * PY + x;
-                w0[i] = gpz - az * ap;
-                w1[i] = gpy - ay * ap;
-                w2[i] = gpx - ax * ap;
-                s0[i] = az * ar;
-                s1[i] = ay * ar;
-                s2[i] = ax * ar;
+                __builtin_nontemporal_store(gpz - az * ap, w0 + i);
+                __builtin_nontemporal_store(gpy - ay * ap, w1 + i);
+                __builtin_nontemporal_store(gpx - ax * ap, w2 + i);
+                __builtin_nontemporal_store(az * ar, s0 + i);
+                __builtin_nontemporal_store(ay * ar, s1 + i);
+                __builtin_nontemporal_store(ax * ar, s2 + i);
             }
         }
     }
