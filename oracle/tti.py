@@ -137,7 +137,7 @@ def forward(g: Grid, v, eps, delta, theta, phi, src=None, q=None, rec=None, nt=0
         f = np.zeros(g.padded_shape)
         if ns:
             np.add.at(f.reshape(-1), snode.reshape(-1),
-                      (sw * (hinv * np.asarray(q)[n])[:, None]).reshape(-1))
+                      (sw * (hinv * np.asarray(q, dtype=np.float64)[n])[:, None]).reshape(-1))
         f = g.interior(f)
         pn = (2.0 * g.interior(p) - (1.0 - a) * g.interior(po) +
               c_pp * hxy + c_x * hz + c * f) / (1.0 + a)

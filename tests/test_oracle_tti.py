@@ -53,6 +53,75 @@ def test_isotropic_limit_any_tilt(so):
     np.testing.assert_allclose(hxy + hz, want, rtol=0, atol=1e-12 * np.abs(want).max())
 
 
+def _trilinear(coords, h, shape):
+    """(node (z, y, x) index triples, weights) of each point's cell, coded
+    here: base = floor(x / h) clamped to n - 2, weights the products of
+    (1 - f) and f per axis."""
+    out = []
+    for c in np.asarray(coords, dtype=np.float64).reshape(-1, 3):
+        base, frac = [], []
+        for x, hh, n in zip(c, h, shape):
+            b = min(int(math.floor(x / hh)), n - 2)
+            base.append(b)
+            frac.append(x / hh - b)
+        nodes = []
+        for bz in (0, 1):
+            for by in (0, 1):
+                for bx in (0, 1):
+                    wgt = ((frac[0] if bz else 1 - frac[0]) * (frac[1] if by else 1 - frac[1]) *
+                           (frac[2] if bx else 1 - frac[2]))
+                    nodes.append(((base[0] + bz, base[1] + by, base[2] + bx), wgt))
+        out.append(nodes)
+    return out
+
+
+def test_isotropic_limit_forward_with_source_damping_receivers():
+    """eps = delta = 0, p = r = 0 at the start, a source driving both fields:
+    p and r stay equal to a time loop coded here independently, an acoustic
+    forward whose Laplacian is the wide stencil sum_i d_i d_i (zero-extended
+    intermediate), with u+ = [2u - (1-a)u- + v^2 dt^2 (L u + f)]/(1 + a),
+    a = gamma dt / 2 from the acoustic damping profile, f the source spread
+    by trilinear weights times q[n] / (hz hy hx), and receivers that sample
+    p after each update.  A wrong source scale, damping factor or receiver
+    time alignment in the TTI forward breaks the match."""
+    shape, so, h, nbl, nt = (16, 15, 17), 8, (10.0, 9.0, 11.0), 4, 24
+    v, _, _, th, ph = _fields(shape, 11)
+    vmax = 3000.0
+    dt = 0.4 * 2.0 / (vmax * math.sqrt(T.stability_number(so) * sum(1 / x ** 2 for x in h)))
+    g = O.Grid(shape, h, so=so, dt=dt, nbl=nbl, vmax=vmax, bc=0)
+    src = np.array([[73.0, 61.5, 93.5]])
+    rec = np.array([[40.0, 30.0, 50.0], [101.0, 77.0, 130.0], [60.5, 100.0, 20.0]])
+    q = (synth.ricker(nt, dt, 40.0)[:, None] * 1e3)
+    zero = np.zeros(shape)
+    p, _, r, _, d = T.forward(g, v, zero, zero, th, ph, src, q, rec, nt)
+    # the loop coded here
+    r_ = g.r
+    gam = O.sponge_gamma(g)          # the acoustic damping profile (pinned separately)
+    a = 0.5 * dt * gam
+    v64 = np.asarray(v, dtype=np.float64)
+    cvv = v64 * v64 * dt * dt
+    snodes = _trilinear(src, h, shape)
+    rnodes = _trilinear(rec, h, shape)
+    u, um = g.zeros(), g.zeros()
+    dref = np.zeros((nt, len(rec)))
+    for n in range(nt):
+        lap = sum(_wide_second(u, r_, so, ax, h[ax], shape) for ax in range(3))
+        f = np.zeros(shape)
+        for nodes in snodes:
+            for idx, wgt in nodes:
+                f[idx] += wgt * q[n, 0] / (h[0] * h[1] * h[2])
+        un = (2 * g.interior(u) - (1 - a) * g.interior(um) + cvv * (lap + f)) / (1 + a)
+        um, u = u, g.pad(un)
+        for i, nodes in enumerate(rnodes):
+            dref[n, i] = sum(wgt * un[idx] for idx, wgt in nodes)
+    scale = np.abs(g.interior(u)).max()
+    assert scale > 0
+    np.testing.assert_allclose(g.interior(p), g.interior(u), rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(g.interior(r), g.interior(u), rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(d, dref, rtol=0, atol=1e-12 * np.abs(dref).max())
+    assert np.abs(dref).max() > 0
+
+
 def test_vertical_axis_is_vti():
     """theta = 0: H_z = d_z d_z and H_xy = d_x d_x + d_y d_y (any phi)."""
     shape, so, h = (12, 14, 13), 8, (10.0, 9.0, 11.0)
