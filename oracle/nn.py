@@ -135,18 +135,33 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, frozen=None):
     return p1, m1, v1
 
 
-class Net:
-    """conv(3->16) - GELU - conv(16->16) - GELU - conv(16->1), 3^3 kernels."""
+def _keep(a):
+    return a
 
-    def __init__(self, w1, b1, w2, b2, w3, b3):
+
+class Net:
+    """conv(3->16) - GELU - conv(16->16) - GELU - conv(16->1), 3^3 kernels.
+
+    ``store`` (default: none) is a rounding applied wherever a stored
+    activation or gradient is formed: the pre-activations z1, z2, the
+    activations GELU(z1), GELU(z2) (each evaluated on the rounded
+    pre-activation), the output gradient dL/dy and the back-propagated
+    gradients dL/dz2, dL/dz1.  With ``store=bf16_round`` the network keeps
+    exactly the BF16 tensors a BF16-storage implementation keeps; y, the loss
+    and the parameter gradients stay in float64.  Without it this is the
+    plain textbook network (pinned by finite differences)."""
+
+    def __init__(self, w1, b1, w2, b2, w3, b3, store=None):
         self.p = [np.asarray(a, dtype=np.float64) for a in (w1, b1, w2, b2, w3, b3)]
+        self.store = store or _keep
 
     def forward(self, x, keep=False):
         w1, b1, w2, b2, w3, b3 = self.p
-        z1 = conv3d(x, w1, b1)
-        a1 = gelu(z1)
-        z2 = conv3d(a1, w2, b2)
-        a2 = gelu(z2)
+        st = self.store
+        z1 = st(conv3d(x, w1, b1))
+        a1 = st(gelu(z1))
+        z2 = st(conv3d(a1, w2, b2))
+        a2 = st(gelu(z2))
         y = conv3d(a2, w3, b3)
         if keep:
             return y, (x, z1, a1, z2, a2)
@@ -159,12 +174,13 @@ class Net:
         y, (x, z1, a1, z2, a2) = self.forward(x, keep=True)
         n = y.size
         m = np.ones_like(y) if mask is None else np.broadcast_to(mask, y.shape)
-        gy = 2.0 * m * (y - target) / n
+        st = self.store
+        gy = st(2.0 * m * (y - target) / n)
         gw3, gb3 = conv3d_wgrad(a2, gy)
         ga2 = conv3d_dgrad(gy, w3)
-        gz2 = ga2 * gelu_grad(z2)
+        gz2 = st(ga2 * gelu_grad(z2))
         gw2, gb2 = conv3d_wgrad(a1, gz2)
         ga1 = conv3d_dgrad(gz2, w2)
-        gz1 = ga1 * gelu_grad(z1)
+        gz1 = st(ga1 * gelu_grad(z1))
         gw1, gb1 = conv3d_wgrad(x, gz1)
         return masked_mse(y, target, m), [gw1, gb1, gw2, gb2, gw3, gb3]

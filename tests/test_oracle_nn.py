@@ -84,6 +84,25 @@ def test_adam_first_step_is_signed_lr():
     np.testing.assert_allclose(v, 0.001 * g * g)
 
 
+def test_adam_two_steps_worked_by_hand():
+    """Kingma & Ba, Algorithm 1, worked by hand for p0 = 1, gradients 2 then
+    -1, lr 0.1, beta1 0.9, beta2 0.999, eps 0:
+      t=1: m = 0.2, v = 0.004, m^ = 2, v^ = 4, p = 1 - 0.1 * 2/2 = 0.9;
+      t=2: m = 0.18 - 0.1 = 0.08, v = 0.003996 + 0.001 = 0.004996,
+           m^ = 0.08/0.19 = 8/19, v^ = 0.004996/0.001999 = 4996/1999,
+           p = 0.9 - 0.1 * (8/19) / sqrt(4996/1999).
+    Swapping the betas, using the other moment's bias correction, or
+    correcting with the step index off by one each changes p2."""
+    p, m, v = N.adam_step(np.array([1.0]), np.array([2.0]), np.zeros(1), np.zeros(1), 1,
+                          lr=0.1, b1=0.9, b2=0.999, eps=0.0)
+    assert abs(p[0] - 0.9) < 1e-15 and abs(m[0] - 0.2) < 1e-15 and abs(v[0] - 0.004) < 1e-15
+    p, m, v = N.adam_step(p, np.array([-1.0]), m, v, 2, lr=0.1, b1=0.9, b2=0.999, eps=0.0)
+    assert abs(m[0] - 0.08) < 1e-15 and abs(v[0] - 0.004996) < 1e-15
+    want = 0.9 - 0.1 * (8.0 / 19.0) / math.sqrt(4996.0 / 1999.0)
+    assert abs(p[0] - want) < 1e-14, (p[0], want)
+    assert abs(want - 0.873366) < 1e-6
+
+
 def test_bf16_rounding():
     a = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -3.1415926, 65504.0, 1e-40],
                  dtype=np.float32)

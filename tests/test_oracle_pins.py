@@ -299,6 +299,78 @@ def test_sponge_profile_shape():
     np.testing.assert_allclose(gam[0, 0], gam[0, 15] + gam[15, 0], rtol=1e-14)
 
 
+def _damped_decay_rate(w, v, dt, h, om, gam, th0):
+    """Imaginary part of the wavenumber (1/m) of the discrete plane wave
+    exp(i(k z - om t)) that solves the damped leapfrog scheme exactly in a
+    homogeneous medium of damping rate gam: with lam = exp(-i om dt) and
+    a = gam dt / 2 the recurrence (1+a) lam^2 - (2 - (v dt/h)^2 s(kh)) lam
+    + (1-a) = 0 fixes the stencil symbol s(kh) = -(w0 + 2 sum w_k cos k kh),
+    solved for complex kh by Newton's method from the undamped root th0."""
+    lam = np.exp(-1j * om * dt)
+    a = 0.5 * gam * dt
+    want = (2.0 - (1.0 + a) * lam - (1.0 - a) / lam) / (v * dt / h) ** 2
+    th = th0 + 0j
+    for _ in range(60):
+        f = -(w[0] + 2 * sum(w[k] * np.cos(k * th) for k in range(1, len(w)))) - want
+        df = 2 * sum(w[k] * k * np.sin(k * th) for k in range(1, len(w)))
+        th = th - f / df
+    return abs(th.imag) / h
+
+
+def test_sponge_absorbs_as_designed():
+    """Physical check of the damping layer's strength.  The reading sizes
+    gamma_max so that the layer would return R = 1e-3 of a normally incident
+    wave in a PML; for the damping term m*gamma*u_t (which attenuates at
+    gamma/(2v) per metre, half a PML's rate) one crossing of both layers of
+    an axis therefore keeps about sqrt(R).  A narrowband plane pulse (12
+    points per wavelength, uniform in x) runs around a periodic z axis,
+    through the +z and then the -z layer; the ratio of its envelope peak at a
+    fixed receiver after the loop to the one before must match the WKB
+    prediction exp(-sum over the path's layer points of Im k(gamma_j) h)
+    built from the exact damped dispersion relation of the discrete scheme
+    (within 3 %).  A log10 for ln, the layer width nbl - 1 for nbl, or a
+    PML-rate constant would each move the ratio by 7 % or more."""
+    from scipy.signal import hilbert
+    so, h, v, nbl, R = 8, 10.0, 1500.0, 60, 1e-3
+    nz, nx = 2 * nbl + 150, 920              # x wide enough that diffraction from
+    w = O.d2_weights(so)                     # the x layers never reaches the receiver
+    S = -w[0] + 2 * sum(abs(x) for x in w[1:])
+    dt = 0.5 * 2 * h / (v * math.sqrt(2 * S))
+    lam = 12.0 * h
+    k0 = 2 * math.pi / lam
+    sig0 = -(w[0] + 2 * sum(w[k] * math.cos(k * k0 * h) for k in range(1, len(w))))
+    om = 2 * math.asin(math.sqrt((v * dt / h) ** 2 * sig0 / 4)) / dt
+    c = om / k0
+    g = O.Grid((nz, nx), (h, h), so=so, dt=dt, nbl=nbl, vmax=v, bc=1)
+    z = np.arange(nz) * h
+    zc, sz = (nbl + 60) * h, 1.5 * lam
+
+    def pulse(t):                            # one-way (+z) narrowband pulse
+        a = z - zc - c * t
+        return np.exp(-0.5 * (a / sz) ** 2) * np.cos(k0 * a)
+
+    u0 = g.pad(np.repeat(pulse(0.0)[:, None], nx, 1))
+    um = g.pad(np.repeat(pulse(-dt)[:, None], nx, 1))
+    zr = nbl + 100
+    nt = int(round(((zr - nbl - 60) * h + nz * h + 4 * sz) / c / dt))
+    _, _, d, _ = O.forward(g, np.full((nz, nx), v), None, None,
+                           np.array([[zr * h, (nx // 2) * h]]), nt, u0=u0, um=um)
+    env = np.abs(hilbert(d[:, 0]))
+    t = (np.arange(nt) + 1) * dt
+    t_inc = (zr - nbl - 60) * h / c
+    t_ret = t_inc + nz * h / c
+    win = 0.25 * nz * h / c
+    a_inc = env[np.abs(t - t_inc) < win].max()
+    a_ret = env[np.abs(t - t_ret) < win].max()
+    gmax = 3 * v * math.log(1 / R) / (2 * nbl * h)
+    expo = 2 * sum(_damped_decay_rate(w, v, dt, h, om, gmax * (j / nbl) ** 2, k0 * h) * h
+                   for j in range(1, nbl + 1))
+    want = math.exp(-expo)
+    assert abs(a_inc - 1.0) < 0.01
+    assert abs(a_ret / a_inc - want) <= 0.03 * want, (a_ret / a_inc, want)
+    assert 0.5 * math.sqrt(R) < want < 1.5 * math.sqrt(R)
+
+
 # --------------------------------------------------------------------------
 # sparse interpolation: exact on affine fields, adjoint pair
 # --------------------------------------------------------------------------
