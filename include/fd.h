@@ -187,7 +187,10 @@ int fd_set_exchange_mode(fd_grid *g, int mode);
  * a miss.  Writes the chosen tile to out4 (may be NULL) and the best
  * measured milliseconds per launch to ms_out (may be NULL; 0 on a cache
  * hit).  Allocates two scratch fields for the search (setup call);
- * synchronises `stream`.  2-D grids keep the one-thread-per-point kernel. */
+ * synchronises `stream`.  2-D grids keep the one-thread-per-point kernel.
+ * Errors: the first failing candidate (launch or event error) ends the
+ * search and its code is returned; the handle then keeps its previous tile
+ * and nothing is written to the cache. */
 int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, void *stream);
 
 /* Multilinear weights of sparse points (paper, "Sparse data" paragraph:

@@ -43,15 +43,28 @@ def _compile(job) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _headers_mtime() -> float:
+    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+    return max((os.path.getmtime(h) for h in hs), default=0.0)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only objects older than their
+    source or any header) and link libfd.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = [j for s in srcs for j in _jobs(s)]
+    every = [j[2] for j in jobs]
+    if incremental:
+        hdr = _headers_mtime()
+        jobs = [j for j in jobs if not os.path.exists(j[2]) or
+                os.path.getmtime(j[2]) < max(os.path.getmtime(j[0]), hdr)]
     # big objects first so the pool stays busy
     jobs.sort(key=lambda j: 0 if j[1] else 1)
-    workers = max(1, min(16, os.cpu_count() or 1, len(jobs)))
+    workers = max(1, min(16, os.cpu_count() or 1, max(len(jobs), 1)))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(_compile, jobs))
+        list(ex.map(_compile, jobs))
+    objs = every
     for stale in glob.glob(os.path.join(BUILD, "*.o")):
         if stale not in objs:
             os.remove(stale)
@@ -64,5 +77,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

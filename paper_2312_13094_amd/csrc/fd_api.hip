@@ -901,46 +901,57 @@ int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, v
         (void)hipFree(a);
         return set_error(FD_ENOMEM, "fd_autotune: scratch allocation failed");
     }
-    (void)hipMemsetAsync(a, 0, g->L.field_bytes, s);
-    (void)hipMemsetAsync(b, 0, g->L.field_bytes, s);
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = FD_OK;
+    if (hipMemsetAsync(a, 0, g->L.field_bytes, s) != hipSuccess ||
+        hipMemsetAsync(b, 0, g->L.field_bytes, s) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = set_error(FD_EDEVICE, "fd_autotune: scratch set-up failed");
     const Tuning saved = g->tune;
     const int cand[7][2] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {2, 8}};
     const int nzbs[5] = {8, 16, 32, 64, 128};
     double best_ms = 1e30;
-    int rc = FD_OK;
-    for (const auto &c : cand)
-        for (int nzb : nzbs)
-            for (int xcd = 0; xcd < 32; ++xcd) {
+    // one timed candidate: a warm-up launch, then three timed launches; the
+    // first error of any candidate ends the whole sweep
+    auto time_one = [&](float *ms) -> int {
+        int r = launch_step(g, a, b, b, s);
+        if (r) return r;
+        if (hipEventRecord(e0, s) != hipSuccess)
+            return set_error(FD_EDEVICE, "fd_autotune: hipEventRecord failed");
+        for (int i = 0; i < 3; ++i)
+            if ((r = launch_step(g, i % 2 ? b : a, i % 2 ? a : b, i % 2 ? a : b, s))) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return set_error(FD_EDEVICE, "fd_autotune: event timing failed");
+        return FD_OK;
+    };
+    for (int ci = 0; ci < 7 && rc == FD_OK; ++ci)
+        for (int zi = 0; zi < 5 && rc == FD_OK; ++zi)
+            for (int xcd = 0; xcd < 32 && rc == FD_OK; ++xcd) {
+                const int *c = cand[ci];
                 const bool wide_ok = (c[0] == 8 && c[1] == 2) ||
                                      (c[0] == 4 && (c[1] == 2 || c[1] == 4));
                 if ((xcd & kTileWide) && !wide_ok) continue;
-                g->tune = Tuning{c[0], c[1], nzb, xcd};
-                if ((rc = launch_step(g, a, b, b, s))) break;   // warm-up
-                (void)hipEventRecord(e0, s);
-                for (int i = 0; i < 3; ++i)
-                    if ((rc = launch_step(g, i % 2 ? b : a, i % 2 ? a : b, i % 2 ? a : b, s))) break;
-                (void)hipEventRecord(e1, s);
-                if (rc || hipEventSynchronize(e1) != hipSuccess) break;
+                g->tune = Tuning{c[0], c[1], nzbs[zi], xcd};
                 float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
+                if ((rc = time_one(&ms))) break;
                 if (ms / 3.0 < best_ms) {
                     best_ms = ms / 3.0;
                     best[0] = c[0];
                     best[1] = c[1];
-                    best[2] = nzb;
+                    best[2] = nzbs[zi];
                     best[3] = xcd;
                 }
             }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    // the scratch fields may still be in use by launches of a failed sweep
+    (void)hipStreamSynchronize(s);
     (void)hipFree(a);
     (void)hipFree(b);
     g->tune = saved;
-    if (rc) return rc;
-    fd_set_tile(g, best[0], best[1], best[2], best[3]);
+    if (rc) return rc;   // nothing cached, the handle keeps its tile
+    if ((rc = fd_set_tile(g, best[0], best[1], best[2], best[3]))) return rc;
     if (cache_path) tune_store(cache_path, key, best);
     if (out4) std::memcpy(out4, best, sizeof best);
     if (ms_out) *ms_out = best_ms;

@@ -257,6 +257,25 @@ def test_headline_512_one_step_vs_oracle():
     assert rel_l2(gd, od) <= 1e-5
 
 
+@pytest.mark.slow
+def test_headline_512_full_run_vs_oracle():
+    """The headline workload exactly as bench.py times it: 512^3, so 8,
+    layered velocity, 40-point sponge, 15 Hz Ricker, 512 receivers, loopback
+    exchange of the six faces every step, 500 steps, default tile.  The final
+    field, the previous field and all traces within 1e-4 relative L2 of the
+    FP64 oracle (about 90 s of oracle time on 16 cores)."""
+    c = synth.cfg_3d_layered()
+    v = c.velocity()
+    args = dict(shape=c.shape, spacing=c.spacing, so=c.so, dt=c.dt, vmax=c.vmax, v=v,
+                nt=c.nt, nbl=c.nbl, boundary=c.boundary, src=c.src, q=c.q, rec=c.rec)
+    gu, gum, gd = run_gpu_forward(**args)
+    ou, oum, od = run_oracle_forward(**args)
+    eu, eum, ed = rel_l2(gu, ou), rel_l2(gum, oum), rel_l2(gd, od)
+    print("512^3 x 500 steps: field %.2e previous %.2e traces %.2e" % (eu, eum, ed))
+    assert np.abs(od).max() > 0
+    assert eu <= 1e-4 and eum <= 1e-4 and ed <= 1e-4
+
+
 def _symbol(w, theta):
     return w[0] + 2 * sum(w[k] * math.cos(k * theta) for k in range(1, len(w)))
 
@@ -471,3 +490,52 @@ def test_zero_steps_and_empty_sparse_sets():
     torch.cuda.synchronize()
     assert torch.equal(a, c) and torch.equal(b, e)
     g.close()
+
+
+def test_autotune_json_cache(tmp_path):
+    """The autotuner's JSON cache: a miss times the candidates and stores the
+    winner under "arch|so|nz|ny|nx"; a second handle of the same shape gets
+    the same tile from the cache without timing (ms 0) and then runs
+    bit-identically to a handle given that tile explicitly; another shape is
+    a miss again and both entries stay in the file."""
+    import json
+    FD = _fd()
+    rng = np.random.default_rng(12)
+    shape, so, h, vmax = (40, 36, 70), 8, 10.0, 3000.0
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, 3, h, vmax)
+    cache = str(tmp_path / "tiles.json")
+
+    def tuned(shp, vv):
+        g = FD.Grid(shp, (h,) * 3, so, dt, vmax, nbl=4)
+        g.set_model(to_dev(vv))
+        return g, g.autotune(cache)
+
+    g1, (t1, ms1) = tuned(shape, v)
+    assert ms1 > 0.0
+    with open(cache) as f:
+        entries = json.load(f)
+    assert len(entries) == 1
+    key, val = next(iter(entries.items()))
+    assert key.endswith("|%d|%d|%d|%d" % ((so,) + shape)) and tuple(val) == tuple(t1)
+    g1.close()
+    g2, (t2, ms2) = tuned(shape, v)
+    assert ms2 == 0.0 and tuple(t2) == tuple(t1)
+    g2.close()
+    u0 = synth.smooth_state(shape, 8, 3.0)
+    a, _, _ = run_gpu_forward(shape, (h,) * 3, so, dt, vmax, v, 6, nbl=4, u0=u0, tile=tuple(t1))
+    import torch
+    g3, _ = tuned(shape, v)
+    x, y = g3.field(), g3.field()
+    g3.domain(x).copy_(to_dev(u0))
+    g3.forward([x, y], nt=6)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(g3.domain(x).double().cpu().numpy(), a)
+    g3.close()
+    shape2 = (24, 20, 70)
+    v2 = synth.minmax(synth.smooth_noise(shape2, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    g4, (_, ms4) = tuned(shape2, v2)
+    assert ms4 > 0.0
+    g4.close()
+    with open(cache) as f:
+        assert len(json.load(f)) == 2

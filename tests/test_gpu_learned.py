@@ -34,22 +34,22 @@ def test_training_lowers_one_step_error(trained):
 
 
 def test_correction_beats_plain_coarse_on_held_out_models(trained):
+    """Every held-out model: the corrected run completes without the guard
+    falling back to the fine solve, and its trace error against the fine
+    solve is below the plain coarse run's."""
     from paper_2312_13094_amd import learned as LC
     lc, cfg, _, _ = trained
-    gains, fell_back = [], 0
+    rows = []
     for seed in cfg.test_seeds:
         lc.set_model(cfg.velocity(seed))
         ref, _, _ = lc.fine_solve()
         plain, _ = lc.coarse_solve()
         res = lc.learned_solve()
-        if res.fallback:          # the guard fired: the fine solve was returned
-            np.testing.assert_array_equal(res.traces, ref)
-            fell_back += 1
-            continue
-        gains.append((LC.trace_error(plain, ref), LC.trace_error(res.traces, ref)))
-    assert gains, "every held-out run fell back to the fine solve"
-    for e_plain, e_learned in gains:
-        assert e_learned < e_plain, (gains, fell_back)
+        rows.append((seed, bool(res.fallback), LC.trace_error(plain, ref),
+                     LC.trace_error(res.traces, ref)))
+    for seed, fell_back, e_plain, e_learned in rows:
+        assert not fell_back, rows
+        assert e_learned < e_plain, rows
 
 
 def test_correction_is_zero_on_zero_field_and_inside_source_box(trained):
