@@ -112,6 +112,22 @@ int nn_dgrad_gelu(int layer, int nz, int ny, int nx, const void *gin_dev,
 int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
              void *workspace_dev, float *grads_dev, int accumulate, void *stream);
 
+/* nn_wgrad without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving or training loops, harnesses that forbid hipMalloc.  Same
+ * kernels, arguments and results as nn_wgrad (bit-identical), but the
+ * per-block partial sums live in a static device array of the library,
+ * 512 partials x 6,928 floats = 14.2 MB per GPU, taken when the library's
+ * device code is loaded and held until the process ends.  Runs on the
+ * current device (its scratch address is looked up once per device on the
+ * first call).  FD_EINVAL if a launch would need more partial sums than the
+ * array holds, or for bad arguments; nothing is allocated, no memset is
+ * issued (every partial that is read is written first in the same call).
+ * Calls that overlap on one GPU (different streams) share the array and
+ * race: serialise them. */
+int nn_wgrad_noalloc(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
+                     float *grads_dev, int accumulate, void *stream);
+
 /* Adam (t is the 1-based step) on every weight, and on the biases too if
  * train_bias is non-zero; otherwise biases and their moments are left as
  * they are (a bias-free network keeps N(0) = 0). */

@@ -19,6 +19,8 @@
 // are reduced in a fixed order by a second kernel (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/fdnn.h"
 #include "fd_internal.h"
 
@@ -585,11 +587,71 @@ __global__ __launch_bounds__(256) void k_adam(float *p, const float *__restrict_
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Scratch of nn_wgrad_noalloc: the per-block partial sums of the weight
+// gradient, room for every persistent block (WG_BLOCKS x WG_PART floats,
+// 14.2 MB).  One copy per GPU, in the code object's static device data, held
+// until the process ends.  Host code never passes this name to a kernel: it
+// is a host-side stand-in, the device address comes from
+// hipGetSymbolAddress (wgrad_scratch below).
+constexpr int64_t kWgScratchFloats = (int64_t)WG_BLOCKS * WG_PART;
+static __device__ __align__(256) float scratch[kWgScratchFloats];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static int wgrad_scratch(float **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return set_error(FD_EDEVICE, "nn_wgrad_noalloc: no usable current device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(FD_EDEVICE, std::string("nn_wgrad_noalloc: hipGetSymbolAddress "
+                                                     "failed: ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return FD_OK;
+}
+
 }  // namespace nn
 }  // namespace fd
 
 using namespace fd;
 using namespace fd::nn;
+
+// Weight gradient of one layer: per-block partial sums in `part` (room for
+// min(WG_BLOCKS, tiles) partials), then the ordered reduction.
+static int wgrad_run(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
+                     float *part, float *grads_dev, int accumulate, hipStream_t s)
+{
+    const uint16_t *x = (const uint16_t *)x_dev, *g = (const uint16_t *)g_dev;
+    const int ntiles = ((nx + TXW - 1) / TXW) * ((ny + TYW - 1) / TYW) * ((nz + TZW - 1) / TZW);
+    const int nbk = std::min(WG_BLOCKS, ntiles);
+    int cin_real, cout_real, woff, boff;
+    if (layer == 1) {
+        hipLaunchKernelGGL((k_wgrad<8, 16>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
+        cin_real = 3; cout_real = 16; woff = kW1; boff = kB1;
+    } else if (layer == 2) {
+        hipLaunchKernelGGL((k_wgrad<16, 16>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
+        cin_real = 16; cout_real = 16; woff = kW2; boff = kB2;
+    } else {
+        hipLaunchKernelGGL((k_wgrad<16, 8>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
+        cin_real = 16; cout_real = 1; woff = kW3; boff = kB3;
+    }
+    int rc = check_launch("nn wgrad");
+    if (rc) return rc;
+    const int nout = cout_real * cin_real * 27 + cout_real;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 255) / 256), dim3(256), 0, s, part, nbk,
+                       cin_real, cout_real, grads_dev + woff, grads_dev + boff, accumulate);
+    return check_launch("nn wgrad reduce");
+}
 
 extern "C" {
 
@@ -752,28 +814,31 @@ int nn_wgrad(int layer, int nz, int ny, int nx, const void *x_dev, const void *g
     if (bad_shape(nz, ny, nx) || !x_dev || !g_dev || !workspace_dev || !grads_dev ||
         layer < 1 || layer > 3)
         return set_error(FD_EINVAL, "nn_wgrad: bad argument");
-    hipStream_t s = (hipStream_t)stream;
-    float *part = (float *)workspace_dev;
-    const uint16_t *x = (const uint16_t *)x_dev, *g = (const uint16_t *)g_dev;
-    const int ntiles = ((nx + TXW - 1) / TXW) * ((ny + TYW - 1) / TYW) * ((nz + TZW - 1) / TZW);
-    const int nbk = std::min(WG_BLOCKS, ntiles);
-    int cin_real, cout_real, woff, boff;
-    if (layer == 1) {
-        hipLaunchKernelGGL((k_wgrad<8, 16>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
-        cin_real = 3; cout_real = 16; woff = kW1; boff = kB1;
-    } else if (layer == 2) {
-        hipLaunchKernelGGL((k_wgrad<16, 16>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
-        cin_real = 16; cout_real = 16; woff = kW2; boff = kB2;
-    } else {
-        hipLaunchKernelGGL((k_wgrad<16, 8>), dim3(nbk), dim3(256), 0, s, nz, ny, nx, x, g, part);
-        cin_real = 16; cout_real = 1; woff = kW3; boff = kB3;
-    }
-    int rc = check_launch("nn wgrad");
+    return wgrad_run(layer, nz, ny, nx, x_dev, g_dev, (float *)workspace_dev, grads_dev,
+                     accumulate, (hipStream_t)stream);
+}
+
+int nn_wgrad_noalloc(int layer, int nz, int ny, int nx, const void *x_dev, const void *g_dev,
+                     float *grads_dev, int accumulate, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !x_dev || !g_dev || !grads_dev || layer < 1 || layer > 3)
+        return set_error(FD_EINVAL, "nn_wgrad_noalloc: bad argument");
+    // tiles of the volume (the persistent launch takes min(WG_BLOCKS, tiles)
+    // blocks, one partial sum each)
+    const int64_t ntiles = (int64_t)((nx + TXW - 1) / TXW) * ((ny + TYW - 1) / TYW) *
+                           ((nz + TZW - 1) / TZW);
+    if (ntiles > INT32_MAX)
+        return set_error(FD_EINVAL, "nn_wgrad_noalloc: volume has more tiles than a launch indexes");
+    const int64_t need = std::min<int64_t>(WG_BLOCKS, ntiles) * WG_PART;
+    if (need > kWgScratchFloats)
+        return set_error(FD_EINVAL, "nn_wgrad_noalloc: " + std::to_string(need) +
+                                        " partial-sum floats exceed the static scratch of " +
+                                        std::to_string(kWgScratchFloats));
+    float *part = nullptr;
+    const int rc = wgrad_scratch(&part);
     if (rc) return rc;
-    const int nout = cout_real * cin_real * 27 + cout_real;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 255) / 256), dim3(256), 0, s, part, nbk,
-                       cin_real, cout_real, grads_dev + woff, grads_dev + boff, accumulate);
-    return check_launch("nn wgrad reduce");
+    return wgrad_run(layer, nz, ny, nx, x_dev, g_dev, part, grads_dev, accumulate,
+                     (hipStream_t)stream);
 }
 
 int nn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int t, float lr,

@@ -65,6 +65,7 @@ def lib():
         L.nn_mse.argtypes = [i, i, i, vp, vp, vp, f, bp, vp, vp, vp]
         L.nn_dgrad_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp]
         L.nn_wgrad.argtypes = [i, i, i, i, vp, vp, vp, vp, i, vp]
+        L.nn_wgrad_noalloc.argtypes = [i, i, i, i, vp, vp, vp, i, vp]
         L.nn_adam.argtypes = [vp, vp, vp, vp, i, f, f, f, f, i, vp]
         _bound = True
     return L
