@@ -78,6 +78,27 @@ int fd_batch_gradient(fd_batch *b, const float *const *q_dev, const float *const
  * gradient the halo-ring variants measured 17-28 % slower. */
 int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int flags);
 
+/* Autotuner of the batched step (the row's "tile shapes and z-blocking
+ * picked by the project's own autotuner"; the paper's problem-setup section
+ * tunes loop blocking per run): a timed search over tile shapes (by, ry),
+ * z chunks of 16, 32 or 64 planes and flag sets (none, non-temporal hints,
+ * halo ring, both, 128-wide with both, XCD remap with hints), each candidate
+ * one launch of the batched step over every shot's aperture on the batch's
+ * own forward fields (which the next gradient zeroes); the fastest is
+ * applied with fd_batch_set_tile (so the next gradient captures its graph
+ * with it).  With cache_path non-NULL the choice is first looked up in that
+ * JSON file under "arch|batch|so|nshots|<hash of the aperture shapes>" and
+ * stored on a miss.  out4 (may be NULL) receives (by, ry, nzb, flags);
+ * ms_out (may be NULL) the best milliseconds per launch (0 on a cache hit).
+ * Needs a loaded model; synchronises `stream`; allocates nothing.  The
+ * first error of any candidate ends the search: its code is returned, the
+ * batch keeps its tile and nothing is cached. */
+int fd_batch_autotune(fd_batch *b, const char *cache_path, int *out4, double *ms_out,
+                      void *stream);
+
+/* The batched step's current tile (by, ry, nzb, flags) into out4. */
+int fd_batch_get_tile(const fd_batch *b, int *out4);
+
 #ifdef __cplusplus
 }
 #endif

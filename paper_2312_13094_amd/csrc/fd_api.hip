@@ -191,7 +191,7 @@ static void free_grid(fd_grid *g)
     (void)hipFree(g->vdt2);
     for (float *&p : g->tti) (void)hipFree(p);
     for (float *&p : g->el) (void)hipFree(p);
-    for (float *&p : g->facebuf) (void)hipFree(p);
+    (void)hipFree(g->facebase);
     for (float *&p : g->inter) (void)hipFree(p);
     (void)hipFree(g->scratch_u32);
     delete g;
@@ -214,17 +214,26 @@ static int validate_sparse(const fd_grid *g, const fd_sparse *sp, const void *va
     return FD_OK;
 }
 
-// step kernel launch, bracketed by timing events while profiling is armed
+// Step kernel launch, timed while profiling is armed: a z-march launch
+// carries the pair as its own start/stop events (the kernel's duration); the
+// other launch paths (one-thread-per-point kernel, full exchange mode's
+// several kernels) are bracketed by event records on the stream.
 static int timed_step(fd_grid *g, float *u, const float *um, float *up, hipStream_t s)
 {
     const bool t = g->prof_used * 2 + 1 < (int)g->prof_ev.size();
-    if (t && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
+    const bool own = t && g->xmode != FD_XCHG_FULL && g->ndim == 3 && g->tune.by > 0;
+    if (t && !own && hipEventRecord(g->prof_ev[2 * g->prof_used], s) != hipSuccess)
         return set_error(FD_EDEVICE, "hipEventRecord failed");
+    if (own) {
+        g->launch_ev[0] = g->prof_ev[2 * g->prof_used];
+        g->launch_ev[1] = g->prof_ev[2 * g->prof_used + 1];
+    }
     int rc = g->xmode == FD_XCHG_FULL ? launch_step_full(g, u, um, up, s)
                                       : launch_step(g, u, um, up, s);
+    g->launch_ev[0] = g->launch_ev[1] = nullptr;
     if (rc) return rc;
     if (t) {
-        if (hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
+        if (!own && hipEventRecord(g->prof_ev[2 * g->prof_used + 1], s) != hipSuccess)
             return set_error(FD_EDEVICE, "hipEventRecord failed");
         ++g->prof_used;
     }
@@ -372,12 +381,18 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
             }
     }
     if (d.boundary == FD_BC_LOOPBACK) {
+        // the six face buffers back to back in one allocation, in face order
+        int64_t tot = 0;
+        for (int f = 0; f < 6; ++f) tot += fd_halo_face_elems(g, f);
+        if (hipMalloc(&g->facebase, tot * sizeof(float)) != hipSuccess) {
+            free_grid(g);
+            return set_error(FD_ENOMEM, "face buffer allocation failed");
+        }
+        int64_t off = 0;
         for (int f = 0; f < 6; ++f) {
             const int64_t e = fd_halo_face_elems(g, f);
-            if (e > 0 && hipMalloc(&g->facebuf[f], e * sizeof(float)) != hipSuccess) {
-                free_grid(g);
-                return set_error(FD_ENOMEM, "face buffer allocation failed");
-            }
+            g->facebuf[f] = e > 0 ? g->facebase + off : nullptr;
+            off += e;
         }
     }
     *out = g;
@@ -681,21 +696,34 @@ int fd_forward(fd_grid *g, float *const *state_dev, const fd_sparse *src, const 
         return forward_elastic(g, state_dev, inj, smp, q_dev, d_dev, nt, s);
     }
     float *cur = state_dev[0], *prev = state_dev[1];
+    auto checkpoint = [&](const int n) -> int {
+        if (!ckpt_dev || n % ckpt_every) return FD_OK;
+        float *c0 = ckpt_dev[2 * (n / ckpt_every)], *c1 = ckpt_dev[2 * (n / ckpt_every) + 1];
+        if (!c0 || !c1) return set_error(FD_EINVAL, "fd_forward: null checkpoint buffer");
+        int r = launch_copy(c0, cur, g->L.field_elems, s);
+        return r ? r : launch_copy(c1, prev, g->L.field_elems, s);
+    };
+    // Per time step: the halo exchange and the step, then one sparse launch
+    // that injects the sources into the new level and samples the receivers
+    // of the previous update from the level before it (a finished field the
+    // step only read), so neither half waits for the other.  The receivers
+    // of the last update are sampled after the loop.
+    SparseArgs none{0, nullptr, nullptr, nullptr, nullptr, 1.0f};
     for (int n = 0; n < nt; ++n) {
-        if (ckpt_dev && n % ckpt_every == 0) {
-            float *c0 = ckpt_dev[2 * (n / ckpt_every)], *c1 = ckpt_dev[2 * (n / ckpt_every) + 1];
-            if (!c0 || !c1) return set_error(FD_EINVAL, "fd_forward: null checkpoint buffer");
-            if ((rc = launch_copy(c0, cur, g->L.field_elems, s)) ||
-                (rc = launch_copy(c1, prev, g->L.field_elems, s)))
-                return rc;
-        }
+        if ((rc = checkpoint(n))) return rc;
         if ((rc = exchange_and_step(g, cur, prev, prev, s))) return rc;
         inj.vals = inj.n ? q_dev + (int64_t)n * inj.n : nullptr;
-        smp.out = smp.n ? d_dev + (int64_t)n * smp.n : nullptr;
-        if ((rc = launch_sparse(g, prev, inj, smp, s))) return rc;
+        SparseArgs prevsmp = smp;
+        prevsmp.n = n > 0 ? smp.n : 0;
+        prevsmp.out = prevsmp.n ? d_dev + (int64_t)(n - 1) * smp.n : nullptr;
+        if ((rc = launch_sparse_split(g, prev, inj, cur, prevsmp, s))) return rc;
         float *t = cur;
         cur = prev;
         prev = t;
+    }
+    if (nt > 0 && smp.n) {
+        smp.out = d_dev + (int64_t)(nt - 1) * smp.n;
+        if ((rc = launch_sparse(g, cur, none, smp, s))) return rc;
     }
     if (nt % 2) return launch_swap(state_dev[0], state_dev[1], g->L.field_elems, s);
     return FD_OK;
@@ -819,23 +847,33 @@ int fd_gradient_to_velocity(const fd_grid *g, const float *grad_m_dev, float *gr
     return launch_grad_to_vel(g, grad_m_dev, grad_v_dev, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
 // -- autotuner ---------------------------------------------------------------
 
-static std::string tune_key(const fd_grid *g)
+namespace fd {
+
+std::string device_arch(int device)
 {
     hipDeviceProp_t prop{};
     std::string arch = "gpu";
-    if (hipGetDeviceProperties(&prop, g->d.device) == hipSuccess) {
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         arch = prop.gcnArchName;
         const size_t c = arch.find(':');
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
-    return arch + "|" + std::to_string(g->d.space_order) + "|" + std::to_string(g->n[0]) + "|" +
-           std::to_string(g->n[1]) + "|" + std::to_string(g->n[2]);
+    return arch;
+}
+
+static std::string tune_key(const fd_grid *g)
+{
+    return device_arch(g->d.device) + "|" + std::to_string(g->d.space_order) + "|" +
+           std::to_string(g->n[0]) + "|" + std::to_string(g->n[1]) + "|" +
+           std::to_string(g->n[2]);
 }
 
 // read "key": [a, b, c, d] from a flat JSON object written by tune_store
-static bool tune_lookup(const char *path, const std::string &key, int t[4])
+bool tune_lookup(const char *path, const std::string &key, int t[4])
 {
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
@@ -851,7 +889,7 @@ static bool tune_lookup(const char *path, const std::string &key, int t[4])
                        &t[2], &t[3]) == 4;
 }
 
-static void tune_store(const char *path, const std::string &key, const int t[4])
+void tune_store(const char *path, const std::string &key, const int t[4])
 {
     std::string txt;
     if (FILE *f = std::fopen(path, "r")) {
@@ -876,6 +914,10 @@ static void tune_store(const char *path, const std::string &key, const int t[4])
         std::rename(tmp.c_str(), path);
     }
 }
+
+}  // namespace fd
+
+extern "C" {
 
 int fd_autotune(fd_grid *g, const char *cache_path, int *out4, double *ms_out, void *stream)
 {

@@ -3,6 +3,7 @@
 // a hipGraph (forward with checkpoints, per-segment recomputation, adjoint
 // with the fused imaging condition, ordered reduction into the full model).
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -278,6 +279,109 @@ int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int xcd)
     drop_graph(b);
     b->tune = Tuning{by, ry, nzb, xcd};
     layout_blocks(b);
+    return FD_OK;
+}
+
+int fd_batch_autotune(fd_batch *b, const char *cache_path, int *out4, double *ms_out,
+                      void *stream)
+{
+    if (!b) return set_error(FD_EINVAL, "fd_batch_autotune: null handle");
+    if (!b->model_loaded) return set_error(FD_EINVAL, "fd_batch_autotune: load a model first");
+    DeviceGuard dg(b->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    // key: architecture, space order and the ordered list of aperture shapes
+    // (FNV-1a over their extents)
+    uint64_t hsh = 1469598103934665603ull;
+    for (const ShotHost &sh : b->sh)
+        for (int a = 0; a < 3; ++a) {
+            hsh ^= (uint64_t)sh.n[a];
+            hsh *= 1099511628211ull;
+        }
+    char hx[24];
+    std::snprintf(hx, sizeof hx, "%016llx", (unsigned long long)hsh);
+    const std::string key = device_arch(b->d.device) + "|batch|" +
+                            std::to_string(b->d.space_order) + "|" + std::to_string(b->nshots) +
+                            "|" + hx;
+    int best[4] = {b->tune.by, b->tune.ry, b->tune.nzb, b->tune.flags};
+    if (cache_path && tune_lookup(cache_path, key, best) &&
+        fd_batch_set_tile(b, best[0], best[1], best[2], best[3]) == FD_OK) {
+        if (out4) std::memcpy(out4, best, sizeof best);
+        if (ms_out) *ms_out = 0.0;
+        return FD_OK;
+    }
+    // timed search over tiles, z chunks and flag sets on the batch's own
+    // forward fields (the gradient zeroes them before use); every candidate
+    // is one launch of the batched step over all shots
+    if (hipStreamSynchronize(s) != hipSuccess) return set_error(FD_EDEVICE, "sync failed");
+    drop_graph(b);
+    const Tuning saved = b->tune;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = FD_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = set_error(FD_EDEVICE, "fd_batch_autotune: event creation failed");
+    const int cand[7][2] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {2, 8}};
+    const int nzbs[3] = {16, 32, 64};
+    const int flagsets[6] = {0, kTileNts, kTileRing, kTileRing | kTileNts,
+                             kTileWide | kTileRing | kTileNts, kTileXcd | kTileNts};
+    double best_ms = 1e30;
+    auto time_one = [&](float *ms) -> int {
+        layout_blocks(b);
+        int r = upload_table(b, nullptr, nullptr, nullptr);
+        if (r) return r;
+        if ((r = launch_batch_step(b->table, b->nshots, b->total_blocks, b->r, b->tune, kFA, kFB,
+                                   kFB, s)))
+            return r;
+        if (hipEventRecord(e0, s) != hipSuccess)
+            return set_error(FD_EDEVICE, "fd_batch_autotune: hipEventRecord failed");
+        for (int i = 0; i < 3; ++i)
+            if ((r = launch_batch_step(b->table, b->nshots, b->total_blocks, b->r, b->tune,
+                                       i % 2 ? kFB : kFA, i % 2 ? kFA : kFB, i % 2 ? kFA : kFB,
+                                       s)))
+                return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return set_error(FD_EDEVICE, "fd_batch_autotune: event timing failed");
+        return FD_OK;
+    };
+    for (int ci = 0; ci < 7 && rc == FD_OK; ++ci)
+        for (int zi = 0; zi < 3 && rc == FD_OK; ++zi)
+            for (int fi = 0; fi < 6 && rc == FD_OK; ++fi) {
+                const int *c = cand[ci];
+                const int fl = flagsets[fi];
+                const bool wide_ok = (c[0] == 8 && c[1] == 2) ||
+                                     (c[0] == 4 && (c[1] == 2 || c[1] == 4));
+                if ((fl & kTileWide) && !wide_ok) continue;
+                b->tune = Tuning{c[0], c[1], nzbs[zi], fl};
+                float ms = 0.0f;
+                if ((rc = time_one(&ms))) break;
+                if (ms / 3.0 < best_ms) {
+                    best_ms = ms / 3.0;
+                    best[0] = c[0];
+                    best[1] = c[1];
+                    best[2] = nzbs[zi];
+                    best[3] = fl;
+                }
+            }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    b->tune = saved;
+    layout_blocks(b);
+    if (rc) return rc;   // nothing cached, the batch keeps its tile
+    if ((rc = fd_batch_set_tile(b, best[0], best[1], best[2], best[3]))) return rc;
+    if (cache_path) tune_store(cache_path, key, best);
+    if (out4) std::memcpy(out4, best, sizeof best);
+    if (ms_out) *ms_out = best_ms;
+    return FD_OK;
+}
+
+int fd_batch_get_tile(const fd_batch *b, int *out4)
+{
+    if (!b || !out4) return set_error(FD_EINVAL, "fd_batch_get_tile: bad argument");
+    out4[0] = b->tune.by;
+    out4[1] = b->tune.ry;
+    out4[2] = b->tune.nzb;
+    out4[3] = b->tune.flags;
     return FD_OK;
 }
 

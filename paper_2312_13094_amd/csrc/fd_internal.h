@@ -158,6 +158,7 @@ struct SparseArgs {
     float scale;
 };
 
+
 }  // namespace fd
 
 struct fd_grid {
@@ -177,12 +178,17 @@ struct fd_grid {
     // moduli times dt, the memory forcing moduli and dt / tau_s; the same
     // three at each shear-stress position)
     float *el[17] = {};
-    float *facebuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    float *facebase = nullptr;    // the six loopback face buffers, back to back
+    float *facebuf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // into facebase
     float *inter[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // TTI pass-1 output
     unsigned *scratch_u32 = nullptr;  // small device scratch (model checks)
     bool model_loaded = false;
     std::vector<hipEvent_t> prof_ev;  // armed step-kernel timing events (pairs)
     int prof_used = 0;
+    // set for one launch while profiling: the z-march step kernel is launched
+    // with these as its start/stop events (recorded with the kernel's own
+    // dispatch, so they time the kernel alone)
+    mutable hipEvent_t launch_ev[2] = {nullptr, nullptr};
     int xmode = 0;                    // FD_XCHG_BASIC / FD_XCHG_FULL
     hipStream_t xs = nullptr;         // exchange stream of full mode
     hipEvent_t xfork = nullptr, xjoin = nullptr;
@@ -215,6 +221,12 @@ void make_geometry(const fd_grid_desc &d, int ndim, const int n[3], const double
 // stability check of a descriptor (FD_OK or FD_EUNSTABLE with the message set)
 int check_stability(const fd_grid_desc &d, int ndim, const double h[3], int r);
 
+// autotuner cache (fd_api.hip): the device's architecture name, and a flat
+// JSON object mapping keys to [by, ry, nzb, flags]
+std::string device_arch(int device);
+bool tune_lookup(const char *path, const std::string &key, int t[4]);
+void tune_store(const char *path, const std::string &key, const int t[4]);
+
 // error helpers (fd_api.hip)
 int set_error(int code, const std::string &msg);
 int check_launch(const char *what);
@@ -232,6 +244,10 @@ int launch_zmarch_radius(const fd_grid *g, const StepParams &p, const Tuning &t,
                          const float *um, float *up, hipStream_t s);
 int launch_sparse(const fd_grid *g, float *u, const SparseArgs &inj, const SparseArgs &smp,
                   hipStream_t s);
+// injection into u_new and sampling of u_old (a different, finished field)
+// in one multi-block launch: the two halves are independent (k_sparse.hip)
+int launch_sparse_split(const fd_grid *g, float *u_new, const SparseArgs &inj,
+                        const float *u_old, const SparseArgs &smp, hipStream_t s);
 int launch_pack(const fd_grid *g, const float *field, unsigned mask, float *const *buf,
                 hipStream_t s);
 int launch_unpack(const fd_grid *g, float *field, unsigned mask, const float *const *buf,

@@ -346,6 +346,21 @@ class Batch:
     def set_tile(self, by, ry, nzb, xcd=1):
         _check(lib().fd_batch_set_tile(self.handle, by, ry, nzb, xcd))
 
+    @property
+    def tile(self):
+        t = (ctypes.c_int * 4)()
+        _check(lib().fd_batch_get_tile(self.handle, t))
+        return tuple(t)
+
+    def autotune(self, cache_path=None):
+        """Timed search of the batched step's tile (or cache lookup); needs a
+        loaded model.  Returns ((by, ry, nzb, flags), ms per launch)."""
+        t = (ctypes.c_int * 4)()
+        ms = ctypes.c_double()
+        _check(lib().fd_batch_autotune(self.handle, cache_path.encode() if cache_path else None,
+                                       t, ctypes.byref(ms), _stream(self.device)))
+        return tuple(t), ms.value
+
     def set_geometry(self, shot, src, rec):
         src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
         rec = np.ascontiguousarray(rec, dtype=np.float64).reshape(-1, 3)
@@ -388,6 +403,8 @@ def _bind_batch(L):
     L.fd_batch_device_bytes.argtypes = [vp]
     L.fd_batch_device_bytes.restype = ctypes.c_size_t
     L.fd_batch_set_tile.argtypes = [vp, i, i, i, i]
+    L.fd_batch_get_tile.argtypes = [vp, P(i)]
+    L.fd_batch_autotune.argtypes = [vp, ctypes.c_char_p, P(i), P(ctypes.c_double), vp]
     L.fd_batch_set_geometry.argtypes = [vp, i, P(ctypes.c_double), i, P(ctypes.c_double), i]
     L.fd_batch_set_model.argtypes = [vp, vp, vp]
     L.fd_batch_gradient.argtypes = [vp, P(vp), P(vp), P(vp), vp, vp]
