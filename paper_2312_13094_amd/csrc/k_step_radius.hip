@@ -4,6 +4,8 @@
 // single-grid kernel and the batched multi-shot kernel, over the supported
 // tiles and flag combinations (see zmarch.h).  Compiling one radius per
 // object keeps the build parallel.
+#include <hip/hip_ext.h>
+
 #include "batch_internal.h"
 #include "zmarch.h"
 
@@ -44,8 +46,13 @@ static void zmarch_v(const fd_grid *g, const StepParams &p, const Tuning &t, con
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY, nzc = (p.nz + nzb - 1) / nzb;
     const unsigned nb = (unsigned)ntx * nty * nzc;
     const int remap = ((t.flags & kTileXcd) && nb % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS, RING, CX>), dim3(nb), dim3(64, BY), 0,
-                       s, u, um, up, g->vdt2, p, ntx, nty, nzb, remap);
+    if (g->launch_ev[0])   // timed launch: the dispatch records the events
+        hipExtLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS, RING, CX>), dim3(nb),
+                              dim3(64, BY), 0, s, g->launch_ev[0], g->launch_ev[1], 0, u, um, up,
+                              g->vdt2, p, ntx, nty, nzb, remap);
+    else
+        hipLaunchKernelGGL((k_acoustic_zmarch<R, BY, RY, PF, NTS, RING, CX>), dim3(nb),
+                           dim3(64, BY), 0, s, u, um, up, g->vdt2, p, ntx, nty, nzb, remap);
 }
 
 // 128-wide tiles (two columns per lane): ring body, tiles (8,2) (4,2) (4,4)
