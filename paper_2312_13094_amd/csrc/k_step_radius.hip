@@ -33,7 +33,7 @@ __global__ __launch_bounds__(64 * BY) void k_acoustic_zmarch(
     const int ty = b % nty;
     const int zc = b / nty;
 
-    if (RING) zmarch_ring_body<R, BY, RY, NTS, CX>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
+    if (RING) zmarch_buf_body<R, BY, RY, NTS, CX>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
     else zmarch_body<R, BY, RY, PF, NTS>(u, um, up, vdt2, p, tx, ty, zc, nzb, lds);
 }
 

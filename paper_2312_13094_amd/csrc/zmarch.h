@@ -363,3 +363,216 @@ __device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, co
 }
 
 }  // namespace fd
+
+namespace fd {
+
+// ---------------------------------------------------------------------------
+// The same z-march as zmarch_ring_body, addressed through buffer resources.
+// Every access is a buffer load or store with a per-plane descriptor (base at
+// the plane's row -R, column -R; as many bytes as the padded plane holds
+// from there) and a 32-bit per-lane offset that stays fixed over the march.
+// Lanes whose point is not loaded (or not written) carry an offset beyond the
+// descriptor's range: the hardware returns 0 for such a load and drops such
+// a store, so the hot loop has no per-lane branches and no 64-bit address
+// arithmetic, and the compiler can count the memory operations in flight
+// exactly between the waits.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBufOOB = 0xFFFFFFF0u;     // beyond every plane descriptor
+constexpr int kBufWord3 = 0x00020000;         // gfx9 raw buffer: 32-bit data format
+
+struct PlaneBuf {
+    const char *b0;      // byte address of plane 0, row -R, column -R
+    int64_t pz;          // bytes per plane
+    int32_t nrec;        // bytes a plane descriptor covers
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t at(const int z) const
+    {
+        return __builtin_amdgcn_make_buffer_rsrc((void *)(b0 + (int64_t)z * pz), (short)0, nrec,
+                                                 kBufWord3);
+    }
+};
+
+__device__ __forceinline__ PlaneBuf plane_buf(const float *field, const StepParams &p, int R)
+{
+    PlaneBuf b;
+    b.b0 = reinterpret_cast<const char *>(field + p.offset - (int64_t)R * p.pitch_y - R);
+    b.pz = p.pitch_z * (int64_t)sizeof(float);
+    b.nrec = (int32_t)(((int64_t)(p.ny + 2 * R) * p.pitch_y) * (int64_t)sizeof(float));
+    return b;
+}
+
+// AUX is the cache policy: 0 default, 2 non-temporal
+template <int AUX = 0>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+
+template <int AUX = 0>
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, AUX);
+}
+
+template <int R, int BY, int RY, bool NTS, int CX = 1>
+__device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, const float *um,
+                                                float *up, const float *__restrict__ vdt2,
+                                                const StepParams &p, const int tx, const int ty,
+                                                const int zc, const int nzb, float *lds)
+{
+    constexpr int TX = 64 * CX, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
+    constexpr int NT = 64 * BY;
+    constexpr int NHY = 2 * R * TX;
+    constexpr int NHX = 2 * R * TY;
+    constexpr int HY = (NHY + NT - 1) / NT;
+    constexpr int HX = (NHX + NT - 1) / NT;
+    constexpr int NR = R + 1;                 // halo ring depth (planes)
+    constexpr int NTA = NTS ? 2 : 0;          // non-temporal cache policy
+    const int lane = threadIdx.x, wy = threadIdx.y;
+    const int tid = wy * 64 + lane;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int yb = y0 + wy * RY;
+    const int z0 = zc * nzb;
+    const int z1 = min(z0 + nzb, p.nz);
+    const int PY = (int)p.pitch_y;
+    const PlaneBuf Bu = plane_buf(u, p, R), Bm = plane_buf(um, p, R), Bv = plane_buf(vdt2, p, R),
+                   Bp = plane_buf(up, p, R);
+    // byte offset of in-plane point (y, x) from the plane descriptor's base
+    auto boff = [&](const int y, const int x) -> uint32_t {
+        return (uint32_t)(((y + R) * PY + (x + R)) * (int)sizeof(float));
+    };
+
+    int xs[CX];
+    uint32_t ol[CX][RY], ow[CX][RY];          // load / store offsets (OOB if masked)
+#pragma unroll
+    for (int c = 0; c < CX; ++c) {
+        xs[c] = x0 + lane + 64 * c;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const bool rl = xs[c] >= p.xlo - R && xs[c] < p.nx + R && (yb + j) < p.ny + R;
+            const bool ro = xs[c] >= p.xlo && xs[c] < p.nx && (yb + j) < p.ny;
+            ol[c][j] = rl ? boff(yb + j, xs[c]) : kBufOOB;
+            ow[c][j] = ro ? boff(yb + j, xs[c]) : kBufOOB;
+        }
+    }
+    uint32_t hyo[HY], hxo[HX];
+    int hys[HY], hxs[HX];
+#pragma unroll
+    for (int k = 0; k < HY; ++k) {
+        const int e = tid + k * NT;
+        const int row = e / TX, col = e % TX;
+        const int yy = row < R ? y0 - R + row : y0 + TY + (row - R);
+        const int ly = row < R ? row : TY + row;
+        const int xx = x0 + col;
+        const bool ok = e < NHY && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
+        hyo[k] = ok ? boff(yy, xx) : kBufOOB;
+        hys[k] = e < NHY ? ly * LX + col + R : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < HX; ++k) {
+        const int e = tid + k * NT;
+        const int row = e / (2 * R), c = e % (2 * R);
+        const int yy = y0 + row;
+        const int xx = c < R ? x0 - R + c : x0 + TX + (c - R);
+        const int lx = c < R ? c : TX + c;
+        const bool ok = e < NHX && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
+        hxo[k] = ok ? boff(yy, xx) : kBufOOB;
+        hxs[k] = e < NHX ? (row + R) * LX + lx : -1;
+    }
+
+    float q[CX][RY][2 * R + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) {
+        const __amdgpu_buffer_rsrc_t r = Bu.at(z0 - R + k);
+#pragma unroll
+        for (int c = 0; c < CX; ++c)
+#pragma unroll
+            for (int j = 0; j < RY; ++j) q[c][j][k + 1] = bload(r, ol[c][j]);
+    }
+    float hy[NR][HY], hx[NR][HX];
+    auto load_halo = [&](const int z, const int d) {
+        const __amdgpu_buffer_rsrc_t r = Bu.at(z);
+#pragma unroll
+        for (int k = 0; k < HY; ++k) hy[d][k] = bload(r, hyo[k]);
+#pragma unroll
+        for (int k = 0; k < HX; ++k) hx[d][k] = bload(r, hxo[k]);
+    };
+#pragma unroll
+    for (int d = 0; d < NR; ++d)
+        if (z0 + d < z1) load_halo(z0 + d, d);
+    float nf[CX][RY], nm[CX][RY], nv[CX][RY];
+    auto prefetch = [&](const int z) {
+        const __amdgpu_buffer_rsrc_t rf = Bu.at(z + R), rm = Bm.at(z), rv = Bv.at(z);
+#pragma unroll
+        for (int c = 0; c < CX; ++c)
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                nf[c][j] = bload(rf, ol[c][j]);
+                nm[c][j] = bload<NTA>(rm, ow[c][j]);
+                nv[c][j] = bload<NTA>(rv, ow[c][j]);
+            }
+    };
+    if (z0 < z1) prefetch(z0);
+
+    float ax[CX];
+#pragma unroll
+    for (int c = 0; c < CX; ++c)
+        ax[c] = p.nbl > 0 ? sponge_ax(p, 2, xs[c], p.gx) : 0.0f;
+    for (int zb = z0; zb < z1; zb += NR) {
+#pragma unroll
+        for (int d = 0; d < NR; ++d) {
+            const int z = zb + d;
+            if (z < z1) {
+                float cm[CX][RY], cv[CX][RY];
+#pragma unroll
+                for (int c = 0; c < CX; ++c)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+#pragma unroll
+                        for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + 1];
+                        q[c][j][2 * R] = nf[c][j];
+                        cm[c][j] = nm[c][j];
+                        cv[c][j] = nv[c][j];
+                    }
+                if (z + 1 < z1) prefetch(z + 1);
+                float *t = lds + (z & 1) * (LY * LX);
+#pragma unroll
+                for (int c = 0; c < CX; ++c)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j)
+                        t[(wy * RY + j + R) * LX + lane + 64 * c + R] = q[c][j][R];
+#pragma unroll
+                for (int k = 0; k < HY; ++k)
+                    if (NHY % NT == 0 || tid + k * NT < NHY) t[hys[k]] = hy[d][k];
+#pragma unroll
+                for (int k = 0; k < HX; ++k)
+                    if (NHX % NT == 0 || tid + k * NT < NHX) t[hxs[k]] = hx[d][k];
+                if (z + NR < z1) load_halo(z + NR, d);
+                __syncthreads();
+
+                const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
+                const __amdgpu_buffer_rsrc_t rp = Bp.at(z);
+#pragma unroll
+                for (int c = 0; c < CX; ++c)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+                        const float *cc = t + (wy * RY + j + R) * LX + lane + 64 * c + R;
+                        float lz = 0.0f, ly = 0.0f, lx = 0.0f;
+#pragma unroll
+                        for (int k = 1; k <= R; ++k) {
+                            lz += p.cz[k] * (q[c][j][R + k] + q[c][j][R - k]);
+                            ly += p.cy[k] * (cc[k * LX] + cc[-k * LX]);
+                            lx += p.cx[k] * (cc[k] + cc[-k]);
+                        }
+                        const float uc = q[c][j][R];
+                        const float lap = p.c0 * uc + lz + ly + lx;
+                        const int y = yb + j;
+                        const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
+                        const float a = p.half_dt * ((az + ax[c]) + ay);
+                        bstore<NTA>(leapfrog_update(uc, cm[c][j], cv[c][j], lap, a), rp, ow[c][j]);
+                    }
+            }
+        }
+    }
+}
+
+}  // namespace fd
