@@ -125,8 +125,8 @@ __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__res
     float *base = S.base;
     const int64_t st = S.stride;
     if (RING)
-        zmarch_ring_body<R, BY, RY, NTS, CX>(base + iu * st, base + ium * st, base + iup * st,
-                                             base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
+        zmarch_buf_body<R, BY, RY, NTS, CX>(base + iu * st, base + ium * st, base + iup * st,
+                                            base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
     else
         zmarch_body<R, BY, RY, PF, NTS>(base + iu * st, base + ium * st, base + iup * st,
                                         base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);

@@ -179,6 +179,11 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
     }
 }
 
+}  // namespace fd
+
+namespace fd {
+
+// ---------------------------------------------------------------------------
 // Variant with the halo loads moved R planes earlier.  In the plain body a
 // tile reads the x/y halo of plane z when it computes plane z, R iterations
 // after its neighbours streamed plane z in as their queue front -- by then
@@ -189,185 +194,8 @@ __device__ __forceinline__ void zmarch_body(const float *__restrict__ u, const f
 // the non-temporal hint when NTS is set so they do not evict u from L2.
 // With CX = 2 every lane owns two columns 64 apart (a 128-wide tile), which
 // halves the share of x-halo cache lines per tile row.
-template <int R, int BY, int RY, bool NTS, int CX = 1>
-__device__ __forceinline__ void zmarch_ring_body(const float *__restrict__ u, const float *um,
-                                                 float *up, const float *__restrict__ vdt2,
-                                                 const StepParams &p, const int tx, const int ty,
-                                                 const int zc, const int nzb, float *lds)
-{
-    constexpr int TX = 64 * CX, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
-    constexpr int NT = 64 * BY;
-    constexpr int NHY = 2 * R * TX;
-    constexpr int NHX = 2 * R * TY;
-    constexpr int HY = (NHY + NT - 1) / NT;
-    constexpr int HX = (NHX + NT - 1) / NT;
-    constexpr int NR = R + 1;                 // halo ring depth (planes)
-    const int lane = threadIdx.x, wy = threadIdx.y;
-    const int tid = wy * 64 + lane;
-    const int x0 = tx * TX, y0 = ty * TY;
-    const int yb = y0 + wy * RY;
-    const int z0 = zc * nzb;
-    const int z1 = min(z0 + nzb, p.nz);
-    const int64_t PY = p.pitch_y, PZ = p.pitch_z;
-    const float *uo = u + p.offset;
-    const float *umo = um + p.offset;
-    const float *vo = vdt2 + p.offset;
-    float *upo = up + p.offset;
-
-    int xs[CX];
-    bool rl[CX][RY], ro[CX][RY];
-#pragma unroll
-    for (int c = 0; c < CX; ++c) {
-        xs[c] = x0 + lane + 64 * c;
-#pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            rl[c][j] = xs[c] >= p.xlo - R && xs[c] < p.nx + R && (yb + j) < p.ny + R;
-            ro[c][j] = xs[c] >= p.xlo && xs[c] < p.nx && (yb + j) < p.ny;
-        }
-    }
-    int64_t hyo[HY], hxo[HX];
-    int hys[HY], hxs[HX];
-    bool hyk[HY], hxk[HX];
-#pragma unroll
-    for (int k = 0; k < HY; ++k) {
-        const int e = tid + k * NT;
-        const int row = e / TX, col = e % TX;
-        const int yy = row < R ? y0 - R + row : y0 + TY + (row - R);
-        const int ly = row < R ? row : TY + row;
-        const int xx = x0 + col;
-        hyk[k] = e < NHY && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
-        hyo[k] = (int64_t)yy * PY + xx;
-        hys[k] = ly * LX + col + R;
-    }
-#pragma unroll
-    for (int k = 0; k < HX; ++k) {
-        const int e = tid + k * NT;
-        const int row = e / (2 * R), c = e % (2 * R);
-        const int yy = y0 + row;
-        const int xx = c < R ? x0 - R + c : x0 + TX + (c - R);
-        const int lx = c < R ? c : TX + c;
-        hxk[k] = e < NHX && yy < p.ny + R && xx >= p.xlo - R && xx < p.nx + R;
-        hxo[k] = (int64_t)yy * PY + xx;
-        hxs[k] = (row + R) * LX + lx;
-    }
-
-    float q[CX][RY][2 * R + 1];
-#pragma unroll
-    for (int c = 0; c < CX; ++c)
-#pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            const int64_t col = (int64_t)(yb + j) * PY + xs[c];
-#pragma unroll
-            for (int k = 0; k < 2 * R; ++k)
-                q[c][j][k + 1] = rl[c][j] ? uo[(int64_t)(z0 - R + k) * PZ + col] : 0.0f;
-        }
-    // halo ring: slot d holds the halo of plane z with (z - z0) % NR == d
-    float hy[NR][HY], hx[NR][HX];
-    auto load_halo = [&](const int z, const int d) {
-        const int64_t pz = (int64_t)z * PZ;
-#pragma unroll
-        for (int k = 0; k < HY; ++k) hy[d][k] = hyk[k] ? uo[pz + hyo[k]] : 0.0f;
-#pragma unroll
-        for (int k = 0; k < HX; ++k) hx[d][k] = hxk[k] ? uo[pz + hxo[k]] : 0.0f;
-    };
-#pragma unroll
-    for (int d = 0; d < NR; ++d)
-        if (z0 + d < z1) load_halo(z0 + d, d);
-    float nf[CX][RY], nm[CX][RY], nv[CX][RY];
-    auto prefetch = [&](const int z) {
-        const int64_t pz = (int64_t)z * PZ;
-#pragma unroll
-        for (int c = 0; c < CX; ++c)
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                const int64_t col = (int64_t)(yb + j) * PY + xs[c];
-                nf[c][j] = rl[c][j] ? uo[pz + R * PZ + col] : 0.0f;
-                if (NTS) {
-                    nm[c][j] = ro[c][j] ? __builtin_nontemporal_load(umo + pz + col) : 0.0f;
-                    nv[c][j] = ro[c][j] ? __builtin_nontemporal_load(vo + pz + col) : 0.0f;
-                } else {
-                    nm[c][j] = ro[c][j] ? umo[pz + col] : 0.0f;
-                    nv[c][j] = ro[c][j] ? vo[pz + col] : 0.0f;
-                }
-            }
-    };
-    if (z0 < z1) prefetch(z0);
-
-    float ax[CX];
-#pragma unroll
-    for (int c = 0; c < CX; ++c)
-        ax[c] = p.nbl > 0 ? sponge_ax(p, 2, xs[c], p.gx) : 0.0f;
-    for (int zb = z0; zb < z1; zb += NR) {
-#pragma unroll
-        for (int d = 0; d < NR; ++d) {
-            const int z = zb + d;
-            if (z < z1) {
-                float cm[CX][RY], cv[CX][RY];
-#pragma unroll
-                for (int c = 0; c < CX; ++c)
-#pragma unroll
-                    for (int j = 0; j < RY; ++j) {
-#pragma unroll
-                        for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + 1];
-                        q[c][j][2 * R] = nf[c][j];
-                        cm[c][j] = nm[c][j];
-                        cv[c][j] = nv[c][j];
-                    }
-                if (z + 1 < z1) prefetch(z + 1);
-                float *t = lds + (z & 1) * (LY * LX);
-#pragma unroll
-                for (int c = 0; c < CX; ++c)
-#pragma unroll
-                    for (int j = 0; j < RY; ++j)
-                        t[(wy * RY + j + R) * LX + lane + 64 * c + R] = q[c][j][R];
-#pragma unroll
-                for (int k = 0; k < HY; ++k)
-                    if (tid + k * NT < NHY) t[hys[k]] = hy[d][k];
-#pragma unroll
-                for (int k = 0; k < HX; ++k)
-                    if (tid + k * NT < NHX) t[hxs[k]] = hx[d][k];
-                // the ring slot is free again: issue the halo of plane z + NR,
-                // together with the neighbours' front loads of that plane
-                if (z + NR < z1) load_halo(z + NR, d);
-                __syncthreads();
-
-                const float az = p.nbl > 0 ? sponge_ax(p, 0, z, p.gz) : 0.0f;
-#pragma unroll
-                for (int c = 0; c < CX; ++c)
-#pragma unroll
-                    for (int j = 0; j < RY; ++j) {
-                        const float *cc = t + (wy * RY + j + R) * LX + lane + 64 * c + R;
-                        float lz = 0.0f, ly = 0.0f, lx = 0.0f;
-#pragma unroll
-                        for (int k = 1; k <= R; ++k) {
-                            lz += p.cz[k] * (q[c][j][R + k] + q[c][j][R - k]);
-                            ly += p.cy[k] * (cc[k * LX] + cc[-k * LX]);
-                            lx += p.cx[k] * (cc[k] + cc[-k]);
-                        }
-                        const float uc = q[c][j][R];
-                        const float lap = p.c0 * uc + lz + ly + lx;
-                        const int y = yb + j;
-                        const float ay =
-                            p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
-                        const float a = p.half_dt * ((az + ax[c]) + ay);
-                        const float val = leapfrog_update(uc, cm[c][j], cv[c][j], lap, a);
-                        if (ro[c][j]) {
-                            float *dst = upo + (int64_t)z * PZ + (int64_t)y * PY + xs[c];
-                            if (NTS) __builtin_nontemporal_store(val, dst);
-                            else *dst = val;
-                        }
-                    }
-            }
-        }
-    }
-}
-
-}  // namespace fd
-
-namespace fd {
-
-// ---------------------------------------------------------------------------
-// The same z-march as zmarch_ring_body, addressed through buffer resources.
+//
+// The march is addressed through buffer resources.
 // Every access is a buffer load or store with a per-plane descriptor (base at
 // the plane's row -R, column -R; as many bytes as the padded plane holds
 // from there) and a 32-bit per-lane offset that stays fixed over the march.
