@@ -382,11 +382,16 @@ def bench_learned(args):
                      res.seconds, t_plain, eager.seconds, LC.trace_error(p8, ref), t8,
                      LC.trace_error(p12, ref), t12, res.fallback))
     r = np.array([x[:10] for x in rows])
+    faster = bool(r[:, 3].mean() < r[:, 2].mean())
+    accurate = bool((r[:, 1] <= 0.02).all())
     return {"metric": "learned vs plain time at same err (wall ms, held-out mean)",
             "value": round(float(r[:, 3].mean() * 1e3), 3), "unit": "ms",
             "n_gpus": 1, "steps": len(rows), "warmup": 0,
             "ms_per_step": round(float(r[:, 3].mean() * 1e3), 3), "higher_is_better": False,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
+            "target": {"learned_trace_err_max": 0.02, "learned_faster_than_fine": faster,
+                       "learned_trace_err_within_target": accurate,
+                       "met": faster and accurate},
             "config": {"workload": c.name, "fine_ms": round(float(r[:, 2].mean() * 1e3), 3),
                        "plain_coarse_ms": round(float(r[:, 4].mean() * 1e3), 3),
                        "learned_eager_ms": round(float(r[:, 5].mean() * 1e3), 3),
