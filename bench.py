@@ -95,8 +95,8 @@ def cpu_baseline(c, budget_s):
 
 
 def bench_tti(args):
-    """Pseudo-acoustic TTI, 384^3, so 12, 500 steps (Gpts/s; the step is the
-    two rotated-operator passes)."""
+    """Pseudo-acoustic TTI, 384^3, so 12, 500 steps (Gpts/s; by default the
+    step is two z-marching passes, tile flag 32 selects one kernel)."""
     import torch
 
     from paper_2312_13094_amd import fd, synth
@@ -108,6 +108,7 @@ def bench_tti(args):
     if tile:
         g.set_tile(*tile)
     zm = not tile or tile[0] > 0
+    one_kernel = bool(tile) and len(tile) > 3 and bool(tile[3] & 32)
     f = {k: torch.from_numpy(v).cuda() for k, v in c.fields.items()}
     g.set_model(f["v"], [f["eps"], f["delta"], f["theta"], f["phi"]])
     del f
@@ -127,7 +128,17 @@ def bench_tti(args):
     kms, nl = g.profile_end()
     gpts = c.points * c.nt * args.steps / wall / 1e9
     avg = kms / max(nl, 1)
-    alg = 44 * c.points
+    # one pass would read p, r, p-, r-, c, c_pp, c_x and the tilt and azimuth
+    # (44 B/pt; the one-kernel step reads the stored axis, 3 fields, instead of
+    # the 2 angles: 48 B/pt) and write p+, r+
+    alg = (48 if one_kernel else 44) * c.points
+    if not zm:
+        kern = "k_tti_pass1 + k_tti_pass2 (one step, two passes through memory)"
+    elif one_kernel:
+        kern = "k_tti_fused (one z-marching kernel per step, 48 B/pt)"
+    else:
+        kern = "k_tti_grad_zm + k_tti_div_zm (one step, two z-marching passes moving " \
+               "100 B/pt: 24 B/pt of intermediates written and read, p and r read twice)"
     return {"metric": "Gpts/s, 3D so-12 TTI", "value": round(gpts, 3), "unit": "Gpts/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
@@ -139,9 +150,7 @@ def bench_tti(args):
                          "frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          "traffic": _traffic_summary(TTI_TRAFFIC_FILE, "hbm_bytes_per_step",
                                                      args.tile or "default", n == 384),
-                         "kernel": ("k_tti_grad_zm + k_tti_div_zm" if zm else
-                                    "k_tti_pass1 + k_tti_pass2") + " (one step, two passes "
-                                   "moving 100 B/pt: 24 B of intermediates written and read)",
+                         "kernel": kern,
                          "avg_launch_ms": round(avg, 5), "launches_timed": nl,
                          "algorithmic_bytes_per_launch": alg}}
 

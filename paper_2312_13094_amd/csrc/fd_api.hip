@@ -341,9 +341,10 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
     const fd_layout &L = g->L;
 
     const bool staggered = d.physics == FD_ELASTIC || d.physics == FD_VISCO;
-    g->tune = staggered             ? el_default_tuning(g->n)
-              : d.ndim == 3            ? default_tuning(g->n)
-                                       : Tuning{0, 0, 0, 0};
+    g->tune = staggered                                ? el_default_tuning(g->n)
+              : d.ndim == 3 && d.physics == FD_TTI ? tti_default_tuning(g->n)
+              : d.ndim == 3                         ? default_tuning(g->n)
+                                                    : Tuning{0, 0, 0, 0};
 
     DeviceGuard dg(d.device);
     if (!dg.ok()) {
@@ -367,7 +368,7 @@ int fd_create_grid(const fd_grid_desc *desc, fd_grid **out)
         return set_error(FD_ENOMEM, "device allocation failed");
     }
     if (d.physics == FD_TTI) {
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 7; ++i)
             if (hipMalloc(&g->tti[i], L.field_bytes) != hipSuccess ||
                 hipMemset(g->tti[i], 0, L.field_bytes) != hipSuccess) {
                 free_grid(g);
@@ -428,6 +429,15 @@ int fd_set_tile(fd_grid *g, int by, int ry, int nzb, int xcd)
             xcd > 31)
             return set_error(FD_EINVAL, "elastic tiles: (by, ry) = (4, 2), (8, 1), (8, 2) or by = 0");
         g->tune = Tuning{by, ry, nzb, 0};
+        return FD_OK;
+    }
+    if (g->d.physics == FD_TTI) {
+        // flag kTileTti1 selects the one-kernel step: by = 16 for 32-wide
+        // tiles, ry = 2 for two tile columns per thread (space orders up to
+        // 6); the two passes use only nzb
+        if (by < 1 || ry < 1 || nzb < 1 || xcd < 0 || xcd > 63)
+            return set_error(FD_EINVAL, "TTI tiles: by, ry, nzb >= 1, flags in 0..63");
+        g->tune = Tuning{by, ry, nzb, xcd};
         return FD_OK;
     }
     const bool known = (by == 4 && (ry == 1 || ry == 2 || ry == 4 || ry == 8)) ||

@@ -111,9 +111,11 @@ struct Tuning {
     int flags;     // bit 0: XCD-aware block remap; bit 1: prefetch two planes
                    // ahead; bit 2: non-temporal hints on the streamed fields;
                    // bit 3: halo loads issued with the neighbours' front loads;
-                   // bit 4: 128-wide tiles, two columns per lane (implies bit 3)
+                   // bit 4: 128-wide tiles, two columns per lane (implies bit 3);
+                   // bit 5: TTI in one z-marching kernel instead of two passes
 };
-constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8, kTileWide = 16;
+constexpr int kTileXcd = 1, kTilePf2 = 2, kTileNts = 4, kTileRing = 8, kTileWide = 16,
+              kTileTti1 = 32;
 
 // Default 3-D tile, with the halo ring and non-temporal hints.  Large grids
 // take 128 x 16 tiles (8 waves of 2 rows, two columns per lane) with the
@@ -136,6 +138,13 @@ inline Tuning default_tuning(const int n[3])
                 return Tuning{sh[0], sh[1], nzb, kTileRing | kTileNts};
     }
     return Tuning{4, 1, 8, kTileRing | kTileNts};
+}
+
+// TTI: the two z-marching passes with the acoustic default's z chunk
+// (32 planes at 384^3); the one-kernel step (flag kTileTti1) measured slower.
+inline Tuning tti_default_tuning(const int n[3])
+{
+    return Tuning{8, 2, default_tuning(n).nzb, 0};
 }
 
 // Elastic passes: z-marching 64 x 16 tiles, (by, ry) = (8, 2); the deepest
@@ -171,7 +180,10 @@ struct fd_grid {
     fd::StepParams sp;
     fd::Tuning tune;
     float *vdt2 = nullptr;        // padded v^2 dt^2
-    float *tti[4] = {nullptr, nullptr, nullptr, nullptr};  // padded eps, delta, theta, phi
+    // padded c_pp = c (1 + 2 eps), c_x = c sqrt(1 + 2 delta), the tilt t and
+    // azimuth f, and the symmetry axis (a_z, a_y, a_x) = (cos t, sin t sin f,
+    // sin t cos f) of each point (read by the one-kernel step)
+    float *tti[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // elastic medium times dt at each component's position (padded):
     // b dt at vx, vy, vz; lambda dt, mu dt at nodes; mu dt at txy, txz, tyz
     // visco-elastic: 17 fields (b dt at the velocities; at nodes the unrelaxed
@@ -279,9 +291,12 @@ int launch_el_sparse(const fd_grid *g, float *const *f, const SparseArgs &inj,
 int launch_vi_model(const fd_grid *g, const float *vp, const float *const *aux, unsigned *flags,
                     hipStream_t s);
 int launch_vi_stress(const fd_grid *g, float *const *f, hipStream_t s);
-// z-marching TTI passes (k_tti_zmarch.hip), used by launch_tti_step for 3-D
-// grids whose tile is not the one-thread-per-point kernel
+// z-marching TTI steps for 3-D grids whose tile is not the one-thread-per-
+// point kernel: two passes through memory (k_tti_zmarch.hip, the default) or
+// one kernel (k_tti_fused.hip, tile flag kTileTti1)
 int launch_tti_step_zm(const fd_grid *g, const float *p, const float *pm, float *pp,
                        const float *r, const float *rm, float *rp, hipStream_t s);
+int launch_tti_step_fused(const fd_grid *g, const float *p, const float *pm, float *pp,
+                          const float *r, const float *rm, float *rp, hipStream_t s);
 
 }  // namespace fd

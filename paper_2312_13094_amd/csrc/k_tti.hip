@@ -106,6 +106,7 @@ __global__ __launch_bounds__(256) void k_tti_model(const float *__restrict__ vel
                                                    const float *__restrict__ theta,
                                                    const float *__restrict__ phi, float *c,
                                                    float *cpp, float *cx, float *th, float *ph,
+                                                   float *az, float *ay, float *ax,
                                                    unsigned *flags, const StepParams p,
                                                    const float dt2)
 {
@@ -125,6 +126,13 @@ __global__ __launch_bounds__(256) void k_tti_model(const float *__restrict__ vel
         cx[j] = cv * sqrtf(1.0f + 2.0f * d);
         th[j] = theta[i];
         ph[j] = phi[i];
+        // the symmetry axis, for the one-kernel step
+        float st, ct, sf, cf;
+        sincosf(theta[i], &st, &ct);
+        sincosf(phi[i], &sf, &cf);
+        az[j] = ct;
+        ay[j] = st * sf;
+        ax[j] = st * cf;
         const unsigned vb = (v > 0.0f) ? __float_as_uint(v) : 0x7f800000u;
         // eps, delta must be > -1/2; flag otherwise (NaN included)
         const unsigned eb = (e >= 0.0f) ? __float_as_uint(e) : ((e > -0.5f) ? 0u : 0x7f800000u);
@@ -143,7 +151,8 @@ int launch_tti_model(const fd_grid *g, const float *vel, const float *const *tti
     const int64_t n = (int64_t)g->n[0] * g->n[1] * g->n[2];
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_tti_model, dim3(nb), dim3(256), 0, s, vel, tti[0], tti[1], tti[2],
-                       tti[3], g->vdt2, g->tti[0], g->tti[1], g->tti[2], g->tti[3], flags, g->sp,
+                       tti[3], g->vdt2, g->tti[0], g->tti[1], g->tti[2], g->tti[3], g->tti[4],
+                       g->tti[5], g->tti[6], flags, g->sp,
                        (float)(g->d.dt * g->d.dt));
     return check_launch("TTI model");
 }
@@ -165,7 +174,9 @@ static void tti_r(const fd_grid *g, const float *p, const float *pm, float *pp, 
 int launch_tti_step(const fd_grid *g, const float *p, const float *pm, float *pp, const float *r,
                     const float *rm, float *rp, hipStream_t s)
 {
-    if (g->ndim == 3 && g->tune.by > 0) return launch_tti_step_zm(g, p, pm, pp, r, rm, rp, s);
+    if (g->ndim == 3 && g->tune.by > 0)
+        return (g->tune.flags & kTileTti1) ? launch_tti_step_fused(g, p, pm, pp, r, rm, rp, s)
+                                           : launch_tti_step_zm(g, p, pm, pp, r, rm, rp, s);
     switch (g->r) {
     case 2: tti_r<2>(g, p, pm, pp, r, rm, rp, s); break;
     case 3: tti_r<3>(g, p, pm, pp, r, rm, rp, s); break;

@@ -1,5 +1,5 @@
-"""GPU TTI step (two-pass rotated operators, coupled leapfrog) against the FP64
-TTI oracle.  Parity: relative L2 <= 1e-5 after one step, <= 1e-4 after a run
+"""GPU TTI step (rotated operators, coupled leapfrog; two z-marching passes by
+default, one z-marching kernel on request) against the FP64 TTI oracle.  Parity: relative L2 <= 1e-5 after one step, <= 1e-4 after a run
 (this coupled system's formulation is a reading of the paper's references:
 the comparison is GPU vs oracle, with the oracle pinned separately)."""
 import math
@@ -126,18 +126,42 @@ def test_tti_rejects_bad_setup():
     assert e.value.code == FD.FD_EUNSTABLE
 
 
-def test_tti_zmarch_matches_point_kernels():
-    """The z-marching passes (any z chunk, ragged tiles) agree with the
-    one-thread-per-point passes to FP32 rounding over several steps."""
-    shape, so, nbl, nt = (27, 21, 75), 12, 4, 6
+@pytest.mark.parametrize("so", [12, 8, 4])
+def test_tti_zmarch_matches_point_kernels(so):
+    """The two z-marching passes and the one-kernel z-march (tile flag 32;
+    64- and 32-wide tiles, one or two tile columns per thread), for any z
+    chunk and ragged tiles and chunks, agree with the one-thread-per-point
+    passes to FP32 rounding over several steps."""
+    shape, nbl, nt = (27, 21, 75), 4, 6
     fields = _fields(shape, 77)
     dt = synth.tti_stable_dt(so, 10.0, 4500.0, 0.3)
     init = [synth.smooth_state(shape, s, 3.0) for s in (5, 6, 7, 8)]
     ref, _ = _run(shape, so, nbl, nt, fields, dt, init=init, tile=(0, 0, 0, 0))
-    for tile in [(4, 1, 5, 0), (4, 2, 64, 0), (8, 2, 13, 12)]:
+    for tile in [(8, 2, 13, 0), (4, 1, 5, 0), (8, 1, 5, 32), (8, 2, 64, 32), (8, 1, 13, 32),
+                 (8, 2, 7, 32), (8, 1, 1, 32), (16, 1, 9, 32), (16, 2, 20, 32)]:
         got, _ = _run(shape, so, nbl, nt, fields, dt, init=init, tile=tile)
         for a, b in zip(got, ref):
             assert rel_l2(a, b) <= 1e-6, tile
+
+
+def test_tti_one_kernel_matches_oracle_with_sources_and_receivers():
+    """The one-kernel step (tile flag 32) against the oracle over several
+    steps with a source, receivers and the damping layer on a grid whose x
+    and y extents are not tile multiples (so 8; 64- and 32-wide tiles)."""
+    shape, so, nbl, nt = (30, 19, 70), 8, 5, 8
+    fields = _fields(shape, 88)
+    dt = synth.tti_stable_dt(so, 10.0, 4500.0, 0.3)
+    init = [synth.smooth_state(shape, s, 3.0) for s in (11, 12, 13, 14)]
+    rng = np.random.default_rng(12)
+    src = np.stack([rng.uniform(10, (s - 2) * 10.0, 3) for s in shape], 1)
+    rec = np.stack([rng.uniform(10, (s - 2) * 10.0, 25) for s in shape], 1)
+    q = (rng.standard_normal((nt, 3)) * 1e4).astype(np.float32)
+    o_out, od = _oracle(shape, so, nbl, nt, fields, dt, src, q, rec, init)
+    for tile in [(8, 1, 64, 32), (16, 1, 11, 32)]:
+        g_out, gd = _run(shape, so, nbl, nt, fields, dt, src, q, rec, init, tile=tile)
+        for k in (0, 2):
+            assert rel_l2(g_out[k], o_out[k]) <= 1e-5, (tile, k)
+        assert rel_l2(gd, od) <= 1e-5, tile
 
 
 @pytest.mark.slow
