@@ -146,6 +146,7 @@ struct ConvArgs {
     const float *scale;       // EPI_OUT: s = scale[0] (NULL = 1)
     float gain;               // EPI_OUT: out = base + gain * s * y
     nn_box skip;              // EPI_OUT: no correction inside (empty = none)
+    int znb;                  // output planes per block (set by the launcher)
 };
 
 __device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
@@ -207,7 +208,7 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
 }
 
 // z-marching implicit-GEMM 3x3x3 convolution.  A block owns a 32 x 8 column
-// tile and marches over ZNB output planes.  Input planes (tile plus a 1-point
+// tile and marches over znb output planes.  Input planes (tile plus a 1-point
 // ring, channels-last BF16) live in a 4-slot LDS ring: planes z-1, z, z+1
 // feed output plane z while plane z+2 is loaded into registers under the
 // MFMAs and stored into the free slot afterwards (one barrier per plane).
@@ -216,7 +217,7 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
 // each row an STEPS-deep chain of v_mfma_f32_16x16x32_bf16 with A = the
 // weights (registers, M = 16 output channels) and B = 8 consecutive K values
 // of the row's 16 points (LDS).
-constexpr int ZX = 32, ZY = 8, ZHX = ZX + 2, ZHY = ZY + 2, ZNB = 16;
+constexpr int ZX = 32, ZY = 8, ZHX = ZX + 2, ZHY = ZY + 2;
 
 template <int CIN, int STEPS, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
     b /= ntx;
     const int ty = b % nty;
     const int zc = b / nty;
-    const int x0 = tx * ZX, y0 = ty * ZY, z0 = zc * ZNB, z1 = min(z0 + ZNB, a.nz);
+    const int x0 = tx * ZX, y0 = ty * ZY, z0 = zc * a.znb, z1 = min(z0 + a.znb, a.nz);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, g = lane >> 4;
 
@@ -337,11 +338,40 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
     }
 }
 
+// The z chunk: each block marches znb + 2 input planes for znb outputs, and
+// the blocks that fit on the device at once (the kernel's occupancy, one
+// wave per SIMD per block) run in rounds; the chunk minimises rounds x
+// (znb + 2).  Deep chunks on few blocks leave most of the device's block
+// slots empty: the march is latency-bound per block (one barrier per plane).
 template <int CIN, int STEPS, int EPI>
-static int conv(const ConvArgs &a, hipStream_t s)
+static int conv(const ConvArgs &a0, hipStream_t s)
 {
-    const int nb = ((a.nx + ZX - 1) / ZX) * ((a.ny + ZY - 1) / ZY) * ((a.nz + ZNB - 1) / ZNB);
-    hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI>), dim3(nb), dim3(256), 0, s, a);
+    static int slots = 0;                       // blocks resident on the device
+    if (slots == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<CIN, STEPS, EPI>, 256,
+                                                         0) != hipSuccess ||
+            cus <= 0 || per_cu <= 0)
+            return set_error(FD_EDEVICE, "nn conv: occupancy query failed");
+        slots = cus * per_cu;
+    }
+    const int64_t tiles = (int64_t)((a0.nx + ZX - 1) / ZX) * ((a0.ny + ZY - 1) / ZY);
+    int best = 16;
+    int64_t best_cost = INT64_MAX;
+    for (int znb = 1; znb <= 32; ++znb) {
+        const int64_t nb = tiles * ((a0.nz + znb - 1) / znb);
+        const int64_t cost = ((nb + slots - 1) / slots) * (int64_t)(std::min(znb, a0.nz) + 2);
+        if (cost < best_cost || (cost == best_cost && znb > best)) {
+            best_cost = cost;
+            best = znb;
+        }
+    }
+    ConvArgs a = a0;
+    a.znb = best;
+    const int64_t nb = tiles * ((a.nz + best - 1) / best);
+    hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI>), dim3((unsigned)nb), dim3(256), 0, s, a);
     return check_launch("nn conv");
 }
 
