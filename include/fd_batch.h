@@ -60,7 +60,11 @@ int fd_batch_set_geometry(fd_batch *b, int shot, const double *src_m, int ns,
  * FD_EUNSTABLE if max(v) > vmax. */
 int fd_batch_set_model(fd_batch *b, const float *vel_full_dev, void *stream);
 
-/* One gradient of J = 1/2 sum_s |d_s - dobs_s|^2 with respect to velocity.
+/* One gradient of J = 1/2 sum_s |d_s - dobs_s|^2 with respect to velocity
+ * (forward with checkpoints; per segment the recomputation, whose steps
+ * also store the imaging factor (u+ - 2u + u-)/dt^2 + gamma (u+ - u-)/(2 dt)
+ * of each update, and the adjoint steps, which apply the imaging condition
+ * g -= lambda D to the adjoint field they read).
  *   q_dev[s]     [nt][ns_s] source signatures
  *   dobs_dev[s]  [nt][nr_s] observed traces
  *   d_dev[s]     [nt][nr_s] output: modelled traces
@@ -73,16 +77,17 @@ int fd_batch_gradient(fd_batch *b, const float *const *q_dev, const float *const
                       float *const *d_dev, float *grad_v_dev, void *stream);
 
 /* Apply a tile and flags (see fd_set_tile, 128-wide tiles included) to the
- * batched step kernel; invalidates the captured graph.  The default is
- * (4, 4, 32) with flag 4 (non-temporal hints only): on the 16-shot
- * gradient the halo-ring variants measured 17-28 % slower. */
+ * batched step kernel; invalidates the captured graph.  Every batched step
+ * runs the buffer-addressed halo-ring body, so flags 1 (XCD remap), 4
+ * (non-temporal hints) and 16 (128-wide tiles) matter and 2 and 8 do not.
+ * The default is (8, 2, 32) with flags 12 (the tile the autotuner picks
+ * for the 16-shot gradient). */
 int fd_batch_set_tile(fd_batch *b, int by, int ry, int nzb, int flags);
 
-/* Autotuner of the batched step (the row's "tile shapes and z-blocking
- * picked by the project's own autotuner"; the paper's problem-setup section
- * tunes loop blocking per run): a timed search over tile shapes (by, ry),
- * z chunks of 16, 32 or 64 planes and flag sets (none, non-temporal hints,
- * halo ring, both, 128-wide with both, XCD remap with hints), each candidate
+/* Autotuner of the batched step (the paper's problem-setup section tunes
+ * loop blocking per run): a timed search over tile shapes (by, ry), z
+ * chunks of 16, 32 or 64 planes and flag sets (halo ring; with non-temporal
+ * hints; 128-wide with hints; XCD remap with hints), each candidate
  * one launch of the batched step over every shot's aperture on the batch's
  * own forward fields (which the next gradient zeroes); the fastest is
  * applied with fd_batch_set_tile (so the next gradient captures its graph

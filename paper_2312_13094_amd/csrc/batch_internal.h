@@ -36,25 +36,44 @@ struct BatchShot {
     float *d;               // [nt][nr]
 };
 
+// What a batched step does besides the update (workspace field slots):
+// mode 0 nothing; mode 1 (recomputed forward step) writes the imaging factor
+// D of its update to field fd; mode 2 (adjoint step) applies the imaging
+// condition g -= lambda D to field fg, with lambda its input field and D
+// read from field fd.
+struct BatchEpi {
+    int mode = 0;
+    int fd = 0, fg = 0;
+    float inv_dt2 = 0.0f, inv_2dt = 0.0f;
+};
+
 // batched z-marching step for stencil radius R (k_step_radius.hip)
 template <int R>
 int launch_batch_radius(const BatchShot *shots_dev, int nshots, int total_blocks,
-                        const Tuning &t, int iu, int ium, int iup, hipStream_t s);
+                        const Tuning &t, int iu, int ium, int iup, const BatchEpi &e,
+                        hipStream_t s);
 
 // launchers (k_batch.hip)
 int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, int r,
-                      const Tuning &t, int iu, int ium, int iup, hipStream_t s);
+                      const Tuning &t, int iu, int ium, int iup, hipStream_t s,
+                      const BatchEpi &e = BatchEpi{});
 // mode 0: inject sources q[n] into field f and sample receivers into d[n]
-// mode 1: inject sources q[n] into field f only
+// mode 1: inject sources q[n] into field f only, and when fd >= 0 add the
+//         injected amounts' share of the imaging factor (times
+//         inv_dt2 + gamma inv_2dt) to field fd
 // mode 2: inject residuals d[n] - dobs[n] at the receivers into field f
 int launch_batch_sparse(const BatchShot *shots_dev, int nshots, int mode, int n, int f,
-                        float hinv, hipStream_t s);
+                        float hinv, hipStream_t s, int fd = -1, float inv_dt2 = 0.0f,
+                        float inv_2dt = 0.0f);
 int launch_batch_copy(const BatchShot *shots_dev, int nshots, int64_t max_stride, int fsrc,
                       int fdst, hipStream_t s);
 int launch_batch_zero(const BatchShot *shots_dev, int nshots, int64_t max_stride, int f,
                       hipStream_t s);
 int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_rows, int flam,
                          int fup, int fu, int fum, float inv_dt2, float inv_2dt, hipStream_t s);
+// g -= lambda D with a stored imaging factor D (field fd)
+int launch_batch_imaging_d(const BatchShot *shots_dev, int nshots, int64_t max_rows, int flam,
+                           int fd, hipStream_t s);
 int launch_batch_reduce(const BatchShot *shots_dev, int nshots, const int64_t full[3],
                         const float *vel_full, float *grad_v, hipStream_t s);
 int launch_batch_vdt2(const BatchShot *shots_dev, int nshots, int64_t max_pts,

@@ -33,7 +33,7 @@ struct fd_batch {
     int64_t full[3] = {0, 0, 0};
     std::vector<ShotHost> sh;
     fd::BatchShot *table = nullptr;
-    fd::Tuning tune{4, 4, 32, fd::kTileNts};
+    fd::Tuning tune{8, 2, 32, fd::kTileRing | fd::kTileNts};
     int total_blocks = 0;
     const float *vel_full = nullptr;
     unsigned *scratch = nullptr;
@@ -144,24 +144,44 @@ int enqueue_schedule(fd_batch *b, float *grad_v, hipStream_t s)
         FD_TRY(launch_batch_sparse(T, ns, 0, n, prev, hinv, s));
         std::swap(cur, prev);
     }
+    // Per checkpoint segment [lo, hi), last segment first: recompute the
+    // forward steps from the checkpoint in two rolling fields (slot0,
+    // slot0 + 1), each step also storing the imaging factor D_n of its
+    // update in slot0 + 2 + (n - lo); then the adjoint steps n = hi-1 .. lo.
+    // The imaging condition g -= lambda_n D_n for n > lo rides on the
+    // adjoint step that reads lambda_n (the next one, n - 1); lambda_lo is
+    // imaged by its own pass before the next segment overwrites the D slots.
     int lam = kLA, lamo = kLB;
+    BatchEpi rec, img;
+    rec.mode = 1;
+    img.mode = 2;
+    img.fg = kGrad;
+    rec.inv_dt2 = img.inv_dt2 = inv_dt2;
+    rec.inv_2dt = img.inv_2dt = inv_2dt;
     for (int j = b->nck - 1; j >= 0; --j) {
         const int lo = j * k, hi = std::min(b->nt, (j + 1) * k);
-        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j, slot0 + 1, s));
-        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j + 1, slot0, s));
+        int cu = slot0 + 1, cp = slot0;
+        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j, cu, s));
+        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j + 1, cp, s));
         for (int i = 0; i < hi - lo; ++i) {
-            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, slot0 + i + 1,
-                                     slot0 + i, slot0 + i + 2, s));
-            FD_TRY(launch_batch_sparse(T, ns, 1, lo + i, slot0 + i + 2, hinv, s));
+            rec.fd = slot0 + 2 + i;
+            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, cu, cp, cp, s, rec));
+            FD_TRY(launch_batch_sparse(T, ns, 1, lo + i, cp, hinv, s, rec.fd, inv_dt2, inv_2dt));
+            std::swap(cu, cp);
         }
         for (int n = hi - 1; n >= lo; --n) {
-            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, lam, lamo, lamo, s));
+            if (n + 1 < hi) {
+                img.fd = slot0 + 2 + (n + 1 - lo);
+                FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, lam, lamo, lamo,
+                                         s, img));
+            } else {
+                FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, lam, lamo, lamo,
+                                         s));
+            }
             FD_TRY(launch_batch_sparse(T, ns, 2, n, lamo, hinv, s));
             std::swap(lam, lamo);
-            const int i = n - lo;
-            FD_TRY(launch_batch_imaging(T, ns, b->max_rows, lam, slot0 + i + 2, slot0 + i + 1,
-                                        slot0 + i, inv_dt2, inv_2dt, s));
         }
+        FD_TRY(launch_batch_imaging_d(T, ns, b->max_rows, lam, slot0 + 2, s));
     }
     FD_TRY(launch_batch_reduce(T, ns, b->full, b->vel_full, grad_v, s));
 #undef FD_TRY
@@ -321,8 +341,10 @@ int fd_batch_autotune(fd_batch *b, const char *cache_path, int *out4, double *ms
         rc = set_error(FD_EDEVICE, "fd_batch_autotune: event creation failed");
     const int cand[7][2] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 2}, {8, 4}, {2, 8}};
     const int nzbs[3] = {16, 32, 64};
-    const int flagsets[6] = {0, kTileNts, kTileRing, kTileRing | kTileNts,
-                             kTileWide | kTileRing | kTileNts, kTileXcd | kTileNts};
+    // every batched variant takes the halo-ring body, so the flag sets differ
+    // in the non-temporal hints, the 128-wide tile and the XCD remap
+    const int flagsets[4] = {kTileRing, kTileRing | kTileNts, kTileWide | kTileRing | kTileNts,
+                             kTileXcd | kTileRing | kTileNts};
     double best_ms = 1e30;
     auto time_one = [&](float *ms) -> int {
         layout_blocks(b);
@@ -345,7 +367,7 @@ int fd_batch_autotune(fd_batch *b, const char *cache_path, int *out4, double *ms
     };
     for (int ci = 0; ci < 7 && rc == FD_OK; ++ci)
         for (int zi = 0; zi < 3 && rc == FD_OK; ++zi)
-            for (int fi = 0; fi < 6 && rc == FD_OK; ++fi) {
+            for (int fi = 0; fi < 4 && rc == FD_OK; ++fi) {
                 const int *c = cand[ci];
                 const int fl = flagsets[fi];
                 const bool wide_ok = (c[0] == 8 && c[1] == 2) ||

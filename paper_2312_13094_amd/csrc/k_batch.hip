@@ -12,18 +12,18 @@
 namespace fd {
 
 int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, int r,
-                      const Tuning &t, int iu, int ium, int iup, hipStream_t s)
+                      const Tuning &t, int iu, int ium, int iup, hipStream_t s, const BatchEpi &e)
 {
     int rc;
     switch (r) {
-    case 1: rc = launch_batch_radius<1>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 2: rc = launch_batch_radius<2>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 3: rc = launch_batch_radius<3>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 4: rc = launch_batch_radius<4>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 5: rc = launch_batch_radius<5>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 6: rc = launch_batch_radius<6>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 7: rc = launch_batch_radius<7>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
-    case 8: rc = launch_batch_radius<8>(shots_dev, nshots, total_blocks, t, iu, ium, iup, s); break;
+    case 1: rc = launch_batch_radius<1>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 2: rc = launch_batch_radius<2>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 3: rc = launch_batch_radius<3>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 4: rc = launch_batch_radius<4>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 5: rc = launch_batch_radius<5>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 6: rc = launch_batch_radius<6>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 7: rc = launch_batch_radius<7>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
+    case 8: rc = launch_batch_radius<8>(shots_dev, nshots, total_blocks, t, iu, ium, iup, e, s); break;
     default: return set_error(FD_EINVAL, "unsupported stencil radius");
     }
     if (rc) return rc;
@@ -31,9 +31,13 @@ int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, 
 }
 
 // One block per shot: injection (atomics), device fence + barrier, sampling.
+// With fd >= 0 (mode 1) each injected amount also enters the imaging factor
+// of the step it completes: D is linear in u+ with weight
+// 1/dt^2 + gamma/(2 dt).
 __global__ __launch_bounds__(256) void k_batch_sparse(const BatchShot *__restrict__ shots,
                                                       const int mode, const int n, const int f,
-                                                      const float hinv)
+                                                      const float hinv, const int fd,
+                                                      const float inv_dt2, const float inv_2dt)
 {
     const BatchShot &S = shots[blockIdx.x];
     const StepParams &p = S.p;
@@ -55,7 +59,10 @@ __global__ __launch_bounds__(256) void k_batch_sparse(const BatchShot *__restric
                                   : S.q[(int64_t)n * S.ns + pt];
         const int64_t i = p.offset + (int64_t)z * PZ + (int64_t)y * PY + x;
         const float a = damp_a(p, z, y, x);
-        atomicAdd(u + i, scale * w * val * vdt2[i] / (1.0f + a));
+        const float amt = scale * w * val * vdt2[i] / (1.0f + a);
+        atomicAdd(u + i, amt);
+        if (fd >= 0)
+            atomicAdd(S.base + fd * S.stride + i, amt * (inv_dt2 + (a / p.half_dt) * inv_2dt));
     }
     if (mode != 0) return;
     __threadfence();
@@ -73,9 +80,10 @@ __global__ __launch_bounds__(256) void k_batch_sparse(const BatchShot *__restric
 }
 
 int launch_batch_sparse(const BatchShot *shots_dev, int nshots, int mode, int n, int f,
-                        float hinv, hipStream_t s)
+                        float hinv, hipStream_t s, int fd, float inv_dt2, float inv_2dt)
 {
-    hipLaunchKernelGGL(k_batch_sparse, dim3(nshots), dim3(256), 0, s, shots_dev, mode, n, f, hinv);
+    hipLaunchKernelGGL(k_batch_sparse, dim3(nshots), dim3(256), 0, s, shots_dev, mode, n, f, hinv,
+                       mode == 1 ? fd : -1, inv_dt2, inv_2dt);
     return check_launch("batched sparse");
 }
 
@@ -164,6 +172,39 @@ int launch_batch_imaging(const BatchShot *shots_dev, int nshots, int64_t max_row
     hipLaunchKernelGGL(k_batch_imaging, dim3(nb, nshots), dim3(64, kImgRows), 0, s, shots_dev,
                        flam, fup, fu, fum, inv_dt2, inv_2dt);
     return check_launch("batched imaging");
+}
+
+// g -= lambda D, D the imaging factor a recomputed step stored: the same
+// row mapping as k_batch_imaging, three streamed operands instead of five.
+__global__ __launch_bounds__(64 * kImgRows) void k_batch_imaging_d(
+    const BatchShot *__restrict__ shots, const int flam, const int fd)
+{
+    const BatchShot &S = shots[blockIdx.y];
+    const StepParams &p = S.p;
+    const int nrows = p.nz * p.ny;
+    const float *lam = S.base + flam * S.stride, *dd = S.base + fd * S.stride;
+    float *g = S.base + kGrad * S.stride;
+    for (int row = blockIdx.x * kImgRows + threadIdx.y; row < nrows;
+         row += gridDim.x * kImgRows) {
+        const int z = row / p.ny, y = row - z * p.ny;
+        const int64_t j0 = p.offset + (int64_t)z * p.pitch_z + (int64_t)y * p.pitch_y;
+        for (int x = threadIdx.x; x < p.nx; x += 64) {
+            const int64_t j = j0 + x;
+            const float l = __builtin_nontemporal_load(lam + j);
+            const float d = __builtin_nontemporal_load(dd + j);
+            const float gj = __builtin_nontemporal_load(g + j);
+            __builtin_nontemporal_store(gj - l * d, g + j);
+        }
+    }
+}
+
+int launch_batch_imaging_d(const BatchShot *shots_dev, int nshots, int64_t max_rows, int flam,
+                           int fd, hipStream_t s)
+{
+    const int nb = (int)std::min<int64_t>((max_rows + kImgRows - 1) / kImgRows, 65535);
+    hipLaunchKernelGGL(k_batch_imaging_d, dim3(nb, nshots), dim3(64, kImgRows), 0, s, shots_dev,
+                       flam, fd);
+    return check_launch("batched imaging (stored factor)");
 }
 
 // Full-model gradient: for each point, add the shots covering it in shot

@@ -10,8 +10,10 @@
 // with one 16-byte LDS read (8 channels of one neighbour point) from a
 // 10 x 10 x 18-point halo tile, while the A fragments (weights) of all K
 // steps stay in registers for the whole block.  Epilogues are fused: bias +
-// GELU (keeping the pre-activation for training), the residual update of
-// the coarse wavefield, or the GELU derivative of the data gradient.
+// GELU (keeping the pre-activation for training) or the GELU derivative of
+// the data gradient.  The output layer (16 channels -> 1) runs on the vector
+// ALU with BF16 dot products instead (k_conv_out_valu), with the residual
+// update of the coarse wavefield fused.
 //
 // Weight gradients contract over points: M = output channels, N = input
 // channels, K = 32 points along x; the tiles are staged channel-major in
@@ -128,24 +130,24 @@ __global__ __launch_bounds__(256) void k_pack_weights(const float *__restrict__ 
 // ---------------------------------------------------------------------------
 // implicit-GEMM 3x3x3 convolution
 // ---------------------------------------------------------------------------
-enum Epi { EPI_GELU = 0, EPI_GELU_Z = 1, EPI_OUT = 2, EPI_DGRAD = 3 };
+enum Epi { EPI_GELU = 0, EPI_GELU_Z = 1, EPI_DGRAD = 3 };
 
 
 struct ConvArgs {
     int nz, ny, nx;
     const uint16_t *in;       // channels-last [n][CIN]
     const uint16_t *frag;     // STEPS x 64 lanes x 8 BF16
-    const float *bias;        // 16 (EPI_GELU*), 1 (EPI_OUT), NULL (EPI_DGRAD)
+    const float *bias;        // 16 (EPI_GELU*), 1 (output layer), NULL (EPI_DGRAD)
     uint16_t *a16;            // GELU output
     uint16_t *z16;            // pre-activation out (EPI_GELU_Z) / previous z in (EPI_DGRAD)
-    float *ydense;            // EPI_OUT: dense y (may be NULL)
-    const float *base;        // EPI_OUT: residual base (may be NULL with out NULL)
+    float *ydense;            // output layer: dense y (may be NULL)
+    const float *base;        // output layer: residual base (may be NULL with out NULL)
     nn_view vbase;
     float *out;
     nn_view vout;
-    const float *scale;       // EPI_OUT: s = scale[0] (NULL = 1)
-    float gain;               // EPI_OUT: out = base + gain * s * y
-    nn_box skip;              // EPI_OUT: no correction inside (empty = none)
+    const float *scale;       // output layer: s = scale[0] (NULL = 1)
+    float gain;               // output layer: out = base + gain * s * y
+    nn_box skip;              // output layer: no correction inside (empty = none)
     int znb;                  // output planes per block (set by the launcher)
 };
 
@@ -162,48 +164,33 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
                                          const int y, const int z, const int g,
                                          const float *bias4)
 {
-    {
-        if (x >= a.nx || y >= a.ny || z >= a.nz) return;
-        const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
-        if (EPI == EPI_OUT) {
-            if (g == 0) {
-                const float yv = acc[0] + bias4[0];
-                if (a.ydense) a.ydense[p] = yv;
-                if (a.out) {
-                    const float s = a.gain * (a.scale ? a.scale[0] : 1.0f);
-                    const int64_t ib = a.vbase.offset + z * a.vbase.pitch_z + y * a.vbase.pitch_y + x;
-                    const int64_t io = a.vout.offset + z * a.vout.pitch_z + y * a.vout.pitch_y + x;
-                    a.out[io] = in_box(a.skip, z, y, x) ? a.base[ib] : a.base[ib] + s * yv;
-                }
-            }
-        } else {
-            uint16_t o[4];
-            if (EPI == EPI_DGRAD) {
-                const uint2 zp = *reinterpret_cast<const uint2 *>(a.z16 + p * 16 + 4 * g);
-                const uint16_t zz[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
-                                        (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
+    if (x >= a.nx || y >= a.ny || z >= a.nz) return;
+    const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
+    uint16_t o[4];
+    if (EPI == EPI_DGRAD) {
+        const uint2 zp = *reinterpret_cast<const uint2 *>(a.z16 + p * 16 + 4 * g);
+        const uint16_t zz[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
+                                (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) o[j] = f2bf(acc[j] * gelu_grad(bf2f(zz[j])));
-                *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
-                    make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
-            } else {
-                uint16_t zo[4];
+        for (int j = 0; j < 4; ++j) o[j] = f2bf(acc[j] * gelu_grad(bf2f(zz[j])));
+        *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
+            make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+    } else {
+        uint16_t zo[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float zv = acc[j] + bias4[j];
-                    const uint16_t zb = f2bf(zv);
-                    zo[j] = zb;
-                    // GELU of the stored (BF16) pre-activation, so training and
-                    // its backward see the same value
-                    o[j] = f2bf(gelu(bf2f(zb)));
-                }
-                *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
-                    make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
-                if (EPI == EPI_GELU_Z)
-                    *reinterpret_cast<uint2 *>(a.z16 + p * 16 + 4 * g) =
-                        make_uint2(zo[0] | ((uint32_t)zo[1] << 16), zo[2] | ((uint32_t)zo[3] << 16));
-            }
+        for (int j = 0; j < 4; ++j) {
+            const float zv = acc[j] + bias4[j];
+            const uint16_t zb = f2bf(zv);
+            zo[j] = zb;
+            // GELU of the stored (BF16) pre-activation, so training and its
+            // backward see the same value
+            o[j] = f2bf(gelu(bf2f(zb)));
         }
+        *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
+            make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+        if (EPI == EPI_GELU_Z)
+            *reinterpret_cast<uint2 *>(a.z16 + p * 16 + 4 * g) =
+                make_uint2(zo[0] | ((uint32_t)zo[1] << 16), zo[2] | ((uint32_t)zo[3] << 16));
     }
 }
 
@@ -245,8 +232,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 
     // this lane's biases (output channels 4g..4g+3; channel 0 for layer 3)
     float bias4[4] = {0.f, 0.f, 0.f, 0.f};
-    if (EPI == EPI_OUT) bias4[0] = a.bias[0];
-    else if (EPI != EPI_DGRAD)
+    if (EPI != EPI_DGRAD)
 #pragma unroll
         for (int j = 0; j < 4; ++j) bias4[j] = a.bias[4 * g + j];
 
@@ -343,36 +329,193 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 // wave per SIMD per block) run in rounds; the chunk minimises rounds x
 // (znb + 2).  Deep chunks on few blocks leave most of the device's block
 // slots empty: the march is latency-bound per block (one barrier per plane).
-template <int CIN, int STEPS, int EPI>
-static int conv(const ConvArgs &a0, hipStream_t s)
+static int pick_znb(int64_t tiles, int nz, int slots)
 {
-    static int slots = 0;                       // blocks resident on the device
-    if (slots == 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv<CIN, STEPS, EPI>, 256,
-                                                         0) != hipSuccess ||
-            cus <= 0 || per_cu <= 0)
-            return set_error(FD_EDEVICE, "nn conv: occupancy query failed");
-        slots = cus * per_cu;
-    }
-    const int64_t tiles = (int64_t)((a0.nx + ZX - 1) / ZX) * ((a0.ny + ZY - 1) / ZY);
     int best = 16;
     int64_t best_cost = INT64_MAX;
     for (int znb = 1; znb <= 32; ++znb) {
-        const int64_t nb = tiles * ((a0.nz + znb - 1) / znb);
-        const int64_t cost = ((nb + slots - 1) / slots) * (int64_t)(std::min(znb, a0.nz) + 2);
+        const int64_t nb = tiles * ((nz + znb - 1) / znb);
+        const int64_t cost = ((nb + slots - 1) / slots) * (int64_t)(std::min(znb, nz) + 2);
         if (cost < best_cost || (cost == best_cost && znb > best)) {
             best_cost = cost;
             best = znb;
         }
     }
+    return best;
+}
+
+// blocks of 256 threads of kernel k resident on the device at once
+template <typename K>
+static int device_slots(K k, int *slots)
+{
+    if (*slots > 0) return FD_OK;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+        return set_error(FD_EDEVICE, "nn conv: occupancy query failed");
+    *slots = cus * per_cu;
+    return FD_OK;
+}
+
+template <int CIN, int STEPS, int EPI>
+static int conv(const ConvArgs &a0, hipStream_t s)
+{
+    static int slots = 0;
+    if (const int rc = device_slots(k_conv<CIN, STEPS, EPI>, &slots)) return rc;
+    const int64_t tiles = (int64_t)((a0.nx + ZX - 1) / ZX) * ((a0.ny + ZY - 1) / ZY);
     ConvArgs a = a0;
-    a.znb = best;
-    const int64_t nb = tiles * ((a.nz + best - 1) / best);
+    a.znb = pick_znb(tiles, a.nz, slots);
+    const int64_t nb = tiles * ((a.nz + a.znb - 1) / a.znb);
     hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI>), dim3((unsigned)nb), dim3(256), 0, s, a);
     return check_launch("nn conv");
+}
+
+// Layer 3 (16 channels -> 1) on the vector ALU: on the matrix cores its one
+// output channel would fill 1 of 16 MFMA rows.  Two lanes share an output
+// point (channels 0-7 and 8-15) and accumulate v_dot2 products of BF16
+// channel pairs in FP32; each lane keeps the BF16 weights of its 8 channels
+// for all 27 taps in registers (108 pairs, read from the layer's packed
+// MFMA fragments, output channel 0).  A block of 256 threads owns a 32 x 4
+// column tile and marches over a z chunk: every input plane (tile + 1-point
+// ring, channels-last, zero outside the volume) is staged once in LDS, and
+// its 9 in-plane taps feed the three output planes it touches through a
+// ring of three accumulators.  The next plane's loads are in flight while
+// the current one is consumed; one barrier per plane.
+constexpr int VX = 32, VY = 4, VHX = VX + 2, VHY = VY + 2, VCH = VHY * VHX * 2;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t w, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a),
+                                           __builtin_bit_cast(bf16x2, w), c, false);
+}
+
+__global__ __launch_bounds__(256) void k_conv_out_valu(const ConvArgs a)
+{
+    __shared__ uint4 pl[2][VCH];
+    const int ntx = (a.nx + VX - 1) / VX, nty = (a.ny + VY - 1) / VY;
+    int b = blockIdx.x;
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty;
+    const int zc = b / nty;
+    const int x0 = tx * VX, y0 = ty * VY, z0 = zc * a.znb, z1 = min(z0 + a.znb, a.nz);
+    const int tid = threadIdx.x, half = tid & 1, pt = tid >> 1;
+    const int lx = pt % VX, ly = pt / VX;
+    const int x = x0 + lx, y = y0 + ly;
+
+    // weights of channels 8 half + 2q, +1 at tap t: element k = 16 t + c of
+    // output channel 0 sits in fragment step k / 32, lane group (k % 32) / 8,
+    // slot k % 8 of the packed layer-3 fragments
+    const uint32_t *wp = reinterpret_cast<const uint32_t *>(a.frag);
+    uint32_t w[27][4];
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 16 * t + 8 * half + 2 * q;
+            w[t][q] = wp[((k / 32) * 512 + ((k % 32) / 8) * 128 + (k % 8)) / 2];
+        }
+    const float bias = a.bias[0];
+    const float gs = a.out ? a.gain * (a.scale ? a.scale[0] : 1.0f) : 0.0f;
+
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
+    constexpr int NIT = (VCH + 255) / 256;
+    // two register sets of staged planes: plane p travels in set (p - z0) & 1
+    // from its load, issued three planes ahead, to its store into LDS
+    uint4 sa[NIT], sb[NIT];
+    auto load = [&](uint4 *stg, const int zz) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * 256;
+            const int p = c >> 1;
+            const int gx = x0 - 1 + p % VHX, gy = y0 - 1 + p / VHX;
+            stg[it] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < VCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny)
+                stg[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * 2 + (c & 1)];
+        }
+    };
+    auto store = [&](const uint4 *stg, const int buf) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * 256;
+            if (c < VCH) pl[buf][c] = stg[it];
+        }
+    };
+
+    // running sums of output planes zi (a_c) and zi - 1 (a_m) before input
+    // plane zi is added
+    float a_c = 0.0f, a_m = 0.0f;
+    // input plane zi: its taps, the finished output plane zi - 1, then plane
+    // zi + 1 (register set stg) into the other LDS buffer and plane zi + 3
+    // into the freed set
+    auto plane = [&](const int zi, uint4 *stg) {
+        const int cb = (zi - z0 + 1) & 1;
+        const uint4 *P = pl[cb];
+        // contributions to outputs zi + 1 (taps dz = -1), zi (dz = 0) and
+        // zi - 1 (dz = +1), one partial sum per channel pair so that twelve
+        // independent chains hide the dot product's latency
+        float sp[4] = {0.f, 0.f, 0.f, 0.f}, sc[4] = {0.f, 0.f, 0.f, 0.f},
+              sm[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const uint4 v = P[((ly + dy) * VHX + lx + dx) * 2 + half];
+                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+                const int t = dy * 3 + dx;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sp[q] = dot2(vv[q], w[t][q], sp[q]);
+                    sc[q] = dot2(vv[q], w[9 + t][q], sc[q]);
+                    sm[q] = dot2(vv[q], w[18 + t][q], sm[q]);
+                }
+            }
+        const float dp = (sp[0] + sp[1]) + (sp[2] + sp[3]);
+        const float dc = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+        const float dm = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        const float done = a_m + dm;                 // output plane zi - 1 is complete
+        a_m = a_c + dc;
+        a_c = dp;
+        const float yv = done + __shfl_xor(done, 1) + bias;
+        const int zo = zi - 1;
+        if (zo >= z0 && half == 0 && x < a.nx && y < a.ny) {
+            const int64_t p = ((int64_t)zo * a.ny + y) * a.nx + x;
+            if (a.ydense) a.ydense[p] = yv;
+            if (a.out) {
+                const int64_t ib = a.vbase.offset + zo * a.vbase.pitch_z + y * a.vbase.pitch_y + x;
+                const int64_t io = a.vout.offset + zo * a.vout.pitch_z + y * a.vout.pitch_y + x;
+                a.out[io] = in_box(a.skip, zo, y, x) ? a.base[ib] : a.base[ib] + gs * yv;
+            }
+        }
+        if (zi + 1 <= z1) store(stg, cb ^ 1);        // slot of plane zi - 1, consumed
+        __syncthreads();
+        if (zi + 3 <= z1) load(stg, zi + 3);
+    };
+
+    load(sa, z0 - 1);
+    store(sa, 0);
+    __syncthreads();
+    load(sa, z0);
+    load(sb, z0 + 1);
+    for (int zi = z0 - 1; zi <= z1; zi += 2) {
+        plane(zi, sa);                               // stores plane zi + 1 (set a)
+        if (zi + 1 <= z1) plane(zi + 1, sb);
+    }
+}
+
+static int conv_out_valu(const ConvArgs &a0, hipStream_t s)
+{
+    static int slots = 0;
+    if (const int rc = device_slots(k_conv_out_valu, &slots)) return rc;
+    const int64_t tiles = (int64_t)((a0.nx + VX - 1) / VX) * ((a0.ny + VY - 1) / VY);
+    ConvArgs a = a0;
+    a.znb = pick_znb(tiles, a.nz, slots);
+    const int64_t nb = tiles * ((a.nz + a.znb - 1) / a.znb);
+    hipLaunchKernelGGL(k_conv_out_valu, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return check_launch("nn conv (output layer)");
 }
 
 // ---------------------------------------------------------------------------
@@ -798,7 +941,7 @@ int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_
     a.scale = scale_dev;
     a.gain = gain;
     a.skip = skip ? *skip : nn_box{{0, 0, 0}, {0, 0, 0}};
-    return conv<16, 14, EPI_OUT>(a, (hipStream_t)stream);
+    return conv_out_valu(a, (hipStream_t)stream);
 }
 
 int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,

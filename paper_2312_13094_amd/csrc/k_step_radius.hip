@@ -102,12 +102,14 @@ int launch_zmarch_radius(const fd_grid *g, const StepParams &p, const Tuning &t,
     return FD_OK;
 }
 
-template <int R, int BY, int RY, int PF, bool NTS, bool RING, int CX = 1>
+// Batched step: every variant takes the buffer-addressed body (halo ring);
+// EPI selects the gradient schedule's extra work (StepImaging in zmarch.h).
+template <int R, int BY, int RY, bool NTS, int CX, int EPI>
 __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__restrict__ shots,
                                                           const int nshots, const int total,
                                                           const int iu, const int ium,
                                                           const int iup, const int nzb,
-                                                          const int remap)
+                                                          const int remap, const BatchEpi e)
 {
     __shared__ float lds[ZTile<R, BY, RY, CX>::LDS];
     int b = blockIdx.x;
@@ -124,59 +126,60 @@ __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__res
     const int zc = lb / S.nty;
     float *base = S.base;
     const int64_t st = S.stride;
-    if (RING)
-        zmarch_buf_body<R, BY, RY, NTS, CX>(base + iu * st, base + ium * st, base + iup * st,
-                                            base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
-    else
-        zmarch_body<R, BY, RY, PF, NTS>(base + iu * st, base + ium * st, base + iup * st,
-                                        base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds);
+    const StepImaging img{base + e.fd * st, base + e.fg * st, e.inv_dt2, e.inv_2dt};
+    zmarch_buf_body<R, BY, RY, NTS, CX, EPI>(base + iu * st, base + ium * st, base + iup * st,
+                                             base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds, img);
 }
 
-template <int R, int BY, int RY, int PF, bool NTS, bool RING, int CX = 1>
+template <int R, int BY, int RY, bool NTS, int CX>
 static void batch_step_v(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
-                         int ium, int iup, hipStream_t s)
+                         int ium, int iup, const BatchEpi &e, hipStream_t s)
 {
     const int remap = (t.flags & kTileXcd) ? 1 : 0;
     const unsigned nb = remap ? (unsigned)((total + 7) / 8 * 8) : (unsigned)total;
-    hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, PF, NTS, RING, CX>), dim3(nb), dim3(64, BY), 0, s,
-                       shots, nshots, total, iu, ium, iup, t.nzb, remap);
+    const dim3 g(nb), blk(64, BY);
+    if (e.mode == 1)
+        hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, NTS, CX, 1>), g, blk, 0, s, shots, nshots,
+                           total, iu, ium, iup, t.nzb, remap, e);
+    else if (e.mode == 2)
+        hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, NTS, CX, 2>), g, blk, 0, s, shots, nshots,
+                           total, iu, ium, iup, t.nzb, remap, e);
+    else
+        hipLaunchKernelGGL((k_batch_zmarch<R, BY, RY, NTS, CX, 0>), g, blk, 0, s, shots, nshots,
+                           total, iu, ium, iup, t.nzb, remap, e);
 }
 
 template <int R, int BY, int RY>
 static bool batch_step(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
-                       int ium, int iup, hipStream_t s)
+                       int ium, int iup, const BatchEpi &e, hipStream_t s)
 {
-    const bool pf2 = t.flags & kTilePf2, nts = t.flags & kTileNts, ring = t.flags & kTileRing;
+    const bool nts = t.flags & kTileNts;
     if (t.flags & kTileWide) {
         // 128-wide tiles (fd_batch_set_tile admits only these shapes)
         if constexpr ((BY == 8 && RY == 2) || (BY == 4 && (RY == 2 || RY == 4))) {
-            if (nts) batch_step_v<R, BY, RY, 1, true, true, 2>(shots, nshots, total, t, iu, ium, iup, s);
-            else batch_step_v<R, BY, RY, 1, false, true, 2>(shots, nshots, total, t, iu, ium, iup, s);
+            if (nts) batch_step_v<R, BY, RY, true, 2>(shots, nshots, total, t, iu, ium, iup, e, s);
+            else batch_step_v<R, BY, RY, false, 2>(shots, nshots, total, t, iu, ium, iup, e, s);
             return true;
         }
         return false;
     }
-    if (ring && nts) batch_step_v<R, BY, RY, 1, true, true>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (ring) batch_step_v<R, BY, RY, 1, false, true>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (pf2 && nts) batch_step_v<R, BY, RY, 2, true, false>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (pf2) batch_step_v<R, BY, RY, 2, false, false>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (nts) batch_step_v<R, BY, RY, 1, true, false>(shots, nshots, total, t, iu, ium, iup, s);
-    else batch_step_v<R, BY, RY, 1, false, false>(shots, nshots, total, t, iu, ium, iup, s);
+    if (nts) batch_step_v<R, BY, RY, true, 1>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else batch_step_v<R, BY, RY, false, 1>(shots, nshots, total, t, iu, ium, iup, e, s);
     return true;
 }
 
 template <int R>
 int launch_batch_radius(const BatchShot *shots, int nshots, int total, const Tuning &t, int iu,
-                        int ium, int iup, hipStream_t s)
+                        int ium, int iup, const BatchEpi &e, hipStream_t s)
 {
     bool ok = false;
-    if (t.by == 4 && t.ry == 4) ok = batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 2) ok = batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 8) ok = batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 8 && t.ry == 2) ok = batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 8 && t.ry == 4) ok = batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 2 && t.ry == 8) ok = batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, s);
-    else if (t.by == 4 && t.ry == 1) ok = batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, s);
+    if (t.by == 4 && t.ry == 4) ok = batch_step<R, 4, 4>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else if (t.by == 4 && t.ry == 2) ok = batch_step<R, 4, 2>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else if (t.by == 4 && t.ry == 8) ok = batch_step<R, 4, 8>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else if (t.by == 8 && t.ry == 2) ok = batch_step<R, 8, 2>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else if (t.by == 8 && t.ry == 4) ok = batch_step<R, 8, 4>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else if (t.by == 2 && t.ry == 8) ok = batch_step<R, 2, 8>(shots, nshots, total, t, iu, ium, iup, e, s);
+    else if (t.by == 4 && t.ry == 1) ok = batch_step<R, 4, 1>(shots, nshots, total, t, iu, ium, iup, e, s);
     if (!ok) return set_error(FD_EINVAL, "unsupported tile shape");
     return FD_OK;
 }
@@ -184,6 +187,6 @@ int launch_batch_radius(const BatchShot *shots, int nshots, int total, const Tun
 template int launch_zmarch_radius<FD_RADIUS>(const fd_grid *, const StepParams &, const Tuning &,
                                              const float *, const float *, float *, hipStream_t);
 template int launch_batch_radius<FD_RADIUS>(const BatchShot *, int, int, const Tuning &, int, int,
-                                            int, hipStream_t);
+                                            int, const BatchEpi &, hipStream_t);
 
 }  // namespace fd

@@ -241,11 +241,23 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, AUX);
 }
 
-template <int R, int BY, int RY, bool NTS, int CX = 1>
+// Extra per-point work of a batched gradient's steps (template EPI of
+// zmarch_buf_body): EPI 1, a recomputed forward step also writes the
+// imaging factor of its update, D = (u+ - 2u + u-)/dt^2 + gamma (u+ - u-)/(2 dt),
+// to field d; EPI 2, an adjoint step also applies the imaging condition to
+// its input field lambda with a stored D: g -= lambda D.
+struct StepImaging {
+    float *d;
+    float *g;
+    float inv_dt2, inv_2dt;
+};
+
+template <int R, int BY, int RY, bool NTS, int CX = 1, int EPI = 0>
 __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, const float *um,
                                                 float *up, const float *__restrict__ vdt2,
                                                 const StepParams &p, const int tx, const int ty,
-                                                const int zc, const int nzb, float *lds)
+                                                const int zc, const int nzb, float *lds,
+                                                const StepImaging img = StepImaging{})
 {
     constexpr int TX = 64 * CX, TY = BY * RY, LX = TX + 2 * R, LY = TY + 2 * R;
     constexpr int NT = 64 * BY;
@@ -264,6 +276,7 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
     const int PY = (int)p.pitch_y;
     const PlaneBuf Bu = plane_buf(u, p, R), Bm = plane_buf(um, p, R), Bv = plane_buf(vdt2, p, R),
                    Bp = plane_buf(up, p, R);
+    const PlaneBuf Bd = plane_buf(EPI ? img.d : up, p, R), Bg = plane_buf(EPI == 2 ? img.g : up, p, R);
     // byte offset of in-plane point (y, x) from the plane descriptor's base
     auto boff = [&](const int y, const int x) -> uint32_t {
         return (uint32_t)(((y + R) * PY + (x + R)) * (int)sizeof(float));
@@ -327,7 +340,7 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
 #pragma unroll
     for (int d = 0; d < NR; ++d)
         if (z0 + d < z1) load_halo(z0 + d, d);
-    float nf[CX][RY], nm[CX][RY], nv[CX][RY];
+    float nf[CX][RY], nm[CX][RY], nv[CX][RY], nd[CX][RY], ng[CX][RY];
     auto prefetch = [&](const int z) {
         const __amdgpu_buffer_rsrc_t rf = Bu.at(z + R), rm = Bm.at(z), rv = Bv.at(z);
 #pragma unroll
@@ -338,6 +351,16 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                 nm[c][j] = bload<NTA>(rm, ow[c][j]);
                 nv[c][j] = bload<NTA>(rv, ow[c][j]);
             }
+        if constexpr (EPI == 2) {
+            const __amdgpu_buffer_rsrc_t rd = Bd.at(z), rg = Bg.at(z);
+#pragma unroll
+            for (int c = 0; c < CX; ++c)
+#pragma unroll
+                for (int j = 0; j < RY; ++j) {
+                    nd[c][j] = bload<NTA>(rd, ow[c][j]);
+                    ng[c][j] = bload<NTA>(rg, ow[c][j]);
+                }
+        }
     };
     if (z0 < z1) prefetch(z0);
 
@@ -350,7 +373,7 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
         for (int d = 0; d < NR; ++d) {
             const int z = zb + d;
             if (z < z1) {
-                float cm[CX][RY], cv[CX][RY];
+                float cm[CX][RY], cv[CX][RY], cd[CX][RY], cg[CX][RY];
 #pragma unroll
                 for (int c = 0; c < CX; ++c)
 #pragma unroll
@@ -360,6 +383,10 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                         q[c][j][2 * R] = nf[c][j];
                         cm[c][j] = nm[c][j];
                         cv[c][j] = nv[c][j];
+                        if constexpr (EPI == 2) {
+                            cd[c][j] = nd[c][j];
+                            cg[c][j] = ng[c][j];
+                        }
                     }
                 if (z + 1 < z1) prefetch(z + 1);
                 float *t = lds + (z & 1) * (LY * LX);
@@ -395,8 +422,18 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                         const float lap = p.c0 * uc + lz + ly + lx;
                         const int y = yb + j;
                         const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
-                        const float a = p.half_dt * ((az + ax[c]) + ay);
-                        bstore<NTA>(leapfrog_update(uc, cm[c][j], cv[c][j], lap, a), rp, ow[c][j]);
+                        const float gam = (az + ax[c]) + ay;
+                        const float a = p.half_dt * gam;
+                        const float un = leapfrog_update(uc, cm[c][j], cv[c][j], lap, a);
+                        bstore<NTA>(un, rp, ow[c][j]);
+                        if constexpr (EPI == 1) {
+                            const float um1 = cm[c][j];
+                            const float dv = ((un - uc) - (uc - um1)) * img.inv_dt2 +
+                                             gam * (un - um1) * img.inv_2dt;
+                            bstore<NTA>(dv, Bd.at(z), ow[c][j]);
+                        }
+                        if constexpr (EPI == 2)
+                            bstore<NTA>(cg[c][j] - uc * cd[c][j], Bg.at(z), ow[c][j]);
                     }
             }
         }
