@@ -48,6 +48,17 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// two floats -> two BF16 (round to nearest even) in one word, first in the
+// low half: one v_cvt_pk_bf16_f32 on gfx950
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){a, b}, bf16x2v));
+}
+__device__ __forceinline__ float lo_bf(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_bf(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
 // erf(a) for a >= 0 by Abramowitz & Stegun, Handbook of Mathematical
 // Functions, formula 7.1.26 (absolute error <= 1.5e-7): with t = 1/(1 + p a),
 // erf(a) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-a^2).  The
@@ -166,31 +177,21 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
 {
     if (x >= a.nx || y >= a.ny || z >= a.nz) return;
     const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
-    uint16_t o[4];
     if (EPI == EPI_DGRAD) {
         const uint2 zp = *reinterpret_cast<const uint2 *>(a.z16 + p * 16 + 4 * g);
-        const uint16_t zz[4] = {(uint16_t)(zp.x & 0xffff), (uint16_t)(zp.x >> 16),
-                                (uint16_t)(zp.y & 0xffff), (uint16_t)(zp.y >> 16)};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] = f2bf(acc[j] * gelu_grad(bf2f(zz[j])));
         *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
-            make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+            make_uint2(pack_bf16(acc[0] * gelu_grad(lo_bf(zp.x)), acc[1] * gelu_grad(hi_bf(zp.x))),
+                       pack_bf16(acc[2] * gelu_grad(lo_bf(zp.y)), acc[3] * gelu_grad(hi_bf(zp.y))));
     } else {
-        uint16_t zo[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float zv = acc[j] + bias4[j];
-            const uint16_t zb = f2bf(zv);
-            zo[j] = zb;
-            // GELU of the stored (BF16) pre-activation, so training and its
-            // backward see the same value
-            o[j] = f2bf(gelu(bf2f(zb)));
-        }
+        const uint32_t z01 = pack_bf16(acc[0] + bias4[0], acc[1] + bias4[1]);
+        const uint32_t z23 = pack_bf16(acc[2] + bias4[2], acc[3] + bias4[3]);
+        // GELU of the stored (BF16) pre-activation, so training and its
+        // backward see the same value
         *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
-            make_uint2(o[0] | ((uint32_t)o[1] << 16), o[2] | ((uint32_t)o[3] << 16));
+            make_uint2(pack_bf16(gelu(lo_bf(z01)), gelu(hi_bf(z01))),
+                       pack_bf16(gelu(lo_bf(z23)), gelu(hi_bf(z23))));
         if (EPI == EPI_GELU_Z)
-            *reinterpret_cast<uint2 *>(a.z16 + p * 16 + 4 * g) =
-                make_uint2(zo[0] | ((uint32_t)zo[1] << 16), zo[2] | ((uint32_t)zo[3] << 16));
+            *reinterpret_cast<uint2 *>(a.z16 + p * 16 + 4 * g) = make_uint2(z01, z23);
     }
 }
 
