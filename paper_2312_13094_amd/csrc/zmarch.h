@@ -320,14 +320,20 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
         hxs[k] = e < NHX ? (row + R) * LX + lx : -1;
     }
 
-    float q[CX][RY][2 * R + 1];
+    // z queue of each column, NR - 1 slots longer than the 2R + 1 planes the
+    // stencil reads, so that it shifts once per unrolled block of NR planes:
+    // plane d of a block reads q[d .. d + 2R] (centre q[d + R]); its front
+    // q[d + 2R] is loaded during plane d - 1 straight into its slot (into nf
+    // for the block's first plane)
+    constexpr int QL = 2 * R + NR;
+    float q[CX][RY][QL];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) {
         const __amdgpu_buffer_rsrc_t r = Bu.at(z0 - R + k);
 #pragma unroll
         for (int c = 0; c < CX; ++c)
 #pragma unroll
-            for (int j = 0; j < RY; ++j) q[c][j][k + 1] = bload(r, ol[c][j]);
+            for (int j = 0; j < RY; ++j) q[c][j][k] = bload(r, ol[c][j]);
     }
     float hy[NR][HY], hx[NR][HX];
     auto load_halo = [&](const int z, const int d) {
@@ -341,13 +347,13 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
     for (int d = 0; d < NR; ++d)
         if (z0 + d < z1) load_halo(z0 + d, d);
     float nf[CX][RY], nm[CX][RY], nv[CX][RY], nd[CX][RY], ng[CX][RY];
+    // the point operands of plane z (the queue front is loaded by the caller)
     auto prefetch = [&](const int z) {
-        const __amdgpu_buffer_rsrc_t rf = Bu.at(z + R), rm = Bm.at(z), rv = Bv.at(z);
+        const __amdgpu_buffer_rsrc_t rm = Bm.at(z), rv = Bv.at(z);
 #pragma unroll
         for (int c = 0; c < CX; ++c)
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
-                nf[c][j] = bload(rf, ol[c][j]);
                 nm[c][j] = bload<NTA>(rm, ow[c][j]);
                 nv[c][j] = bload<NTA>(rv, ow[c][j]);
             }
@@ -362,7 +368,14 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                 }
         }
     };
-    if (z0 < z1) prefetch(z0);
+    if (z0 < z1) {
+        const __amdgpu_buffer_rsrc_t rf = Bu.at(z0 + R);
+#pragma unroll
+        for (int c = 0; c < CX; ++c)
+#pragma unroll
+            for (int j = 0; j < RY; ++j) nf[c][j] = bload(rf, ol[c][j]);
+        prefetch(z0);
+    }
 
     float ax[CX];
 #pragma unroll
@@ -378,9 +391,7 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                 for (int c = 0; c < CX; ++c)
 #pragma unroll
                     for (int j = 0; j < RY; ++j) {
-#pragma unroll
-                        for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + 1];
-                        q[c][j][2 * R] = nf[c][j];
+                        if (d == 0) q[c][j][2 * R] = nf[c][j];
                         cm[c][j] = nm[c][j];
                         cv[c][j] = nv[c][j];
                         if constexpr (EPI == 2) {
@@ -388,13 +399,24 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                             cg[c][j] = ng[c][j];
                         }
                     }
-                if (z + 1 < z1) prefetch(z + 1);
+                if (z + 1 < z1) {
+                    // front of plane z + 1: its queue slot, or nf across blocks
+                    const __amdgpu_buffer_rsrc_t rf = Bu.at(z + 1 + R);
+#pragma unroll
+                    for (int c = 0; c < CX; ++c)
+#pragma unroll
+                        for (int j = 0; j < RY; ++j) {
+                            if (d + 1 < NR) q[c][j][2 * R + d + 1] = bload(rf, ol[c][j]);
+                            else nf[c][j] = bload(rf, ol[c][j]);
+                        }
+                    prefetch(z + 1);
+                }
                 float *t = lds + (z & 1) * (LY * LX);
 #pragma unroll
                 for (int c = 0; c < CX; ++c)
 #pragma unroll
                     for (int j = 0; j < RY; ++j)
-                        t[(wy * RY + j + R) * LX + lane + 64 * c + R] = q[c][j][R];
+                        t[(wy * RY + j + R) * LX + lane + 64 * c + R] = q[c][j][d + R];
 #pragma unroll
                 for (int k = 0; k < HY; ++k)
                     if (NHY % NT == 0 || tid + k * NT < NHY) t[hys[k]] = hy[d][k];
@@ -414,11 +436,11 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                         float lz = 0.0f, ly = 0.0f, lx = 0.0f;
 #pragma unroll
                         for (int k = 1; k <= R; ++k) {
-                            lz += p.cz[k] * (q[c][j][R + k] + q[c][j][R - k]);
+                            lz += p.cz[k] * (q[c][j][d + R + k] + q[c][j][d + R - k]);
                             ly += p.cy[k] * (cc[k * LX] + cc[-k * LX]);
                             lx += p.cx[k] * (cc[k] + cc[-k]);
                         }
-                        const float uc = q[c][j][R];
+                        const float uc = q[c][j][d + R];
                         const float lap = p.c0 * uc + lz + ly + lx;
                         const int y = yb + j;
                         const float ay = p.nbl > 0 ? sponge_ax(p, 1, y, p.gy) : 0.0f;
@@ -437,6 +459,13 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                     }
             }
         }
+        // the next block's window starts NR planes further
+#pragma unroll
+        for (int c = 0; c < CX; ++c)
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+#pragma unroll
+                for (int k = 0; k < 2 * R; ++k) q[c][j][k] = q[c][j][k + NR];
     }
 }
 
