@@ -74,14 +74,11 @@ __device__ inline float damp_a(const StepParams &p, int z, int y, int x)
 // The damped leapfrog update (appendix "Isotropic acoustic"): given u, u-,
 // v^2 dt^2, the Laplacian and a = gamma dt / 2, returns
 // u + [(1 - a)(u - u-) + v^2 dt^2 lap] / (1 + a).  Every acoustic step kernel
-// goes through this one expression, so they round identically.  The division
-// is the hardware reciprocal (1 ulp) times the numerator: exact where a = 0,
-// outside the damping layer, and a quarter of the vector instructions of an
-// IEEE division in a kernel whose vector ALU is more than half busy.
+// goes through this one expression, so they round identically.
 __device__ __forceinline__ float leapfrog_update(float uc, float um, float vdt2, float lap,
                                                 float a)
 {
-    return uc + ((1.0f - a) * (uc - um) + vdt2 * lap) * __builtin_amdgcn_rcpf(1.0f + a);
+    return uc + ((1.0f - a) * (uc - um) + vdt2 * lap) / (1.0f + a);
 }
 
 // Node (z, y, x) and multilinear weight of corner c of a sparse point's
