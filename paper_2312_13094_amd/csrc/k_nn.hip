@@ -11,9 +11,11 @@
 // 10 x 10 x 18-point halo tile, while the A fragments (weights) of all K
 // steps stay in registers for the whole block.  Epilogues are fused: bias +
 // GELU (keeping the pre-activation for training) or the GELU derivative of
-// the data gradient.  The output layer (16 channels -> 1) runs on the vector
-// ALU with BF16 dot products instead (k_conv_out_valu), with the residual
-// update of the coarse wavefield fused.
+// the data gradient.  The output layer (16 channels -> 1), whose single
+// output channel would fill 1 of 16 rows of that tile, is a per-tap GEMM
+// (points x taps, K = channels) followed by a gather of the 27 tap values of
+// each point's neighbours (k_conv_out_mfma), with the residual update of the
+// coarse wavefield fused.
 //
 // Weight gradients contract over points: M = output channels, N = input
 // channels, K = 32 points along x; the tiles are staged channel-major in
@@ -373,68 +375,69 @@ static int conv(const ConvArgs &a0, hipStream_t s)
     return check_launch("nn conv");
 }
 
-// Layer 3 (16 channels -> 1) on the vector ALU: on the matrix cores its one
-// output channel would fill 1 of 16 MFMA rows.  Two lanes share an output
-// point (channels 0-7 and 8-15) and accumulate v_dot2 products of BF16
-// channel pairs in FP32; each lane keeps the BF16 weights of its 8 channels
-// for all 27 taps in registers (108 pairs, read from the layer's packed
-// MFMA fragments, output channel 0).  A block of 256 threads owns a 32 x 4
-// column tile and marches over a z chunk: every input plane (tile + 1-point
-// ring, channels-last, zero outside the volume) is staged once in LDS, and
-// its 9 in-plane taps feed the three output planes it touches through a
-// ring of three accumulators.  The next plane's loads are in flight while
-// the current one is consumed; one barrier per plane.
-constexpr int VX = 32, VY = 4, VHX = VX + 2, VHY = VY + 2, VCH = VHY * VHX * 2;
-typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+// Layer 3 as a per-tap GEMM on the matrix cores plus a gather.  For every
+// point q of a staged input plane (tile + 1-point ring) and every tap t,
+// Y[q][t] = sum_c a[q][c] w[t][c] (v_mfma_f32_16x16x16_bf16 with M = 16
+// points, N = 16 taps, K = the 16 channels; two MFMAs cover the 27 taps);
+// each output point then adds the 9 in-plane neighbours' Y of the taps of
+// every z offset into a ring of three accumulators (output planes zi + 1,
+// zi, zi - 1), as in the vector version.  The matrix cores do the 432
+// multiply-adds per point; the vector ALU 27 additions.  A block of 256
+// threads owns a 32 x 8 column tile; Y rows are padded to 33 floats so that
+// the gather's lanes hit distinct LDS banks.  (A single staging buffer, 52 KB
+// of LDS and three blocks per CU instead of two, measured 5 % slower.)
+constexpr int QX = 32, QY = 8, QHX = QX + 2, QHY = QY + 2, NQ = QHX * QHY;
+constexpr int NQG = (NQ + 15) / 16, NQP = NQG * 16, QYS = 33;
+typedef short short4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t w, float c)
+__global__ __launch_bounds__(256) void k_conv_out_mfma(const ConvArgs a)
 {
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a),
-                                           __builtin_bit_cast(bf16x2, w), c, false);
-}
-
-__global__ __launch_bounds__(256) void k_conv_out_valu(const ConvArgs a)
-{
-    __shared__ uint4 pl[2][VCH];
-    const int ntx = (a.nx + VX - 1) / VX, nty = (a.ny + VY - 1) / VY;
+    __shared__ uint4 pl[2][NQP * 2];          // staged planes, 2 x 16 B per point
+    __shared__ float yl[NQP * QYS];           // Y of the current input plane
+    const int ntx = (a.nx + QX - 1) / QX, nty = (a.ny + QY - 1) / QY;
     int b = blockIdx.x;
     const int tx = b % ntx;
     b /= ntx;
     const int ty = b % nty;
     const int zc = b / nty;
-    const int x0 = tx * VX, y0 = ty * VY, z0 = zc * a.znb, z1 = min(z0 + a.znb, a.nz);
-    const int tid = threadIdx.x, half = tid & 1, pt = tid >> 1;
-    const int lx = pt % VX, ly = pt / VX;
+    const int x0 = tx * QX, y0 = ty * QY, z0 = zc * a.znb, z1 = min(z0 + a.znb, a.nz);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lx = tid % QX, ly = tid / QX;
     const int x = x0 + lx, y = y0 + ly;
 
-    // weights of channels 8 half + 2q, +1 at tap t: element k = 16 t + c of
-    // output channel 0 sits in fragment step k / 32, lane group (k % 32) / 8,
-    // slot k % 8 of the packed layer-3 fragments
-    const uint32_t *wp = reinterpret_cast<const uint32_t *>(a.frag);
-    uint32_t w[27][4];
+    // B operand: taps (lane & 15) + 16 h, channels 4 (lane >> 4) .. + 3; the
+    // BF16 weight of tap t, channel c is element k = 16 t + c of output
+    // channel 0 in the packed layer-3 fragments
+    short4v wb[2];
 #pragma unroll
-    for (int t = 0; t < 27; ++t)
+    for (int h = 0; h < 2; ++h) {
+        const int t = (lane & 15) + 16 * h;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = 16 * t + 8 * half + 2 * q;
-            w[t][q] = wp[((k / 32) * 512 + ((k % 32) / 8) * 128 + (k % 8)) / 2];
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * t + 4 * (lane >> 4) + j;
+            wb[h][j] = t < 27 ? (short)a.frag[(k / 32) * 512 + ((k % 32) / 8) * 128 + (k % 8)]
+                              : (short)0;
         }
+    }
     const float bias = a.bias[0];
     const float gs = a.out ? a.gain * (a.scale ? a.scale[0] : 1.0f) : 0.0f;
 
+    // zero the padding points of both staging buffers once
+    for (int c = NQ * 2 + tid; c < NQP * 2; c += 256)
+        pl[0][c] = pl[1][c] = make_uint4(0u, 0u, 0u, 0u);
+
     const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
-    constexpr int NIT = (VCH + 255) / 256;
-    // two register sets of staged planes: plane p travels in set (p - z0) & 1
-    // from its load, issued three planes ahead, to its store into LDS
+    constexpr int NIT = (NQ * 2 + 255) / 256;
     uint4 sa[NIT], sb[NIT];
     auto load = [&](uint4 *stg, const int zz) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int c = tid + it * 256;
             const int p = c >> 1;
-            const int gx = x0 - 1 + p % VHX, gy = y0 - 1 + p / VHX;
+            const int gx = x0 - 1 + p % QHX, gy = y0 - 1 + p / QHX;
             stg[it] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < VCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny)
+            if (c < NQ * 2 && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 &&
+                gy < a.ny)
                 stg[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * 2 + (c & 1)];
         }
     };
@@ -442,47 +445,46 @@ __global__ __launch_bounds__(256) void k_conv_out_valu(const ConvArgs a)
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int c = tid + it * 256;
-            if (c < VCH) pl[buf][c] = stg[it];
+            if (c < NQ * 2) pl[buf][c] = stg[it];
         }
     };
 
-    // running sums of output planes zi (a_c) and zi - 1 (a_m) before input
-    // plane zi is added
-    float a_c = 0.0f, a_m = 0.0f;
-    // input plane zi: its taps, the finished output plane zi - 1, then plane
-    // zi + 1 (register set stg) into the other LDS buffer and plane zi + 3
-    // into the freed set
+    float a_c = 0.0f, a_m = 0.0f;   // running sums of output planes zi and zi - 1
     auto plane = [&](const int zi, uint4 *stg) {
         const int cb = (zi - z0 + 1) & 1;
-        const uint4 *P = pl[cb];
-        // contributions to outputs zi + 1 (taps dz = -1), zi (dz = 0) and
-        // zi - 1 (dz = +1), one partial sum per channel pair so that twelve
-        // independent chains hide the dot product's latency
-        float sp[4] = {0.f, 0.f, 0.f, 0.f}, sc[4] = {0.f, 0.f, 0.f, 0.f},
-              sm[4] = {0.f, 0.f, 0.f, 0.f};
+        const char *P = reinterpret_cast<const char *>(pl[cb]);
+        // Y of every staged point: groups of 16 points dealt to the waves
+        for (int g = wave; g < NQG; g += 4) {
+            const int q = 16 * g + (lane & 15);
+            const short4v av = *reinterpret_cast<const short4v *>(P + q * 32 + (lane >> 4) * 8);
+            const floatx4 y0v = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, wb[0],
+                                                                          floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            const floatx4 y1v = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, wb[1],
+                                                                          floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int qo = 16 * g + 4 * (lane >> 4) + j;
+                yl[qo * QYS + (lane & 15)] = y0v[j];
+                yl[qo * QYS + 16 + (lane & 15)] = y1v[j];
+            }
+        }
+        __syncthreads();
+        // contributions to outputs zi + 1 (taps dz = -1), zi (dz = 0), zi - 1
+        float sp = 0.0f, sc = 0.0f, sm = 0.0f;
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
-                const uint4 v = P[((ly + dy) * VHX + lx + dx) * 2 + half];
-                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
-                const int t = dy * 3 + dx;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    sp[q] = dot2(vv[q], w[t][q], sp[q]);
-                    sc[q] = dot2(vv[q], w[9 + t][q], sc[q]);
-                    sm[q] = dot2(vv[q], w[18 + t][q], sm[q]);
-                }
+                const float *yq = yl + ((ly + dy) * QHX + lx + dx) * QYS + dy * 3 + dx;
+                sp += yq[0];
+                sc += yq[9];
+                sm += yq[18];
             }
-        const float dp = (sp[0] + sp[1]) + (sp[2] + sp[3]);
-        const float dc = (sc[0] + sc[1]) + (sc[2] + sc[3]);
-        const float dm = (sm[0] + sm[1]) + (sm[2] + sm[3]);
-        const float done = a_m + dm;                 // output plane zi - 1 is complete
-        a_m = a_c + dc;
-        a_c = dp;
-        const float yv = done + __shfl_xor(done, 1) + bias;
+        const float yv = a_m + sm + bias;            // output plane zi - 1 is complete
+        a_m = a_c + sc;
+        a_c = sp;
         const int zo = zi - 1;
-        if (zo >= z0 && half == 0 && x < a.nx && y < a.ny) {
+        if (zo >= z0 && x < a.nx && y < a.ny) {
             const int64_t p = ((int64_t)zo * a.ny + y) * a.nx + x;
             if (a.ydense) a.ydense[p] = yv;
             if (a.out) {
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(256) void k_conv_out_valu(const ConvArgs a)
                 a.out[io] = in_box(a.skip, zo, y, x) ? a.base[ib] : a.base[ib] + gs * yv;
             }
         }
-        if (zi + 1 <= z1) store(stg, cb ^ 1);        // slot of plane zi - 1, consumed
+        if (zi + 1 <= z1) store(stg, cb ^ 1);        // buffer of plane zi - 1, consumed
         __syncthreads();
         if (zi + 3 <= z1) load(stg, zi + 3);
     };
@@ -502,22 +504,23 @@ __global__ __launch_bounds__(256) void k_conv_out_valu(const ConvArgs a)
     load(sa, z0);
     load(sb, z0 + 1);
     for (int zi = z0 - 1; zi <= z1; zi += 2) {
-        plane(zi, sa);                               // stores plane zi + 1 (set a)
+        plane(zi, sa);
         if (zi + 1 <= z1) plane(zi + 1, sb);
     }
 }
 
-static int conv_out_valu(const ConvArgs &a0, hipStream_t s)
+static int conv_out_mfma(const ConvArgs &a0, hipStream_t s)
 {
     static int slots = 0;
-    if (const int rc = device_slots(k_conv_out_valu, &slots)) return rc;
-    const int64_t tiles = (int64_t)((a0.nx + VX - 1) / VX) * ((a0.ny + VY - 1) / VY);
+    if (const int rc = device_slots(k_conv_out_mfma, &slots)) return rc;
+    const int64_t tiles = (int64_t)((a0.nx + QX - 1) / QX) * ((a0.ny + QY - 1) / QY);
     ConvArgs a = a0;
     a.znb = pick_znb(tiles, a.nz, slots);
     const int64_t nb = tiles * ((a.nz + a.znb - 1) / a.znb);
-    hipLaunchKernelGGL(k_conv_out_valu, dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_conv_out_mfma, dim3((unsigned)nb), dim3(256), 0, s, a);
     return check_launch("nn conv (output layer)");
 }
+
 
 // ---------------------------------------------------------------------------
 // weight gradient
@@ -942,7 +945,7 @@ int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_
     a.scale = scale_dev;
     a.gain = gain;
     a.skip = skip ? *skip : nn_box{{0, 0, 0}, {0, 0, 0}};
-    return conv_out_valu(a, (hipStream_t)stream);
+    return conv_out_mfma(a, (hipStream_t)stream);
 }
 
 int nn_mse(int nz, int ny, int nx, const float *y_dev, const float *t_dev,
