@@ -142,9 +142,13 @@ int fd_field_layout(const fd_grid *g, fd_layout *out);
  * registers until used; bit 1 is then ignored), bit 4 makes the tile 128
  * columns wide with two columns per lane (with bit 3 behaviour; only for
  * (by, ry) = (8,2) (4,2) (4,4)).  by = 0 selects the
- * one-thread-per-point kernel.  FD_TTI grids use only by = 0 (the
- * one-thread-per-point passes) or not (z-marching passes on a fixed 64 x 16
- * tile with nzb planes per block).  FD_ELASTIC grids: by = 0 selects the
+ * one-thread-per-point kernel.  FD_TTI grids: by = 0 selects the
+ * one-thread-per-point passes; otherwise flags 0 gives the two z-marching
+ * passes on 64 x 16 tiles with nzb planes per block (six vector
+ * intermediates through memory), and flag 32 the whole step in one
+ * z-marching kernel (by = 16 for 32-wide tiles, ry = 2 for two tile columns
+ * per thread up to space order 6); flags 0..63.
+ * FD_ELASTIC grids: by = 0 selects the
  * one-thread-per-point passes, (by, ry) = (4, 2), (8, 1) or (8, 2) the
  * z-marching passes on 64 x (by ry) tiles with nzb planes per block ((8, 2)
  * the default, with the deepest of 256 .. 8 planes giving 1024 blocks;
