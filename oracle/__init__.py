@@ -166,6 +166,19 @@ def sponge_gamma(g: Grid) -> np.ndarray:
     return out.reshape(g.shape)
 
 
+def sponge_gamma_box(g: Grid, lo, hi) -> np.ndarray:
+    """The damping rate of grid g on the box of DOMAIN indices [lo, hi) (one
+    (z, y, x) triple each; 3-D grids), point by point as sponge_gamma: for a
+    window of a larger grid whose own boundary is not the damping layer's."""
+    L = _L()
+    out = np.zeros(tuple(int(h) - int(l) for l, h in zip(lo, hi)))
+    for z in range(lo[0], hi[0]):
+        for y in range(lo[1], hi[1]):
+            for x in range(lo[2], hi[2]):
+                out[z - lo[0], y - lo[1], x - lo[2]] = L.or_sponge_gamma(ctypes.byref(g._c), z, y, x)
+    return out
+
+
 def laplacian(g: Grid, u: np.ndarray) -> np.ndarray:
     u = np.ascontiguousarray(u, dtype=np.float64)
     lap = np.zeros(g.shape)

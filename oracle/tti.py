@@ -108,16 +108,18 @@ def operators(g: Grid, p: np.ndarray, r: np.ndarray, theta, phi, bc: int):
 
 
 def forward(g: Grid, v, eps, delta, theta, phi, src=None, q=None, rec=None, nt=0,
-            p0=None, pm=None, r0=None, rm=None):
+            p0=None, pm=None, r0=None, rm=None, gamma=None):
     """nt leapfrog updates of the TTI system.  Returns
-    (p^nt, p^(nt-1), r^nt, r^(nt-1), d[nt][nr]) with padded fields."""
+    (p^nt, p^(nt-1), r^nt, r^(nt-1), d[nt][nr]) with padded fields.  gamma,
+    if given, is the DOMAIN-shaped damping rate to use instead of g's own
+    layer (a window of a larger grid keeps that grid's damping)."""
     bc = g.bc
     v = np.asarray(v, dtype=np.float64)
     p = g.zeros() if p0 is None else np.array(p0, dtype=np.float64)
     po = g.zeros() if pm is None else np.array(pm, dtype=np.float64)
     r = g.zeros() if r0 is None else np.array(r0, dtype=np.float64)
     ro = g.zeros() if rm is None else np.array(rm, dtype=np.float64)
-    gam = sponge_gamma(g)
+    gam = sponge_gamma(g) if gamma is None else np.asarray(gamma, dtype=np.float64)
     a = 0.5 * g.dt * gam
     c = v * v * g.dt * g.dt
     c_pp = c * (1.0 + 2.0 * np.asarray(eps, dtype=np.float64))

@@ -206,3 +206,49 @@ def test_stability_number():
     """S1 for so 12 (3.6897) from the symbol's peak; so 2 gives 1."""
     assert abs(T.stability_number(2) - 1.0) < 1e-9
     assert abs(T.stability_number(12) - 3.6897) < 1e-3
+
+
+def _window(n, k, w):
+    """Index box of half-width w around k, clipped at the DOMAIN faces."""
+    lo = tuple(max(int(c) - w, 0) for c in k)
+    hi = tuple(min(int(c) + w + 1, s) for c, s in zip(k, n))
+    return lo, hi
+
+
+def test_clipped_window_with_global_damping_equals_whole_grid():
+    """The windowed oracle the 384^3 GPU check uses: one step at a point from
+    a window of half-width 2R around it, clipped at the DOMAIN faces (where
+    the window's zero halo is the grid's own) and carrying the whole grid's
+    damping rate (sponge_gamma_box), equals the whole-grid step there, for
+    points deep inside, inside the damping layer and next to the faces.  A
+    window of half-width R, or one without the whole grid's damping rate,
+    fails it."""
+    shape, so, nbl, h = (26, 24, 28), 6, 5, (10.0, 10.0, 10.0)
+    R = so // 2
+    rng = np.random.default_rng(31)
+    F = {k: rng.uniform(lo, hi, shape) for k, lo, hi in
+         [("v", 1500, 4500), ("eps", 0, 0.3), ("delta", 0, 0.15),
+          ("theta", 0, math.pi / 4), ("phi", 0, math.pi / 4)]}
+    dt = 0.4 * 2.0 / (4500 * math.sqrt(1.6) * math.sqrt(T.stability_number(so) * 3 / 100.0))
+    g = O.Grid(shape, h, so=so, dt=dt, nbl=nbl, vmax=4500.0, bc=0)
+    init = [rng.standard_normal(shape) for _ in range(4)]
+    whole = T.forward(g, F["v"], F["eps"], F["delta"], F["theta"], F["phi"], nt=1,
+                      p0=g.pad(init[0]), pm=g.pad(init[1]), r0=g.pad(init[2]),
+                      rm=g.pad(init[3]))
+    gam = O.sponge_gamma(g)
+    pts = [(13, 12, 14), (2, 12, 14), (13, 21, 3), (0, 0, 27), (25, 23, 0), (7, 1, 22)]
+    for k in pts:
+        lo, hi = _window(shape, k, 2 * R)
+        win = tuple(slice(a, b) for a, b in zip(lo, hi))
+        gw = O.sponge_gamma_box(g, lo, hi)
+        np.testing.assert_array_equal(gw, gam[win])
+        og = O.Grid(tuple(b - a for a, b in zip(lo, hi)), h, so=so, dt=dt, nbl=0,
+                    vmax=4500.0, bc=0)
+        p, _, r, _, _ = T.forward(og, F["v"][win], F["eps"][win], F["delta"][win],
+                                  F["theta"][win], F["phi"][win], nt=1,
+                                  p0=og.pad(init[0][win]), pm=og.pad(init[1][win]),
+                                  r0=og.pad(init[2][win]), rm=og.pad(init[3][win]), gamma=gw)
+        c = tuple(a - b for a, b in zip(k, lo))
+        for got, want in ((og.interior(p)[c], g.interior(whole[0])[k]),
+                          (og.interior(r)[c], g.interior(whole[2])[k])):
+            assert abs(got - want) <= 1e-12 * max(1.0, abs(want)), (k, got, want)
