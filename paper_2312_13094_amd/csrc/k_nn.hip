@@ -203,19 +203,31 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
 // feed output plane z while plane z+2 is loaded into registers under the
 // MFMAs and stored into the free slot afterwards (one barrier per plane).
 // Every input plane is fetched once per column tile instead of with a full
-// 3-D halo per block.  Per plane: 16 rows of 16 points (two per tile row),
-// each row an STEPS-deep chain of v_mfma_f32_16x16x32_bf16 with A = the
-// weights (registers, M = 16 output channels) and B = 8 consecutive K values
-// of the row's 16 points (LDS).
+// 3-D halo per block.  Per plane each wave computes 4 rows of 16 points (tile
+// rows wave/2 + 2j, half wave%2), each row an STEPS-deep chain of
+// v_mfma_f32_16x16x32_bf16 with A = the weights (registers, M = 16 output
+// channels) and B = 8 consecutive K values of the row's 16 points (LDS).
+// The LDS address of a lane's B fragment is fixed per K step up to the ring
+// slot of its tap's z offset: it is precomputed once, the three slot bases
+// are uniform per plane, and the four rows sit at constant offsets, so a
+// fetch costs one address add per step instead of a per-read index
+// computation (which had made the kernel bound by vector ALU work).
 constexpr int ZX = 32, ZY = 8, ZHX = ZX + 2, ZHY = ZY + 2;
 
 template <int CIN, int STEPS, int EPI>
 __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 {
     constexpr int CH = CIN / 8;                 // 16-byte chunks per point
-    constexpr int PLANE = ZHY * ZHX * CIN;      // BF16 per staged plane
+    // staged row pitch: with two chunks per point it is padded to 36 points
+    // so that the bank swizzle (bit 2 of the point index) is the same in
+    // every row a wave reads
+    constexpr int ZHXS = CH == 2 ? 36 : ZHX;
+    constexpr int PLANE = ZHY * ZHXS * CIN;     // BF16 per staged plane
+    constexpr int PB = PLANE * 2;               // bytes per staged plane
     constexpr int NCH = ZHY * ZHX * CH;         // chunks per staged plane
     constexpr int NIT = (NCH + 255) / 256;
+    constexpr int NR = 4;                       // rows per wave and plane
+    constexpr int ROWB = 2 * ZHXS * CIN * 2;    // bytes between a wave's rows
     __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
     const int ntx = (a.nx + ZX - 1) / ZX, nty = (a.ny + ZY - 1) / ZY;
     int b = blockIdx.x;
@@ -253,15 +265,18 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                 stage[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * CH + ch];
         }
     };
-    // with two chunks per point, the chunks of points whose index has bit 2
-    // set are stored swapped, so the 8 lanes served together by a 128-bit
-    // LDS read (8 consecutive points, 32 bytes apart) hit distinct banks
+    // with two chunks per point, the chunks of points whose (padded) index
+    // has bit 2 set are stored swapped, so the 8 lanes served together by a
+    // 128-bit LDS read (8 consecutive points, 32 bytes apart) hit distinct
+    // banks
     auto store_plane = [&](const int zz) {
         uint4 *dst = reinterpret_cast<uint4 *>(ring + (zz & 3) * PLANE);
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int c = tid + it * 256;
-            if (c < NCH) dst[CH == 2 ? (c ^ ((c >> 3) & 1)) : c] = stage[it];
+            const int pt = c / CH, ch = c % CH;
+            const int cc = ((pt / ZHX) * ZHXS + pt % ZHX) * CH + ch;
+            if (c < NCH) dst[CH == 2 ? (cc ^ ((cc >> 3) & 1)) : cc] = stage[it];
         }
     };
 
@@ -273,38 +288,46 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
     store_plane(z0 + 1);
     __syncthreads();
 
-    // per-lane tap geometry of every K step, fixed over the march: ring slot
-    // offset dz (0..2) and the point offset within a staged plane
-    int tdz[STEPS], tpo[STEPS], tc0[STEPS];
+    // per-lane byte offset of the B fragment of every K step within a staged
+    // plane (first row of this wave), and whether the lane's tap lies one z
+    // offset above the step's first tap (steps whose taps straddle two
+    // input planes)
+    uint32_t boff[STEPS];
+    bool zhi[STEPS];
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) {
         const int kb = 32 * s + 8 * g;
         int tap = kb / CIN;
         tap = tap > 26 ? 26 : tap;              // padding steps: zero weights
-        tdz[s] = tap / 9;
-        tpo[s] = ((tap / 3) % 3) * ZHX + tap % 3;
-        tc0[s] = kb % CIN;
+        int t0 = (32 * s) / CIN;
+        t0 = t0 > 26 ? 26 : t0;
+        zhi[s] = tap / 9 != t0 / 9;
+        const int pt = (wave / 2) * ZHXS + (wave % 2) * 16 + n + ((tap / 3) % 3) * ZHXS + tap % 3;
+        const int c0 = kb % CIN;
+        const int cs = CH == 2 ? (c0 ^ (((pt >> 2) & 1) << 3)) : c0;
+        boff[s] = (uint32_t)((pt * CIN + cs) * 2);
     }
-    constexpr int NR = 2;                       // rows per wave and pass, two passes per plane
+    const char *ringb = reinterpret_cast<const char *>(ring);
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 1 < z1;
         if (more) load_plane(z + 2);            // in flight under the MFMAs
-#pragma unroll 1
-        for (int rp = 0; rp < 2; ++rp) {
+        // byte bases of the slots holding input planes z - 1, z, z + 1
+        const uint32_t sb0 = (uint32_t)(((z + 3) & 3) * PB), sb1 = (uint32_t)((z & 3) * PB),
+                       sb2 = (uint32_t)(((z + 1) & 3) * PB);
+        auto slot = [&](const int d) { return d == 0 ? sb0 : (d == 1 ? sb1 : sb2); };
         floatx4 acc[NR];
 #pragma unroll
         for (int j = 0; j < NR; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
         // B fragments of step s+1 are read from LDS while the MFMAs of step s
         // run (two register sets)
         auto fetch = [&](const int s, bf16x8 *bv) {
-            const uint16_t *pl = ring + ((z + tdz[s] - 1) & 3) * PLANE;
+            int d0 = (32 * s) / CIN;
+            d0 = (d0 > 26 ? 26 : d0) / 9;
+            const uint32_t base = d0 < 2 && zhi[s] ? slot(d0 + 1) : slot(d0);
+            const char *p = ringb + base + boff[s];
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const int row = wave + 4 * (2 * rp + j);   // tile row row/2, half row%2
-                const int pt = (row / 2) * ZHX + (row % 2) * 16 + n + tpo[s];
-                const int cs = CIN == 16 ? (tc0[s] ^ (((pt >> 2) & 1) << 3)) : tc0[s];
-                bv[j] = *reinterpret_cast<const bf16x8 *>(pl + pt * CIN + cs);
-            }
+            for (int j = 0; j < NR; ++j)
+                bv[j] = *reinterpret_cast<const bf16x8 *>(p + j * ROWB);
         };
         bf16x8 bq[2][NR];
         fetch(0, bq[0]);
@@ -317,11 +340,8 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                                                                   0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const int row = wave + 4 * (2 * rp + j);
-            epilogue<EPI>(a, acc[j], x0 + (row % 2) * 16 + n, y0 + row / 2, z, g, bias4);
-        }
-        }
+        for (int j = 0; j < NR; ++j)
+            epilogue<EPI>(a, acc[j], x0 + (wave % 2) * 16 + n, y0 + wave / 2 + 2 * j, z, g, bias4);
         if (more) store_plane(z + 2);           // slot of plane z-2, read by nobody now
         __syncthreads();
     }
