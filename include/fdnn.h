@@ -76,6 +76,17 @@ int64_t nn_rms_scratch_floats(void);
 int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const void *packed_dev,
                  const float *params_dev, void *z16_dev, void *a16_dev, void *stream);
 
+/* Layer 1 straight from the three input fields: the same act16 (and z16)
+ * as nn_pack_input(nz, ny, nx, a, va, b, vb, c, vc, c_times_a, scale_dev,
+ * x8) followed by nn_conv_gelu(1, ..., x8, ...), bitwise (the staging forms
+ * each point's packed input with nn_pack_input's arithmetic and rounding),
+ * without writing the packed input: for inference, where nothing else reads
+ * it.  Arguments as in those two calls; the fields are read in place. */
+int nn_conv_gelu_fields(int nz, int ny, int nx, const float *a, nn_view va, const float *b,
+                        nn_view vb, const float *c, nn_view vc, int c_times_a,
+                        const float *scale_dev, const void *packed_dev, const float *params_dev,
+                        void *z16_dev, void *a16_dev, void *stream);
+
 /* Forward layer 3 (16 -> 1): y = conv(a16) + b3.  If y_dense_dev is
  * non-NULL it receives y (dense [nz][ny][nx]); if out_dev is non-NULL,
  * out[vout] = base[vbase] + gain * s * y with s = scale_dev[0] (or 1 if

@@ -162,6 +162,12 @@ struct ConvArgs {
     float gain;               // output layer: out = base + gain * s * y
     nn_box skip;              // output layer: no correction inside (empty = none)
     int znb;                  // output planes per block (set by the launcher)
+    // layer 1 staged straight from three fields (nn_conv_gelu_fields):
+    // (fa sa, fb sa, fc3) as in k_pack_input, sa = 1 / fscale[0] (or 1)
+    const float *fa, *fb, *fc;
+    nn_view fva, fvb, fvc;
+    int fct;                  // fc3 = fc fa sa (else fc)
+    const float *fscale;
 };
 
 __device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
@@ -214,9 +220,10 @@ __device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, 
 // computation (which had made the kernel bound by vector ALU work).
 constexpr int ZX = 32, ZY = 8, ZHX = ZX + 2, ZHY = ZY + 2;
 
-template <int CIN, int STEPS, int EPI>
+template <int CIN, int STEPS, int EPI, bool FIN = false>
 __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 {
+    static_assert(!FIN || CIN == 8, "fields input is layer 1's");
     constexpr int CH = CIN / 8;                 // 16-byte chunks per point
     // staged row pitch: with two chunks per point it is padded to 36 points
     // so that the bank swizzle (bit 2 of the point index) is the same in
@@ -252,8 +259,11 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
         for (int j = 0; j < 4; ++j) bias4[j] = a.bias[4 * g + j];
 
     const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
+    const float inv = FIN && a.fscale ? 1.0f / a.fscale[0] : 1.0f;
     uint4 stage[NIT];
-    // plane zz of the tile + ring into registers (zero outside the volume)
+    // plane zz of the tile + ring into registers (zero outside the volume);
+    // from the three fields, the point's packed input is formed here with
+    // k_pack_input's arithmetic
     auto load_plane = [&](const int zz) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -261,8 +271,17 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
             const int pt = c / CH, ch = c % CH;
             const int gx = x0 - 1 + pt % ZHX, gy = y0 - 1 + pt / ZHX;
             stage[it] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < NCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny)
-                stage[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * CH + ch];
+            if (c < NCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) {
+                if constexpr (FIN) {
+                    const float va_ = a.fa[a.fva.offset + zz * a.fva.pitch_z + gy * a.fva.pitch_y + gx] * inv;
+                    const float vb_ = a.fb[a.fvb.offset + zz * a.fvb.pitch_z + gy * a.fvb.pitch_y + gx] * inv;
+                    const float cv = a.fc[a.fvc.offset + zz * a.fvc.pitch_z + gy * a.fvc.pitch_y + gx];
+                    const float vc_ = a.fct ? cv * va_ : cv;
+                    stage[it] = make_uint4(f2bf(va_) | ((uint32_t)f2bf(vb_) << 16), f2bf(vc_), 0u, 0u);
+                } else {
+                    stage[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * CH + ch];
+                }
+            }
         }
     };
     // with two chunks per point, the chunks of points whose (padded) index
@@ -382,16 +401,16 @@ static int device_slots(K k, int *slots)
     return FD_OK;
 }
 
-template <int CIN, int STEPS, int EPI>
+template <int CIN, int STEPS, int EPI, bool FIN = false>
 static int conv(const ConvArgs &a0, hipStream_t s)
 {
     static int slots = 0;
-    if (const int rc = device_slots(k_conv<CIN, STEPS, EPI>, &slots)) return rc;
+    if (const int rc = device_slots(k_conv<CIN, STEPS, EPI, FIN>, &slots)) return rc;
     const int64_t tiles = (int64_t)((a0.nx + ZX - 1) / ZX) * ((a0.ny + ZY - 1) / ZY);
     ConvArgs a = a0;
     a.znb = pick_znb(tiles, a.nz, slots);
     const int64_t nb = tiles * ((a.nz + a.znb - 1) / a.znb);
-    hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_conv<CIN, STEPS, EPI, FIN>), dim3((unsigned)nb), dim3(256), 0, s, a);
     return check_launch("nn conv");
 }
 
@@ -940,6 +959,33 @@ int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const voi
     a.frag = pk + kF2 * 512;
     a.bias = params_dev + kB2;
     return z16_dev ? conv<16, 14, EPI_GELU_Z>(a, s) : conv<16, 14, EPI_GELU>(a, s);
+}
+
+int nn_conv_gelu_fields(int nz, int ny, int nx, const float *a, nn_view va, const float *b,
+                        nn_view vb, const float *c, nn_view vc, int c_times_a,
+                        const float *scale_dev, const void *packed_dev, const float *params_dev,
+                        void *z16_dev, void *a16_dev, void *stream)
+{
+    if (bad_shape(nz, ny, nx) || !a || !b || !c || !packed_dev || !params_dev || !a16_dev)
+        return set_error(FD_EINVAL, "nn_conv_gelu_fields: bad argument");
+    ConvArgs g{};
+    g.nz = nz;
+    g.ny = ny;
+    g.nx = nx;
+    g.fa = a;
+    g.fb = b;
+    g.fc = c;
+    g.fva = va;
+    g.fvb = vb;
+    g.fvc = vc;
+    g.fct = c_times_a ? 1 : 0;
+    g.fscale = scale_dev;
+    g.a16 = (uint16_t *)a16_dev;
+    g.z16 = (uint16_t *)z16_dev;
+    g.frag = (const uint16_t *)packed_dev + kF1 * 512;
+    g.bias = params_dev + kB1;
+    hipStream_t s = (hipStream_t)stream;
+    return z16_dev ? conv<8, 7, EPI_GELU_Z, true>(g, s) : conv<8, 7, EPI_GELU, true>(g, s);
 }
 
 int nn_conv_out(int nz, int ny, int nx, const void *a16_dev, const void *packed_dev,

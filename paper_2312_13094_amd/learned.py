@@ -182,10 +182,10 @@ class LearnedCorrector:
         """new <- new + k s N(new/s, old/s, vhat new/s) outside B, s = rms(new)."""
         net = self.net
         net.rms(new, self.cview)
-        net.pack_input(new, self.cview, old, self.cview, self.vhat, self.dview,
-                       scale=net.scale, c_times_a=True)
+        # layer 1 forms the network input (new/s, old/s, vhat new/s) itself
         net.forward(keep=False, out=new, base=new, vbase=self.cview, vout=self.cview,
-                    scale=net.scale, ydense=False, gain=self.GAIN, skip=self.skip)
+                    scale=net.scale, ydense=False, gain=self.GAIN, skip=self.skip,
+                    fields=(new, self.cview, old, self.cview, self.vhat, self.dview, True))
 
     def _corrected_run(self, d, hist):
         """The whole corrected coarse run from rest: traces into d, the RMS of

@@ -60,6 +60,8 @@ def lib():
         L.nn_pack_input.argtypes = [i, i, i, vp, View, vp, View, vp, View, i, vp, vp, vp]
         L.nn_rms.argtypes = [i, i, i, vp, View, vp, vp, vp]
         L.nn_conv_gelu.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp]
+        L.nn_conv_gelu_fields.argtypes = [i, i, i, vp, View, vp, View, vp, View, i, vp, vp, vp,
+                                          vp, vp, vp]
         bp = ctypes.POINTER(Box)
         L.nn_conv_out.argtypes = [i, i, i, vp, vp, vp, vp, vp, View, vp, View, vp, f, bp, vp]
         L.nn_mse.argtypes = [i, i, i, vp, vp, vp, f, bp, vp, vp, vp]
@@ -171,12 +173,21 @@ class Net:
         _chk(lib().nn_rms(nz, ny, nx, _p(u), vu, _p(self.scale), _p(self.flag), _s()))
 
     def forward(self, keep=True, out=None, base=None, vbase=None, vout=None, scale=None,
-                ydense=True, gain=1.0, skip=None):
-        """Layers 1-3 on self.x8.  keep: store pre-activations (training)."""
+                ydense=True, gain=1.0, skip=None, fields=None):
+        """Layers 1-3 on self.x8, or, with fields = (a, va, b, vb, c, vc,
+        c_times_a), on the input pack_input(a, va, b, vb, c, vc, scale,
+        c_times_a) would write, formed inside layer 1 (bitwise the same).
+        keep: store pre-activations (training)."""
         nz, ny, nx = self.shape
         L = lib()
-        _chk(L.nn_conv_gelu(1, nz, ny, nx, _p(self.x8), _p(self.packed), _p(self.params),
-                            _p(self.z1) if keep else None, _p(self.a1), _s()))
+        if fields is None:
+            _chk(L.nn_conv_gelu(1, nz, ny, nx, _p(self.x8), _p(self.packed), _p(self.params),
+                                _p(self.z1) if keep else None, _p(self.a1), _s()))
+        else:
+            a, va, b, vb, c, vc, cta = fields
+            _chk(L.nn_conv_gelu_fields(nz, ny, nx, _p(a), va, _p(b), vb, _p(c), vc, int(cta),
+                                       _p(scale), _p(self.packed), _p(self.params),
+                                       _p(self.z1) if keep else None, _p(self.a1), _s()))
         _chk(L.nn_conv_gelu(2, nz, ny, nx, _p(self.a1), _p(self.packed), _p(self.params),
                             _p(self.z2) if keep else None, _p(self.a2), _s()))
         dv = dense_view(self.shape)

@@ -174,6 +174,42 @@ def test_pack_input_modulated_channel(shape):
     assert np.all(x[2][3] == 0.0) and np.all(x[3:] == 0.0)
 
 
+def test_layer1_from_fields_equals_pack_then_conv(shape):
+    """nn_conv_gelu_fields (layer 1 forming its input from three fields, two
+    of them read through a padded view) writes bitwise the pre-activations
+    and activations of nn_pack_input followed by nn_conv_gelu(1), and so the
+    same layer-3 output."""
+    import torch
+    from paper_2312_13094_amd import nn
+    net = _net(_params(), shape)
+    a, b, c = _input(shape, 12)
+    dv = nn.dense_view(shape)
+    nz, ny, nx = shape
+    pad = (nz + 4, ny + 4, nx + 9)
+
+    def padded(v):
+        P = np.zeros(pad, np.float32)
+        P[2:2 + nz, 2:2 + ny, 3:3 + nx] = v
+        return torch.from_numpy(P).cuda()
+
+    pv = nn.View(2 * pad[1] * pad[2] + 2 * pad[2] + 3, pad[2], pad[1] * pad[2])
+    pa, pb = padded(a), padded(b)
+    tc = torch.from_numpy(np.ascontiguousarray(c, dtype=np.float32)).cuda()
+    scale = torch.zeros(int(nn.lib().nn_rms_scratch_floats()), device="cuda")
+    scale[0] = 2.7
+    net.pack_input(pa, pv, pb, pv, tc, dv, scale=scale, c_times_a=True)
+    net.forward(keep=True, ydense=True)
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (net.z1, net.a1, net.y)]
+    for t in (net.z1, net.a1, net.y):
+        t.zero_()
+    net.forward(keep=True, ydense=True, scale=scale, fields=(pa, pv, pb, pv, tc, dv, True))
+    torch.cuda.synchronize()
+    for got, w in zip((net.z1, net.a1, net.y), want):
+        assert torch.equal(got, w)
+    assert float(want[2].abs().max()) > 0
+
+
 @pytest.mark.parametrize("layer", [1, 2, 3])
 def test_weight_gradients_match_oracle(layer, shape):
     import torch
