@@ -260,6 +260,19 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 
     const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
     const float inv = FIN && a.fscale ? 1.0f / a.fscale[0] : 1.0f;
+    // fields input: in-plane element offsets of this thread's staged points
+    // (fixed over the march)
+    int64_t foa[FIN ? NIT : 1], fob[FIN ? NIT : 1], foc[FIN ? NIT : 1];
+    if constexpr (FIN) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int c = tid + it * 256;
+            const int gx = x0 - 1 + c % ZHX, gy = y0 - 1 + c / ZHX;
+            foa[it] = a.fva.offset + gy * a.fva.pitch_y + gx;
+            fob[it] = a.fvb.offset + gy * a.fvb.pitch_y + gx;
+            foc[it] = a.fvc.offset + gy * a.fvc.pitch_y + gx;
+        }
+    }
     uint4 stage[NIT];
     // plane zz of the tile + ring into registers (zero outside the volume);
     // from the three fields, the point's packed input is formed here with
@@ -273,11 +286,14 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
             stage[it] = make_uint4(0u, 0u, 0u, 0u);
             if (c < NCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) {
                 if constexpr (FIN) {
-                    const float va_ = a.fa[a.fva.offset + zz * a.fva.pitch_z + gy * a.fva.pitch_y + gx] * inv;
-                    const float vb_ = a.fb[a.fvb.offset + zz * a.fvb.pitch_z + gy * a.fvb.pitch_y + gx] * inv;
-                    const float cv = a.fc[a.fvc.offset + zz * a.fvc.pitch_z + gy * a.fvc.pitch_y + gx];
+                    // k_pack_input's products; the packed conversion rounds
+                    // to nearest even as f2bf does (they differ only in the
+                    // bits of a NaN)
+                    const float va_ = a.fa[foa[it] + zz * a.fva.pitch_z] * inv;
+                    const float vb_ = a.fb[fob[it] + zz * a.fvb.pitch_z] * inv;
+                    const float cv = a.fc[foc[it] + zz * a.fvc.pitch_z];
                     const float vc_ = a.fct ? cv * va_ : cv;
-                    stage[it] = make_uint4(f2bf(va_) | ((uint32_t)f2bf(vb_) << 16), f2bf(vc_), 0u, 0u);
+                    stage[it] = make_uint4(pack_bf16(va_, vb_), pack_bf16(vc_, 0.0f), 0u, 0u);
                 } else {
                     stage[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * CH + ch];
                 }
