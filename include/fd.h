@@ -272,6 +272,16 @@ int fd_forward(fd_grid *g, float *const *state_dev,
 int fd_step(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src,
             const float *q_dev, const fd_sparse *rec, float *d_dev, void *stream);
 
+/* fd_step with the receivers one level behind (paper, "Sparse data"
+ * paragraph): the same update and injection, but rec samples u_dev (u^n, the
+ * level this update reads, after its halo refresh) into d_dev, in the same
+ * launch that injects src into the new level.  For callers that change each
+ * new level before it is recorded (a correction applied after the update):
+ * they sample it as the next update's input, and the last level with
+ * fd_sample.  Same arguments, errors and allocation behaviour as fd_step. */
+int fd_step_lagged(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src,
+                   const float *q_dev, const fd_sparse *rec, float *d_dev, void *stream);
+
 /* Adjoint (exact transpose of fd_forward, acoustic): the same recurrence
  * run backwards in time, receivers injecting the residual resid[nt][nr]
  * (scaled by v^2 dt^2 / (1 + gamma dt/2), no cell-volume factor) and

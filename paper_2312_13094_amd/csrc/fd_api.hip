@@ -759,6 +759,29 @@ int fd_step(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src, co
     return launch_sparse(g, um_up_dev, inj, smp, s);
 }
 
+int fd_step_lagged(fd_grid *g, float *u_dev, float *um_up_dev, const fd_sparse *src,
+                   const float *q_dev, const fd_sparse *rec, float *d_dev, void *stream)
+{
+    if (!g || !u_dev || !um_up_dev || u_dev == um_up_dev)
+        return set_error(FD_EINVAL, "fd_step_lagged: bad argument");
+    if (g->d.physics != FD_ACOUSTIC)
+        return set_error(FD_ENOTSUP, "fd_step_lagged: acoustic physics only");
+    if (!g->model_loaded) return set_error(FD_EINVAL, "fd_step_lagged: no model loaded");
+    int rc = validate_sparse(g, src, q_dev, "sources");
+    if (rc) return rc;
+    if ((rc = validate_sparse(g, rec, d_dev, "receivers"))) return rc;
+    DeviceGuard dg(g->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    SparseArgs inj{src ? src->n : 0, src ? src->base_dev : nullptr, src ? src->frac_dev : nullptr,
+                   src && src->n ? q_dev : nullptr, nullptr, (float)(1.0 / cell_volume(g))};
+    SparseArgs smp{rec ? rec->n : 0, rec ? rec->base_dev : nullptr, rec ? rec->frac_dev : nullptr,
+                   nullptr, rec && rec->n ? d_dev : nullptr, 1.0f};
+    if ((rc = exchange_and_step(g, u_dev, um_up_dev, um_up_dev, s))) return rc;
+    // u^n is a finished field the update only read: one launch injects into
+    // the new level and samples it
+    return launch_sparse_split(g, um_up_dev, inj, u_dev, smp, s);
+}
+
 int fd_adjoint(fd_grid *g, float *const *state_dev, const fd_sparse *rec, const float *resid_dev,
                const fd_sparse *src, const float *q_dev, float *qadj_dev, int nt,
                float *const *ckpt_dev, int ckpt_every, float *const *slot_dev, float *grad_m_dev,

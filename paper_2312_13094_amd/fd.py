@@ -75,6 +75,7 @@ def lib():
     L.fd_adjoint.argtypes = [vp, P(vp), P(SparseC), vp, P(SparseC), vp, vp, i, P(vp), i, P(vp),
                              vp, vp]
     L.fd_step.argtypes = [vp, vp, vp, P(SparseC), vp, P(SparseC), vp, vp]
+    L.fd_step_lagged.argtypes = [vp, vp, vp, P(SparseC), vp, P(SparseC), vp, vp]
     L.fd_gradient_to_velocity.argtypes = [vp, vp, vp, vp]
     L.fd_sample.argtypes = [vp, vp, P(SparseC), vp, vp]
     L.fd_autotune.argtypes = [vp, ctypes.c_char_p, P(ctypes.c_int), P(ctypes.c_double), vp]
@@ -268,10 +269,12 @@ class Grid:
             _ptr_array(slots, k + 2 if grad_m is not None and k >= 1 else 0, "slots"),
             _ptr(grad_m), _stream(self.device)))
 
-    def step(self, u, um_up, src=None, q=None, rec=None, d=None):
+    def step(self, u, um_up, src=None, q=None, rec=None, d=None, lagged=False):
         """One update in place: um_up (u^(n-1)) becomes u^(n+1); q, d are this
-        update's source values and receiver outputs."""
-        _check(lib().fd_step(
+        update's source values and receiver outputs (lagged: d records u, the
+        level the update reads, instead of the new one)."""
+        fn = lib().fd_step_lagged if lagged else lib().fd_step
+        _check(fn(
             self.handle, _ptr(u), _ptr(um_up), ctypes.byref(src.c) if src else None, _ptr(q),
             ctypes.byref(rec.c) if rec else None, _ptr(d), _stream(self.device)))
 

@@ -178,31 +178,42 @@ class LearnedCorrector:
         """Plain coarse update n in place: um_up (u(n-1)) becomes u~(n+1)."""
         self.coarse.step(u, um_up, self.Sc, self.qc[n])
 
-    def correct(self, new, old):
-        """new <- new + k s N(new/s, old/s, vhat new/s) outside B, s = rms(new)."""
+    def correct(self, new, old, scale=None):
+        """new <- new + k s N(new/s, old/s, vhat new/s) outside B, s = rms(new)
+        (computed into scale, nn_rms_scratch_floats() floats; the network's own
+        buffer if None)."""
         net = self.net
-        net.rms(new, self.cview)
+        sc = net.scale if scale is None else scale
+        net.rms(new, self.cview, sc)
         # layer 1 forms the network input (new/s, old/s, vhat new/s) itself
         net.forward(keep=False, out=new, base=new, vbase=self.cview, vout=self.cview,
-                    scale=net.scale, ydense=False, gain=self.GAIN, skip=self.skip,
+                    scale=sc, ydense=False, gain=self.GAIN, skip=self.skip,
                     fields=(new, self.cview, old, self.cview, self.vhat, self.dview, True))
+
+    def _scales(self):
+        """One RMS buffer per coarse step: row n's first value is then the RMS
+        of prediction n, the history the guard reads, with no copy."""
+        return torch.zeros((self.cfg.nt_coarse, int(NN.lib().nn_rms_scratch_floats())),
+                           dtype=torch.float32, device=self.dev)
 
     def _corrected_run(self, d, hist):
         """The whole corrected coarse run from rest: traces into d, the RMS of
-        every coarse prediction into hist, non-finite values flagged in
-        net.flag.  Enqueues only (no host synchronisation), so it can be
-        captured into a graph."""
+        coarse prediction n into hist[n, 0] (hist from _scales), non-finite
+        values flagged in net.flag.  Enqueues only (no host synchronisation),
+        so it can be captured into a graph."""
         c = self.cfg
         self.ca.zero_()
         self.cb.zero_()
         self.net.flag.zero_()
         u, um = self.ca, self.cb
         for n in range(c.nt_coarse):
-            self.coarse_step(n, u, um)
-            self.correct(um, u)
-            hist[n:n + 1].copy_(self.net.scale[:1])
-            self.coarse.sample(um, self.Rc, d[n])
+            # the update's launch that injects the source also records the
+            # corrected level it reads (the previous update's)
+            self.coarse.step(u, um, self.Sc, self.qc[n], self.Rc if n else None,
+                             d[n - 1] if n else None, lagged=True)
+            self.correct(um, u, hist[n])
             u, um = um, u
+        self.coarse.sample(u, self.Rc, d[c.nt_coarse - 1])
 
     def learned_solve(self, guard=True, graph=False):
         """Corrected coarse run; falls back to the plain fine solve if the
@@ -218,7 +229,7 @@ class LearnedCorrector:
             if getattr(self, "_graph", None) is None:
                 self._gd = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32,
                                        device=self.dev)
-                self._gh = torch.zeros(c.nt_coarse, dtype=torch.float32, device=self.dev)
+                self._gh = self._scales()
                 torch.cuda.synchronize()
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g):
@@ -231,14 +242,14 @@ class LearnedCorrector:
             self._graph.replay()
         else:
             d = torch.zeros((c.nt_coarse, self.Rc.n), dtype=torch.float32, device=self.dev)
-            hist = torch.zeros(c.nt_coarse, dtype=torch.float32, device=self.dev)
+            hist = self._scales()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             self._corrected_run(d, hist)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         tr = d.double().cpu().numpy()
-        h = hist.cpu().numpy()
+        h = hist[:, 0].cpu().numpy()
         q = (3 * len(h)) // 4
         growth = len(h) > 4 and h[q:].max() > 2.0 * h[:q].max()
         bad = bool(self.net.flag.item()) or not np.isfinite(tr).all() or not np.isfinite(h).all()

@@ -168,9 +168,12 @@ class Net:
         _chk(lib().nn_pack_input(nz, ny, nx, _p(a), va, _p(b), vb, _p(c), vc, int(c_times_a),
                                  _p(scale), _p(self.x8), _s()))
 
-    def rms(self, u, vu):
+    def rms(self, u, vu, scale=None):
+        """RMS of u into scale[0] (scale: nn_rms_scratch_floats() floats;
+        self.scale if None)."""
         nz, ny, nx = self.shape
-        _chk(lib().nn_rms(nz, ny, nx, _p(u), vu, _p(self.scale), _p(self.flag), _s()))
+        _chk(lib().nn_rms(nz, ny, nx, _p(u), vu, _p(self.scale if scale is None else scale),
+                          _p(self.flag), _s()))
 
     def forward(self, keep=True, out=None, base=None, vbase=None, vout=None, scale=None,
                 ydense=True, gain=1.0, skip=None, fields=None):

@@ -348,6 +348,20 @@ def test_step_loop_equals_forward(boundary):
     np.testing.assert_array_equal(g.domain(cur).cpu().numpy(), g.domain(a).cpu().numpy())
     np.testing.assert_array_equal(g.domain(prev).cpu().numpy(), g.domain(b).cpu().numpy())
     np.testing.assert_array_equal(d.cpu().numpy(), d_ref.cpu().numpy())
+    # fd_step_lagged: the same updates, each recording the level it reads
+    # (update n records the result of update n - 1; the last level by
+    # fd_sample)
+    c2, e2 = g.field(), g.field()
+    g.domain(c2).copy_(to_dev(u0))
+    d2 = torch.zeros_like(d_ref)
+    cur, prev = c2, e2
+    for n in range(nt):
+        g.step(cur, prev, S, qd[n], R if n else None, d2[n - 1] if n else None, lagged=True)
+        cur, prev = prev, cur
+    g.sample(cur, R, d2[nt - 1])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(g.domain(cur).cpu().numpy(), g.domain(a).cpu().numpy())
+    np.testing.assert_array_equal(d2.cpu().numpy(), d_ref.cpu().numpy())
     g.close()
 
 
