@@ -81,6 +81,29 @@ def test_null_arguments(lib):
     assert lib.fd_forward(None, None, None, None, None, None, 0, None, 0, None) == fd.FD_EINVAL
     assert lib.fd_pack_halo(None, None, 0, None, None) == fd.FD_EINVAL
     assert lib.fd_halo_face_elems(None, 0) < 0
+    assert lib.fd_step(None, None, None, None, None, None, None, None) == fd.FD_EINVAL
+    assert lib.fd_step_lagged(None, None, None, None, None, None, None, None) == fd.FD_EINVAL
+
+
+def test_network_entry_points_reject_bad_arguments():
+    """Shape and pointer checks of the network calls return FD_EINVAL before
+    any launch (so they run without a GPU)."""
+    from paper_2312_13094_amd import fd, nn
+    L = nn.lib()
+    v = nn.View(0, 1, 1)
+    x = ctypes.c_void_p(16)
+    # empty volume, then a missing field pointer
+    assert L.nn_conv_gelu_fields(0, 4, 4, x, v, x, v, x, v, 1, None, x, x, None, x,
+                                 None) == fd.FD_EINVAL
+    assert L.nn_conv_gelu_fields(4, 4, 4, None, v, x, v, x, v, 1, None, x, x, None, x,
+                                 None) == fd.FD_EINVAL
+    assert b"nn_conv_gelu_fields" in lib_error(L)
+    assert L.nn_conv_gelu(3, 4, 4, 4, x, x, x, None, x, None) == fd.FD_EINVAL
+    assert L.nn_rms(4, 4, 4, None, v, x, None, None) == fd.FD_EINVAL
+
+
+def lib_error(L):
+    return L.fd_last_error()
 
 
 def test_binding_rejects_short_pointer_arrays():
