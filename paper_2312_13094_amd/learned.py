@@ -4,7 +4,7 @@ A space-order-4 propagation on a 2x coarser grid with a 2x larger time step
 is corrected after every coarse step by the 3-layer BF16 network of
 ``fdnn.h`` toward the space-order-8 fine-grid solution:
 
-    u~(n+1) = coarse leapfrog step of (u(n), u(n-1))             [fd_forward]
+    u~(n+1) = coarse leapfrog step of (u(n), u(n-1))             [fd_step_lagged]
     s       = rms(u~(n+1))                                        [nn_rms]
     u(n+1)  = u~(n+1) + k s N(u~/s, u(n)/s, v^ u~/s)  outside B   [nn_* kernels]
             = u~(n+1)                                 inside B
