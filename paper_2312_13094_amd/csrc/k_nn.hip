@@ -85,6 +85,32 @@ __device__ __forceinline__ float gelu(float x)
     const float r = erf_as(a, e);
     return 0.5f * x * (1.0f + copysignf(r, x));
 }
+// gelu() of four values, written stage by stage so that the four
+// dependent chains interleave (each value's operations are those of gelu())
+__device__ __forceinline__ void gelu4(const float x[4], float y[4])
+{
+    float a[4], e[4], t[4], q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = fabsf(x[i]) * 0.70710678118654752f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a[i], 1.0f));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = __expf(-a[i] * a[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = fmaf(1.061405429f, t[i], -1.453152027f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = fmaf(q[i], t[i], 1.421413741f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = fmaf(q[i], t[i], -0.284496736f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = fmaf(q[i], t[i], 0.254829592f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float r = 1.0f - q[i] * t[i] * e[i];
+        y[i] = 0.5f * x[i] * (1.0f + copysignf(r, x[i]));
+    }
+}
+
 // GELU'(x) = Phi(x) + x phi(x), phi(x) = exp(-x^2 / 2) / sqrt(2 pi)
 __device__ __forceinline__ float gelu_grad(float x)
 {
@@ -176,30 +202,37 @@ __device__ __forceinline__ bool in_box(const nn_box &b, int z, int y, int x)
            x < b.hi[2];
 }
 
-// Epilogue of one MFMA row: bias, activation and stores for point (x, y, z)
-// of this lane (lane group g holds output channels 4g..4g+3).
+// Epilogue of one MFMA row: bias, activation and stores (lane group g holds
+// output channels 4g..4g+3 of its point).  The lane's 8 bytes of point p go
+// through buffer descriptors of output plane z at byte offset
+// off = 32 p_plane + 8 g (an offset past the plane for points outside the
+// volume, whose loads return zero and whose stores are dropped), so the
+// epilogue has no control flow.
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+constexpr uint32_t kNnOOB = 0xFFFFFFF0u;     // beyond every plane descriptor
+constexpr int kNnWord3 = 0x00020000;         // gfx9 raw buffer: 32-bit data format
+
 template <int EPI>
-__device__ __forceinline__ void epilogue(const ConvArgs &a, const floatx4 &acc, const int x,
-                                         const int y, const int z, const int g,
-                                         const float *bias4)
+__device__ __forceinline__ void epilogue_buf(const floatx4 &acc, const __amdgpu_buffer_rsrc_t ra,
+                                             const __amdgpu_buffer_rsrc_t rz, const uint32_t off,
+                                             const float *bias4)
 {
-    if (x >= a.nx || y >= a.ny || z >= a.nz) return;
-    const int64_t p = ((int64_t)z * a.ny + y) * a.nx + x;
     if (EPI == EPI_DGRAD) {
-        const uint2 zp = *reinterpret_cast<const uint2 *>(a.z16 + p * 16 + 4 * g);
-        *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
-            make_uint2(pack_bf16(acc[0] * gelu_grad(lo_bf(zp.x)), acc[1] * gelu_grad(hi_bf(zp.x))),
-                       pack_bf16(acc[2] * gelu_grad(lo_bf(zp.y)), acc[3] * gelu_grad(hi_bf(zp.y))));
+        const v2u zp = __builtin_amdgcn_raw_buffer_load_b64(rz, off, 0, 0);
+        const v2u o = {pack_bf16(acc[0] * gelu_grad(lo_bf(zp.x)), acc[1] * gelu_grad(hi_bf(zp.x))),
+                       pack_bf16(acc[2] * gelu_grad(lo_bf(zp.y)), acc[3] * gelu_grad(hi_bf(zp.y)))};
+        __builtin_amdgcn_raw_buffer_store_b64(o, ra, off, 0, 0);
     } else {
         const uint32_t z01 = pack_bf16(acc[0] + bias4[0], acc[1] + bias4[1]);
         const uint32_t z23 = pack_bf16(acc[2] + bias4[2], acc[3] + bias4[3]);
         // GELU of the stored (BF16) pre-activation, so training and its
         // backward see the same value
-        *reinterpret_cast<uint2 *>(a.a16 + p * 16 + 4 * g) =
-            make_uint2(pack_bf16(gelu(lo_bf(z01)), gelu(hi_bf(z01))),
-                       pack_bf16(gelu(lo_bf(z23)), gelu(hi_bf(z23))));
-        if (EPI == EPI_GELU_Z)
-            *reinterpret_cast<uint2 *>(a.z16 + p * 16 + 4 * g) = make_uint2(z01, z23);
+        const float xs[4] = {lo_bf(z01), hi_bf(z01), lo_bf(z23), hi_bf(z23)};
+        float ys[4];
+        gelu4(xs, ys);
+        const v2u o = {pack_bf16(ys[0], ys[1]), pack_bf16(ys[2], ys[3])};
+        __builtin_amdgcn_raw_buffer_store_b64(o, ra, off, 0, 0);
+        if (EPI == EPI_GELU_Z) __builtin_amdgcn_raw_buffer_store_b64(v2u{z01, z23}, rz, off, 0, 0);
     }
 }
 
@@ -343,6 +376,16 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
         boff[s] = (uint32_t)((pt * CIN + cs) * 2);
     }
     const char *ringb = reinterpret_cast<const char *>(ring);
+    // this lane's output bytes within a plane for its 4 rows (tile rows
+    // wave/2 + 2j, half wave%2), past the plane outside the volume
+    const int64_t plane = (int64_t)a.ny * a.nx;
+    const uint32_t pbytes = (uint32_t)(plane * 32);
+    uint32_t eoff[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int x = x0 + (wave % 2) * 16 + n, y = y0 + wave / 2 + 2 * j;
+        eoff[j] = x < a.nx && y < a.ny ? (uint32_t)(((int64_t)y * a.nx + x) * 32 + 8 * g) : kNnOOB;
+    }
     for (int z = z0; z < z1; ++z) {
         const bool more = z + 1 < z1;
         if (more) load_plane(z + 2);            // in flight under the MFMAs
@@ -364,6 +407,11 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
             for (int j = 0; j < NR; ++j)
                 bv[j] = *reinterpret_cast<const bf16x8 *>(p + j * ROWB);
         };
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.a16 + z * plane * 16), (short)0, (int)pbytes, kNnWord3);
+        const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(EPI == EPI_GELU ? a.a16 : a.z16 + z * plane * 16), (short)0,
+            EPI == EPI_GELU ? 0 : (int)pbytes, kNnWord3);
         bf16x8 bq[2][NR];
         fetch(0, bq[0]);
 #pragma unroll
@@ -375,8 +423,7 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
                                                                   0, 0);
         }
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-            epilogue<EPI>(a, acc[j], x0 + (wave % 2) * 16 + n, y0 + wave / 2 + 2 * j, z, g, bias4);
+        for (int j = 0; j < NR; ++j) epilogue_buf<EPI>(acc[j], ra, rz, eoff[j], bias4);
         if (more) store_plane(z + 2);           // slot of plane z-2, read by nobody now
         __syncthreads();
     }
@@ -420,6 +467,9 @@ static int device_slots(K k, int *slots)
 template <int CIN, int STEPS, int EPI, bool FIN = false>
 static int conv(const ConvArgs &a0, hipStream_t s)
 {
+    // the epilogue addresses a plane's outputs with 32-bit byte offsets
+    if ((int64_t)a0.ny * a0.nx * 32 > 0x7fffffff)
+        return set_error(FD_EINVAL, "nn conv: an x-y plane holds at most 2^26 points");
     static int slots = 0;
     if (const int rc = device_slots(k_conv<CIN, STEPS, EPI, FIN>, &slots)) return rc;
     const int64_t tiles = (int64_t)((a0.nx + ZX - 1) / ZX) * ((a0.ny + ZY - 1) / ZY);
