@@ -81,7 +81,9 @@ int nn_conv_gelu(int layer, int nz, int ny, int nx, const void *x_dev, const voi
  * x8) followed by nn_conv_gelu(1, ..., x8, ...), bitwise (the staging forms
  * each point's packed input with nn_pack_input's arithmetic and rounding),
  * without writing the packed input: for inference, where nothing else reads
- * it.  Arguments as in those two calls; the fields are read in place. */
+ * it.  Arguments as in those two calls; the fields are read in place.  Each
+ * view's plane (pitch_z floats, at most 2^31 bytes) must hold ny rows of
+ * pitch_y >= nx points, else FD_EINVAL. */
 int nn_conv_gelu_fields(int nz, int ny, int nx, const float *a, nn_view va, const float *b,
                         nn_view vb, const float *c, nn_view vc, int c_times_a,
                         const float *scale_dev, const void *packed_dev, const float *params_dev,

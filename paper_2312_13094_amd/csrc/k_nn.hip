@@ -291,45 +291,66 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) bias4[j] = a.bias[4 * g + j];
 
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.in);
     const float inv = FIN && a.fscale ? 1.0f / a.fscale[0] : 1.0f;
-    // fields input: in-plane element offsets of this thread's staged points
-    // (fixed over the march)
-    int64_t foa[FIN ? NIT : 1], fob[FIN ? NIT : 1], foc[FIN ? NIT : 1];
-    if constexpr (FIN) {
+    // staging through buffer descriptors of input plane zz (empty outside
+    // the volume): this thread's in-plane byte offsets are fixed over the
+    // march, past the plane for points outside the volume, whose loads
+    // return zero
+    const int64_t plane = (int64_t)a.ny * a.nx;
+    uint32_t soff[NIT], sfa[FIN ? NIT : 1], sfb[FIN ? NIT : 1], sfc[FIN ? NIT : 1];
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int c = tid + it * 256;
-            const int gx = x0 - 1 + c % ZHX, gy = y0 - 1 + c / ZHX;
-            foa[it] = a.fva.offset + gy * a.fva.pitch_y + gx;
-            fob[it] = a.fvb.offset + gy * a.fvb.pitch_y + gx;
-            foc[it] = a.fvc.offset + gy * a.fvc.pitch_y + gx;
+    for (int it = 0; it < NIT; ++it) {
+        const int c = tid + it * 256;
+        const int pt = c / CH, ch = c % CH;
+        const int gx = x0 - 1 + pt % ZHX, gy = y0 - 1 + pt / ZHX;
+        const bool in = c < NCH && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny;
+        soff[it] = in ? (uint32_t)((((int64_t)gy * a.nx + gx) * CH + ch) * 16) : kNnOOB;
+        if constexpr (FIN) {
+            sfa[it] = in ? (uint32_t)((gy * a.fva.pitch_y + gx) * 4) : kNnOOB;
+            sfb[it] = in ? (uint32_t)((gy * a.fvb.pitch_y + gx) * 4) : kNnOOB;
+            sfc[it] = in ? (uint32_t)((gy * a.fvc.pitch_y + gx) * 4) : kNnOOB;
         }
     }
+    auto plane_rsrc = [&](const void *base, const int64_t elem_off, const int bytes,
+                          const bool zin) {
+        return __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const char *)base + (zin ? elem_off : 0)), (short)0, zin ? bytes : 0,
+            kNnWord3);
+    };
     uint4 stage[NIT];
     // plane zz of the tile + ring into registers (zero outside the volume);
     // from the three fields, the point's packed input is formed here with
     // k_pack_input's arithmetic
     auto load_plane = [&](const int zz) {
+        const bool zin = zz >= 0 && zz < a.nz;
+        if constexpr (FIN) {
+            const auto ra = plane_rsrc(a.fa, (a.fva.offset + zz * a.fva.pitch_z) * 4,
+                                       (int)(a.fva.pitch_z * 4), zin);
+            const auto rb = plane_rsrc(a.fb, (a.fvb.offset + zz * a.fvb.pitch_z) * 4,
+                                       (int)(a.fvb.pitch_z * 4), zin);
+            const auto rc = plane_rsrc(a.fc, (a.fvc.offset + zz * a.fvc.pitch_z) * 4,
+                                       (int)(a.fvc.pitch_z * 4), zin);
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int c = tid + it * 256;
-            const int pt = c / CH, ch = c % CH;
-            const int gx = x0 - 1 + pt % ZHX, gy = y0 - 1 + pt / ZHX;
-            stage[it] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < NCH && zz >= 0 && zz < a.nz && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny) {
-                if constexpr (FIN) {
-                    // k_pack_input's products; the packed conversion rounds
-                    // to nearest even as f2bf does (they differ only in the
-                    // bits of a NaN)
-                    const float va_ = a.fa[foa[it] + zz * a.fva.pitch_z] * inv;
-                    const float vb_ = a.fb[fob[it] + zz * a.fvb.pitch_z] * inv;
-                    const float cv = a.fc[foc[it] + zz * a.fvc.pitch_z];
-                    const float vc_ = a.fct ? cv * va_ : cv;
-                    stage[it] = make_uint4(pack_bf16(va_, vb_), pack_bf16(vc_, 0.0f), 0u, 0u);
-                } else {
-                    stage[it] = src[(((int64_t)zz * a.ny + gy) * a.nx + gx) * CH + ch];
-                }
+            for (int it = 0; it < NIT; ++it) {
+                // k_pack_input's products; the packed conversion rounds to
+                // nearest even as f2bf does (they differ only in the bits of
+                // a NaN); zeros outside the volume stay zeros
+                const float va_ = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(ra, sfa[it], 0, 0)) * inv;
+                const float vb_ = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rb, sfb[it], 0, 0)) * inv;
+                const float cv = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rc, sfc[it], 0, 0));
+                const float vc_ = a.fct ? cv * va_ : cv;
+                stage[it] = make_uint4(pack_bf16(va_, vb_), pack_bf16(vc_, 0.0f), 0u, 0u);
+            }
+        } else {
+            const auto rs = plane_rsrc(a.in, zz * plane * CIN * 2, (int)(plane * CIN * 2), zin);
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+                const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rs, soff[it], 0, 0);
+                stage[it] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
     };
@@ -378,7 +399,6 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs a)
     const char *ringb = reinterpret_cast<const char *>(ring);
     // this lane's output bytes within a plane for its 4 rows (tile rows
     // wave/2 + 2j, half wave%2), past the plane outside the volume
-    const int64_t plane = (int64_t)a.ny * a.nx;
     const uint32_t pbytes = (uint32_t)(plane * 32);
     uint32_t eoff[NR];
 #pragma unroll
@@ -1034,6 +1054,11 @@ int nn_conv_gelu_fields(int nz, int ny, int nx, const float *a, nn_view va, cons
 {
     if (bad_shape(nz, ny, nx) || !a || !b || !c || !packed_dev || !params_dev || !a16_dev)
         return set_error(FD_EINVAL, "nn_conv_gelu_fields: bad argument");
+    // each field's plane is read with 32-bit byte offsets
+    for (const nn_view *v : {&va, &vb, &vc})
+        if (v->pitch_y < nx || v->pitch_z < (int64_t)ny * v->pitch_y || v->pitch_z * 4 > 0x7fffffff)
+            return set_error(FD_EINVAL, "nn_conv_gelu_fields: a field view's plane does not hold "
+                                        "ny rows of nx points, or exceeds 2^31 bytes");
     ConvArgs g{};
     g.nz = nz;
     g.ny = ny;
