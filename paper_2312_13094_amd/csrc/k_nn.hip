@@ -790,6 +790,25 @@ constexpr int kRmsBlocks = 1024;
 static_assert(kRmsBlocks % 256 == 0, "k_rms_final splits the partials over 256 threads");
 
 // stage 1: per-block sums of squares (double) and non-finite flags
+// The fixed tree red[t] += red[t + w], w = 128 .. 1, over a 256-thread
+// block's values: the same additions in the same order, the first two levels
+// through LDS and the last six inside wave 0 by lane shuffles (no barriers).
+// The sum is valid in thread 0.
+__device__ __forceinline__ double tree_sum256(const double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < 128) red[threadIdx.x] += red[threadIdx.x + 128];
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < 64) {
+        r = red[threadIdx.x] + red[threadIdx.x + 64];
+#pragma unroll
+        for (int w = 32; w > 0; w >>= 1) r += __shfl_down(r, w, 64);
+    }
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_rms_part(const int nz, const int ny, const int nx,
                                                   const float *u, const nn_view vu, double *part,
                                                   unsigned *flag, const int seg)
@@ -811,13 +830,8 @@ __global__ __launch_bounds__(256) void k_rms_part(const int nz, const int ny, co
         }
         s += (double)rs;
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    const double t = tree_sum256(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
     if (bad && flag) flag[0] = 1u;
 }
 
@@ -832,13 +846,8 @@ __global__ __launch_bounds__(256) void k_rms_final(const double *part, const int
     constexpr int per = kRmsBlocks / 256;
 #pragma unroll
     for (int b = 0; b < per; ++b) s += part[threadIdx.x * per + b];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) scale[0] = (float)sqrt(red[0] / (double)n) + 1e-30f;
+    const double t = tree_sum256(s, red);
+    if (threadIdx.x == 0) scale[0] = (float)sqrt(t / (double)n) + 1e-30f;
 }
 
 __global__ __launch_bounds__(256) void k_mse(const int nz, const int ny, const int nx,
