@@ -63,8 +63,9 @@ int fd_batch_set_model(fd_batch *b, const float *vel_full_dev, void *stream);
 /* One gradient of J = 1/2 sum_s |d_s - dobs_s|^2 with respect to velocity
  * (forward with checkpoints; per segment the recomputation, whose steps
  * also store the imaging factor (u+ - 2u + u-)/dt^2 + gamma (u+ - u-)/(2 dt)
- * of each update, and the adjoint steps, which apply the imaging condition
- * g -= lambda D to the adjoint field they read).
+ * of each update -- for the last segment the forward steps store it, and
+ * that segment is not recomputed -- and the adjoint steps, which apply the
+ * imaging condition g -= lambda D to the adjoint field they read).
  *   q_dev[s]     [nt][ns_s] source signatures
  *   dobs_dev[s]  [nt][nr_s] observed traces
  *   d_dev[s]     [nt][nr_s] output: modelled traces

@@ -134,36 +134,53 @@ int enqueue_schedule(fd_batch *b, float *grad_v, hipStream_t s)
     if ((rc = (x))) return rc
     for (int f : {(int)kFA, (int)kFB, (int)kLA, (int)kLB, (int)kGrad})
         FD_TRY(launch_batch_zero(T, ns, b->max_stride, f, s));
+    // The forward run, with a checkpoint at the start of every segment but
+    // the last: the last segment's steps store their imaging factors D_n
+    // (as its recomputation would, in slot0 + 2 + (n - lo)), so that segment
+    // is not recomputed.
+    BatchEpi rec;
+    rec.mode = 1;
+    rec.inv_dt2 = inv_dt2;
+    rec.inv_2dt = inv_2dt;
+    const int lo_last = (b->nck - 1) * k;
     int cur = kFA, prev = kFB;
     for (int n = 0; n < b->nt; ++n) {
-        if (n % k == 0) {
+        if (n % k == 0 && n < lo_last) {
             FD_TRY(launch_batch_copy(T, ns, b->max_stride, cur, kCkpt0 + 2 * (n / k), s));
             FD_TRY(launch_batch_copy(T, ns, b->max_stride, prev, kCkpt0 + 2 * (n / k) + 1, s));
         }
-        FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, cur, prev, prev, s));
-        FD_TRY(launch_batch_sparse(T, ns, 0, n, prev, hinv, s));
+        if (n >= lo_last) {
+            rec.fd = slot0 + 2 + (n - lo_last);
+            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, cur, prev, prev, s, rec));
+            FD_TRY(launch_batch_sparse(T, ns, 0, n, prev, hinv, s, rec.fd, inv_dt2, inv_2dt));
+        } else {
+            FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, cur, prev, prev, s));
+            FD_TRY(launch_batch_sparse(T, ns, 0, n, prev, hinv, s));
+        }
         std::swap(cur, prev);
     }
     // Per checkpoint segment [lo, hi), last segment first: recompute the
     // forward steps from the checkpoint in two rolling fields (slot0,
     // slot0 + 1), each step also storing the imaging factor D_n of its
-    // update in slot0 + 2 + (n - lo); then the adjoint steps n = hi-1 .. lo.
+    // update in slot0 + 2 + (n - lo) (the forward run stored the last
+    // segment's); then the adjoint steps n = hi-1 .. lo.
     // The imaging condition g -= lambda_n D_n for n > lo rides on the
     // adjoint step that reads lambda_n (the next one, n - 1); lambda_lo is
     // imaged by its own pass before the next segment overwrites the D slots.
     int lam = kLA, lamo = kLB;
-    BatchEpi rec, img;
-    rec.mode = 1;
+    BatchEpi img;
     img.mode = 2;
     img.fg = kGrad;
-    rec.inv_dt2 = img.inv_dt2 = inv_dt2;
-    rec.inv_2dt = img.inv_2dt = inv_2dt;
+    img.inv_dt2 = inv_dt2;
+    img.inv_2dt = inv_2dt;
     for (int j = b->nck - 1; j >= 0; --j) {
         const int lo = j * k, hi = std::min(b->nt, (j + 1) * k);
         int cu = slot0 + 1, cp = slot0;
-        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j, cu, s));
-        FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j + 1, cp, s));
-        for (int i = 0; i < hi - lo; ++i) {
+        if (j < b->nck - 1) {
+            FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j, cu, s));
+            FD_TRY(launch_batch_copy(T, ns, b->max_stride, kCkpt0 + 2 * j + 1, cp, s));
+        }
+        for (int i = 0; i < hi - lo && j < b->nck - 1; ++i) {
             rec.fd = slot0 + 2 + i;
             FD_TRY(launch_batch_step(T, ns, b->total_blocks, b->r, b->tune, cu, cp, cp, s, rec));
             FD_TRY(launch_batch_sparse(T, ns, 1, lo + i, cp, hinv, s, rec.fd, inv_dt2, inv_2dt));

@@ -31,8 +31,8 @@ int launch_batch_step(const BatchShot *shots_dev, int nshots, int total_blocks, 
 }
 
 // One block per shot: injection (atomics), device fence + barrier, sampling.
-// With fd >= 0 (mode 1) each injected amount also enters the imaging factor
-// of the step it completes: D is linear in u+ with weight
+// With fd >= 0 (modes 0 and 1) each injected amount also enters the imaging
+// factor of the step it completes: D is linear in u+ with weight
 // 1/dt^2 + gamma/(2 dt).
 __global__ __launch_bounds__(256) void k_batch_sparse(const BatchShot *__restrict__ shots,
                                                       const int mode, const int n, const int f,
@@ -83,7 +83,7 @@ int launch_batch_sparse(const BatchShot *shots_dev, int nshots, int mode, int n,
                         float hinv, hipStream_t s, int fd, float inv_dt2, float inv_2dt)
 {
     hipLaunchKernelGGL(k_batch_sparse, dim3(nshots), dim3(256), 0, s, shots_dev, mode, n, f, hinv,
-                       mode == 1 ? fd : -1, inv_dt2, inv_2dt);
+                       mode != 2 ? fd : -1, inv_dt2, inv_2dt);
     return check_launch("batched sparse");
 }
 

@@ -68,6 +68,38 @@ def test_batch_gradient_matches_per_shot_oracle(nbl):
     b.close()
 
 
+def test_batch_gradient_independent_of_checkpoint_interval():
+    """The gradient and traces are bitwise the same for any checkpoint
+    interval: one segment (the forward run stores every imaging factor and
+    nothing is recomputed), 13 steps (a partial last segment) and 1 step."""
+    import torch
+    from paper_2312_13094_amd import fd
+    c = _small_problem(6)
+    vstart = c.start_velocity()
+    rng = np.random.default_rng(4)
+    dobs = [to_dev((rng.standard_normal((c.nt, len(c.rec[s]))) * 1e-3).astype(np.float32))
+            for s in range(len(c.shapes))]
+    q = [to_dev(c.q) for _ in c.shapes]
+    out = []
+    for k in (c.nt, 13, 1):
+        b = fd.Batch(c.spacing, c.so, c.dt, c.vmax, c.nbl, c.shapes, c.origins, c.full_shape,
+                     c.nt, k)
+        for s in range(len(c.shapes)):
+            b.set_geometry(s, c.src[s], c.rec[s])
+        b.set_model(to_dev(vstart))
+        d = [torch.zeros((c.nt, len(c.rec[s])), device="cuda") for s in range(len(c.shapes))]
+        gv = torch.zeros(c.full_shape, device="cuda")
+        b.gradient(q, dobs, d, gv)
+        torch.cuda.synchronize()
+        out.append((gv.cpu().numpy(), [t.cpu().numpy() for t in d]))
+        b.close()
+    assert np.abs(out[0][0]).max() > 0
+    for g, d in out[1:]:
+        np.testing.assert_array_equal(g, out[0][0])
+        for a_, b_ in zip(d, out[0][1]):
+            np.testing.assert_array_equal(a_, b_)
+
+
 def test_batch_tiles_agree():
     import torch
     from paper_2312_13094_amd import fd
