@@ -170,12 +170,20 @@ def sponge_gamma_box(g: Grid, lo, hi) -> np.ndarray:
     """The damping rate of grid g on the box of DOMAIN indices [lo, hi) (one
     (z, y, x) triple each; 3-D grids), point by point as sponge_gamma: for a
     window of a larger grid whose own boundary is not the damping layer's."""
+    return sponge_gamma_at(g, *(range(int(l), int(h)) for l, h in zip(lo, hi)))
+
+
+def sponge_gamma_at(g: Grid, zs, ys, xs) -> np.ndarray:
+    """The damping rate of grid g at every (z, y, x) of the three lists of
+    DOMAIN indices (any order, repeats allowed), point by point as
+    sponge_gamma: for a window that wraps round a periodic grid."""
     L = _L()
-    out = np.zeros(tuple(int(h) - int(l) for l, h in zip(lo, hi)))
-    for z in range(lo[0], hi[0]):
-        for y in range(lo[1], hi[1]):
-            for x in range(lo[2], hi[2]):
-                out[z - lo[0], y - lo[1], x - lo[2]] = L.or_sponge_gamma(ctypes.byref(g._c), z, y, x)
+    zs, ys, xs = ([int(v) for v in a] for a in (zs, ys, xs))
+    out = np.zeros((len(zs), len(ys), len(xs)))
+    for i, z in enumerate(zs):
+        for j, y in enumerate(ys):
+            for k, x in enumerate(xs):
+                out[i, j, k] = L.or_sponge_gamma(ctypes.byref(g._c), z, y, x)
     return out
 
 

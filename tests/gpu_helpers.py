@@ -16,6 +16,16 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def wrapped_boxes(g, f, names, pt, w):
+    """The DOMAIN values of fields f (named by names) on the box of
+    half-width w around pt, at periodically wrapped indices, as float64."""
+    import torch
+    idx = [torch.from_numpy(np.arange(int(k) - w, int(k) + w + 1) % n).cuda()
+           for k, n in zip(pt, g.shape)]
+    return {name: g.domain(t).index_select(0, idx[0]).index_select(1, idx[1])
+            .index_select(2, idx[2]).double().cpu().numpy() for name, t in zip(names, f)}
+
+
 def gpu_grid(shape, spacing, so, dt, vmax, nbl=0, boundary=FD.FD_BC_ZERO, tile=None):
     g = FD.Grid(shape, spacing, so, dt, vmax, nbl=nbl, boundary=boundary)
     if tile is not None:

@@ -8,7 +8,8 @@ import pytest
 import oracle as O
 import oracle.elastic as E
 from paper_2312_13094_amd import synth
-from gpu_helpers import rel_l2, to_dev
+from gpu_helpers import rel_l2, to_dev, wrapped_boxes as _wrapped_boxes
+import window_oracle as WO
 
 pytestmark = pytest.mark.gpu
 
@@ -138,9 +139,12 @@ def test_elastic_source_only_first_update():
 
 def test_elastic_full_size_sampled_points():
     """The benchmark's launch (512^3, so 8, layered medium, 40-point sponge,
-    loopback halos) for one update from a random state, checked at sampled
-    interior points: each sample's oracle runs the two half steps on the
-    (4r+1)^3 box around it, which holds every value the point depends on."""
+    loopback halos) for one update from a random state, checked at 24
+    sampled points: 8 deep inside, 8 inside the damping layer and 8 within 3r
+    of a face.  Each sample's oracle runs the two half steps on the window of
+    half-width 2r (plus an r-wide halo) around it, taken with the periodic
+    halo's wrapped indices and carrying the whole grid's medium coefficients
+    and damping rate."""
     import torch
     FD = _fd()
     c = synth.cfg_elastic(n=512, nt=1)
@@ -158,36 +162,21 @@ def test_elastic_full_size_sampled_points():
     for k, name in enumerate(FD.ELASTIC_FIELDS):
         scale = 1e-3 if name[0] == "v" else 1e3
         g.domain(f[k]).copy_(torch.randn(c.shape, generator=gen, device="cuda") * scale)
-    rng = np.random.default_rng(5)
-    lo, hi = c.nbl + 2 * r + 1, n - c.nbl - 2 * r - 1
-    pts = rng.integers(lo, hi, size=(12, 3))
-    pts[0] = (lo, lo, lo)
-    pts[1] = (hi - 1, hi - 1, hi - 1)
-    w = 2 * r
-    boxes = [{name: g.domain(f[k])[z - w - r:z + w + r + 1, y - w - r:y + w + r + 1,
-                                   x - w - r:x + w + r + 1].double().cpu().numpy()
-              for k, name in enumerate(FD.ELASTIC_FIELDS)} for z, y, x in pts]
+    pts = np.concatenate(WO.sample_points(n, c.nbl, r, np.random.default_rng(5), 8))
+    boxes = [_wrapped_boxes(g, f, FD.ELASTIC_FIELDS, pt, 3 * r) for pt in pts]
     g.forward(f, None, None, None, None, 1)
     torch.cuda.synchronize()
-    got = [{name: float(g.domain(f[k])[z, y, x]) for k, name in enumerate(FD.ELASTIC_FIELDS)}
-           for z, y, x in pts]
-    prof = (c.vp_profile.astype(np.float64), c.vs_profile.astype(np.float64),
-            c.rho_profile.astype(np.float64))
+    got = [{name: float(g.domain(f[k])[tuple(pt)]) for k, name in enumerate(FD.ELASTIC_FIELDS)}
+           for pt in pts]
     g.close()
-    for (z, y, x), box, gv in zip(pts, boxes, got):
-        sub = (2 * w + 1,) * 3
-        og = O.Grid(sub, c.spacing, so=c.so, dt=c.dt)
-        st = {name: box[name].copy() for name in E.FIELDS}
-        zs = np.arange(z - w, z + w + 1)
-        med = [np.broadcast_to(pr[zs][:, None, None], sub) for pr in prof]
-        par = E.staggered_params(*E.medium(*med))
-        a = np.zeros(sub)
-        E.velocity_update(og, st, par, a)
-        E.stress_update(og, st, par, a)
+    big = O.Grid(c.shape, c.spacing, so=c.so, dt=c.dt, nbl=c.nbl, vmax=c.vmax, bc=1)
+    cols = [p.astype(np.float64)[:, None, None] for p in (c.vp_profile, c.vs_profile, c.rho_profile)]
+    coef = E.staggered_params(*E.medium(*cols))
+    for pt, box, gv in zip(pts, boxes, got):
+        want = WO.step_at(big, "elastic", coef, box, pt)
         for name in E.FIELDS:
-            want = og.interior(st[name])[w, w, w]
-            mag = np.abs(og.interior(box[name])).max()
-            assert abs(gv[name] - want) <= 1e-5 * mag, (name, (z, y, x), gv[name], want)
+            mag = np.abs(box[name]).max()
+            assert abs(gv[name] - want[name]) <= 1e-5 * mag, (name, tuple(pt), gv[name], want[name])
 
 
 def test_elastic_errors():
