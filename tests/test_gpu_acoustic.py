@@ -365,6 +365,64 @@ def test_step_loop_equals_forward(boundary):
     g.close()
 
 
+XFACE_CASES = [
+    # shape, so, source x positions (cells), tile (by, ry, nzb, flags)
+    ((24, 21, 70), 8, [33.2, 1.5], (8, 2, 64, 28)),    # one 128-wide tile holds both x faces
+    ((24, 21, 70), 8, [67.6], (4, 2, 13, 13)),         # within R of the x+ face; two 64-wide tiles
+    ((24, 21, 70), 8, [0.0], (4, 4, 7, 8)),            # on the x- face itself
+    ((20, 19, 40), 16, [20.3, 38.5], (4, 2, 9, 12)),   # radius 8
+    ((24, 21, 70), 8, [68.9], (4, 2, 13, 5)),          # no halo-ring tile
+    ((24, 21, 70), 8, [68.9], (0, 0, 0, 0)),           # one thread per point
+]
+
+
+@pytest.mark.parametrize("shape,so,sx,tile", XFACE_CASES)
+def test_loopback_sources_next_to_x_faces(shape, so, sx, tile):
+    """Loopback grid with sources injecting within R of the x faces (whose
+    values the next exchange must carry into the opposite halo) and a
+    receiver line across x: fd_forward equals a loop of fd_step bit for bit,
+    fields and traces, and the oracle within 1e-5, over halo-ring tiles of
+    one and two 64-wide columns per lane, other tiles and the
+    one-thread-per-point kernel."""
+    import torch
+    FD = _fd()
+    rng = np.random.default_rng(21)
+    h, vmax, nt = 10.0, 3000.0, 9
+    v = synth.minmax(synth.smooth_noise(shape, 3.0, rng), 1500.0, vmax).astype(np.float32)
+    dt = synth.stable_dt(so, 3, h, vmax)
+    src = np.array([[(shape[0] / 2 - 0.3) * h, (shape[1] / 2 + 0.2) * h, x * h] for x in sx])
+    rec = np.array([[5 * h, 10.5 * h, (1 + 2 * i) * h] for i in range((shape[2] - 2) // 2)])
+    q = (rng.standard_normal((nt, len(sx))) * 1e3).astype(np.float32)
+    u0 = synth.smooth_state(shape, 6, 3.0)
+    g = FD.Grid(shape, (h,) * 3, so, dt, vmax, nbl=5, boundary=1)
+    g.set_tile(*tile)
+    g.set_model(to_dev(v))
+    S, R = g.sparse(src), g.sparse(rec)
+    qd = to_dev(q)
+    a, b = g.field(), g.field()
+    g.domain(a).copy_(to_dev(u0))
+    d_ref = torch.zeros((nt, R.n), device="cuda")
+    g.forward([a, b], S, qd, R, d_ref, nt)
+    c, e = g.field(), g.field()
+    g.domain(c).copy_(to_dev(u0))
+    d = torch.zeros_like(d_ref)
+    cur, prev = c, e
+    for n in range(nt):
+        g.step(cur, prev, S, qd[n], R, d[n])
+        cur, prev = prev, cur
+    torch.cuda.synchronize()
+    got = g.domain(a).cpu().numpy()
+    np.testing.assert_array_equal(g.domain(cur).cpu().numpy(), got)
+    np.testing.assert_array_equal(g.domain(prev).cpu().numpy(), g.domain(b).cpu().numpy())
+    np.testing.assert_array_equal(d.cpu().numpy(), d_ref.cpu().numpy())
+    dg = d_ref.cpu().numpy()
+    g.close()
+    ou, _, od = run_oracle_forward(shape, (h,) * 3, so, dt, vmax, v, nt, nbl=5, boundary=1,
+                                   src=src, q=q, rec=rec, u0=u0)
+    assert rel_l2(got, ou) <= 1e-5
+    assert rel_l2(dg, od) <= 1e-5
+
+
 def test_multidomain_emulation_bitwise():
     import torch
     FD = _fd()
