@@ -69,6 +69,8 @@ __global__ __launch_bounds__(256) void k_faces(float *field, const FaceJob job,
 struct LoopJob {
     FaceJob own;          // owned slabs and their buffers
     int hstart[6][3];     // origin of the halo slab that face f's slab fills
+    int nx;               // DOMAIN x extent
+    int xline;            // 1: the x faces move whole 128-byte lines (below)
 };
 
 __global__ __launch_bounds__(256) void k_faces_loopback(float *field, const LoopJob job,
@@ -82,6 +84,33 @@ __global__ __launch_bounds__(256) void k_faces_loopback(float *field, const Loop
     const int sz = job.own.start[f][0], sy = job.own.start[f][1], sx = job.own.start[f][2];
     const int hz = job.hstart[f][0], hy = job.hstart[f][1], hx = job.hstart[f][2];
     float *buf = job.own.buf[f];
+    if (f >= 4 && job.xline) {
+        // x faces with nx a multiple of 32 (rows start on a line boundary):
+        // the line holding the halo beyond the opposite face is written
+        // whole, as a copy of its periodic image (the first or last 32
+        // DOMAIN columns), so the store covers a full line; the columns of
+        // that line beyond the halo are row padding nothing reads.  The
+        // owned slab (R columns at the start or the end of the image) also
+        // goes to the face buffer.  8 float4 per row.
+        const int R = c2;
+        const int sx0 = f == 4 ? 0 : job.nx - 32, hx0 = f == 4 ? job.nx : -32;
+        const int so = f == 4 ? 0 : 32 - R;
+        const int rows = n / R;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * 8;
+             e += gridDim.x * blockDim.x) {
+            const int k = e & 7;
+            const int t = e >> 3;
+            const int i1 = t % c1;
+            const int i0 = t / c1;
+            const int64_t row = offset + (int64_t)(sz + i0) * PZ + (int64_t)(sy + i1) * PY;
+            const float4 v = *reinterpret_cast<const float4 *>(field + row + sx0 + 4 * k);
+            *reinterpret_cast<float4 *>(field + row + (int64_t)(hz - sz) * PZ +
+                                        (int64_t)(hy - sy) * PY + hx0 + 4 * k) = v;
+            if (4 * k >= so && 4 * k < so + R)
+                reinterpret_cast<float4 *>(buf)[t * (R >> 2) + ((4 * k - so) >> 2)] = v;
+        }
+        return;
+    }
     if (job.own.vec[f]) {
         const int q2 = c2 >> 2;
         const int nq = n >> 2;
@@ -173,6 +202,14 @@ int launch_loopback(const fd_grid *g, float *field, float *const *buf, hipStream
         for (int a = 0; a < 3; ++a) job.hstart[f][a] = halo.start[f ^ 1][a];
         job.own.vec[f] = job.own.vec[f] && halo.vec[f ^ 1];
     }
+    job.nx = g->n[2];
+    // whole-line x faces: rows start on a line boundary (DOMAIN x = 0 at a
+    // multiple of 32 floats), nx a multiple of 32 and the slab whole float4s
+    job.xline = (g->ndim == 3 && g->n[2] % 32 == 0 && g->r % 4 == 0 && kXOff % 32 == 0 &&
+                 g->L.pitch_y % 32 == 0 && job.own.elems[4] > 0)
+                    ? 1
+                    : 0;
+    if (job.xline) maxe = std::max(maxe, job.own.elems[4] / g->r * 8);
     if (maxe == 0) return FD_OK;
     const int nbx = std::min((maxe + 255) / 256, 2048);
     hipLaunchKernelGGL(k_faces_loopback, dim3(nbx, 6), dim3(256), 0, s, field, job, g->L.offset,

@@ -64,7 +64,8 @@ def test_pack_unpack_bit_exact(shape, so):
     del r
 
 
-@pytest.mark.parametrize("shape,so", [((12, 10, 40), 8), ((9, 11, 13), 6), ((14, 37), 4)])
+@pytest.mark.parametrize("shape,so", [((12, 10, 40), 8), ((9, 11, 13), 6), ((14, 37), 4),
+                                      ((12, 10, 64), 8), ((10, 9, 32), 16), ((8, 7, 96), 8)])
 def test_loopback_exchange_equals_pack_then_unpack(shape, so):
     """The fused loopback exchange inside a loopback update leaves the
     current field exactly as the oracle's face pack followed by unpack of
@@ -373,6 +374,8 @@ XFACE_CASES = [
     ((20, 19, 40), 16, [20.3, 38.5], (4, 2, 9, 12)),   # radius 8
     ((24, 21, 70), 8, [68.9], (4, 2, 13, 5)),          # no halo-ring tile
     ((24, 21, 70), 8, [68.9], (0, 0, 0, 0)),           # one thread per point
+    ((24, 21, 64), 8, [62.5, 30.1], (8, 2, 64, 28)),   # nx a multiple of 32: whole-line x faces
+    ((20, 19, 64), 16, [0.5], (4, 2, 9, 12)),
 ]
 
 
