@@ -73,7 +73,11 @@ enum { FD_ACOUSTIC = 0, FD_TTI = 1, FD_ELASTIC = 2, FD_VISCO = 3 };
  *   FD_BC_ZERO      never written: stays as the caller allocated it (zero);
  *   FD_BC_LOOPBACK  the rank is its own neighbour on a periodic topology:
  *                   all faces are packed into device buffers and unpacked
- *                   into the opposite face's halo every step;
+ *                   into the opposite face's halo every step (3-D, nx a
+ *                   multiple of 32: each x halo is written as part of a
+ *                   whole 128-byte line, so the row padding beyond it, x in
+ *                   [-32, -halo) and [n + halo, n + 32), also receives
+ *                   periodic images; nothing reads the padding);
  *   FD_BC_EXTERNAL  left as the caller filled it (one step per call, with
  *                   fd_pack_halo / fd_unpack_halo around it). */
 enum { FD_BC_ZERO = 0, FD_BC_LOOPBACK = 1, FD_BC_EXTERNAL = 2 };
