@@ -127,8 +127,9 @@ __global__ __launch_bounds__(64 * BY) void k_batch_zmarch(const BatchShot *__res
     float *base = S.base;
     const int64_t st = S.stride;
     const StepImaging img{base + e.fd * st, base + e.fg * st, e.inv_dt2, e.inv_2dt};
-    zmarch_buf_body<R, BY, RY, NTS, CX, EPI>(base + iu * st, base + ium * st, base + iup * st,
-                                             base + kVdt2 * st, S.p, tx, ty, zc, nzb, lds, img);
+    zmarch_buf_body<R, BY, RY, NTS, CX, EPI, true>(base + iu * st, base + ium * st,
+                                                   base + iup * st, base + kVdt2 * st, S.p, tx,
+                                                   ty, zc, nzb, lds, img);
 }
 
 template <int R, int BY, int RY, bool NTS, int CX>

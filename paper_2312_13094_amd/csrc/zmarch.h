@@ -252,7 +252,11 @@ struct StepImaging {
     float inv_dt2, inv_2dt;
 };
 
-template <int R, int BY, int RY, bool NTS, int CX = 1, int EPI = 0>
+// LEND (whole zero-halo grids only, never a sub-box): the lanes past the last
+// DOMAIN column of a row, up to the end of its 128-byte line, store 0 into
+// every written field (zero halo, then row padding), so that the row's last
+// line is stored whole rather than in part.
+template <int R, int BY, int RY, bool NTS, int CX = 1, int EPI = 0, bool LEND = false>
 __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, const float *um,
                                                 float *up, const float *__restrict__ vdt2,
                                                 const StepParams &p, const int tx, const int ty,
@@ -284,6 +288,7 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
 
     int xs[CX];
     uint32_t ol[CX][RY], ow[CX][RY];          // load / store offsets (OOB if masked)
+    bool zr[CX][RY];                          // LEND: a line-end lane, stores 0
 #pragma unroll
     for (int c = 0; c < CX; ++c) {
         xs[c] = x0 + lane + 64 * c;
@@ -292,7 +297,10 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
             const bool rl = xs[c] >= p.xlo - R && xs[c] < p.nx + R && (yb + j) < p.ny + R;
             const bool ro = xs[c] >= p.xlo && xs[c] < p.nx && (yb + j) < p.ny;
             ol[c][j] = rl ? boff(yb + j, xs[c]) : kBufOOB;
-            ow[c][j] = ro ? boff(yb + j, xs[c]) : kBufOOB;
+            const bool le = LEND && !ro && xs[c] >= p.nx && xs[c] < ((p.nx + 31) & ~31) &&
+                            (yb + j) < p.ny;
+            zr[c][j] = le;
+            ow[c][j] = ro || le ? boff(yb + j, xs[c]) : kBufOOB;
         }
     }
     uint32_t hyo[HY], hxo[HX];
@@ -447,15 +455,17 @@ __device__ __forceinline__ void zmarch_buf_body(const float *__restrict__ u, con
                         const float gam = (az + ax[c]) + ay;
                         const float a = p.half_dt * gam;
                         const float un = leapfrog_update(uc, cm[c][j], cv[c][j], lap, a);
-                        bstore<NTA>(un, rp, ow[c][j]);
+                        bstore<NTA>(LEND && zr[c][j] ? 0.0f : un, rp, ow[c][j]);
                         if constexpr (EPI == 1) {
                             const float um1 = cm[c][j];
                             const float dv = ((un - uc) - (uc - um1)) * img.inv_dt2 +
                                              gam * (un - um1) * img.inv_2dt;
-                            bstore<NTA>(dv, Bd.at(z), ow[c][j]);
+                            bstore<NTA>(LEND && zr[c][j] ? 0.0f : dv, Bd.at(z), ow[c][j]);
                         }
-                        if constexpr (EPI == 2)
-                            bstore<NTA>(cg[c][j] - uc * cd[c][j], Bg.at(z), ow[c][j]);
+                        if constexpr (EPI == 2) {
+                            const float gv = cg[c][j] - uc * cd[c][j];
+                            bstore<NTA>(LEND && zr[c][j] ? 0.0f : gv, Bg.at(z), ow[c][j]);
+                        }
                     }
             }
         }
